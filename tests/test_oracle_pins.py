@@ -1,0 +1,392 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics:
+closed forms, hand-worked Table II examples, independent library routes,
+invariants of the set operations, and brute force on tiny inputs.
+
+A plausible mistake anywhere in the oracle (a swapped Morton bit, a fused or
+double-precision quantizer, a dropped duplicate, a wrong tie-break, a missed
+far side in the kd-tree, a gradient sign) fails at least one test here.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gen import Grid
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+M, L = oracle.MORTON, oracle.LINEAR
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def int_grid(depth, mode):
+    """Identity grid for integer-valued float coordinates: voxel = coordinate."""
+    return Grid((0.0, 0.0, 0.0), 1.0, depth, mode)
+
+
+# ------------------------------------------------------------- quantization
+class TestQuantize:
+    g = Grid((0.0, 0.0, 0.0), 1024.0, 10, M)
+
+    def test_exact_dyadic(self):
+        i = np.arange(1024, dtype=np.float64)
+        p = np.stack([i / 1024, i[::-1] / 1024, (i * 7 % 1024) / 1024], 1).astype(np.float32)
+        v = oracle.quantize(p, self.g)
+        assert (v[:, 0] == i).all() and (v[:, 1] == i[::-1]).all()
+        assert (v[:, 2] == i * 7 % 1024).all()
+
+    def test_just_below_one_and_clamps(self):
+        p = np.array([[1 - 2 ** -24, 0.0, 0.5], [-1e-7, 1.0, 5.0], [-3.0, 1e30, -1e30]], np.float32)
+        v = oracle.quantize(p, self.g)
+        assert v.tolist() == [[1023, 0, 512], [0, 1023, 1023], [0, 1023, 0]]
+
+    def test_subtract_is_rounded_before_multiply(self):
+        # fl32(1 - 2^-25) ties to even = 1.0, so the voxel is 512; the exact
+        # value (1 - 2^-25) * 512 would floor to 511.
+        g = Grid((2.0 ** -25, 0.0, 0.0), 512.0, 10, M)
+        v = oracle.quantize(np.array([[1.0, 0.0, 0.0]], np.float32), g)
+        assert v[0, 0] == 512
+
+    def test_matches_ieee_float32_arithmetic(self):
+        rng = np.random.default_rng(5)
+        p = rng.uniform(-10, 110, (20000, 3)).astype(np.float32)
+        o = np.float32([-3.3, 0.7, 1.1])
+        s = np.float32(17.123)
+        g = Grid(tuple(float(x) for x in o), float(s), 11, M)
+        t = (p - o).astype(np.float32)
+        u = (t * s).astype(np.float32)
+        want = np.clip(np.floor(u), 0, 2 ** 11 - 1).astype(np.uint32)
+        assert (oracle.quantize(p, g) == want).all()
+
+    @pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+    def test_nonfinite_is_error(self, bad):
+        p = np.array([[0.5, 0.5, 0.5], [0.1, bad, 0.2]], np.float32)
+        with pytest.raises(oracle.NonFinite):
+            oracle.quantize(p, self.g)
+        with pytest.raises(oracle.NonFinite):
+            oracle.build(p, self.g)
+
+
+# ------------------------------------------------------------------- keys
+def _spread3(v):
+    """Test-local magic-number bit spread (a different algorithm from the
+    oracle's per-bit loop): bit b -> bit 3b, for values below 2^21."""
+    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
+    v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+    v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+    v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+    v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+    v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
+    return v
+
+
+class TestKeys:
+    def test_morton_hand_values(self):
+        vox = [[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1], [2, 0, 0], [3, 3, 3], [0, 2, 1]]
+        assert oracle.encode(vox, 10, M).tolist() == [4, 2, 1, 7, 32, 63, 16 + 1]
+
+    @pytest.mark.parametrize("d", [1, 5, 10, 11, 16, 21])
+    def test_all_ones(self, d):
+        m = 2 ** d - 1
+        assert int(oracle.encode([[m, m, m]], d, M)[0]) == 2 ** (3 * d) - 1
+        assert int(oracle.encode([[m, m, m]], d, L)[0]) == 2 ** (3 * d) - 1
+
+    @pytest.mark.parametrize("d", [3, 10, 12, 16, 21])
+    def test_matches_magic_spread_and_roundtrips(self, d):
+        rng = np.random.default_rng(d)
+        v = rng.integers(0, 2 ** d, (5000, 3)).astype(np.uint32)
+        want = (_spread3(v[:, 0]) << np.uint64(2)) | (_spread3(v[:, 1]) << np.uint64(1)) | _spread3(v[:, 2])
+        k = oracle.encode(v, d, M)
+        assert (k == want).all()
+        assert (oracle.decode(k, d, M) == v).all()
+        kl = oracle.encode(v, d, L)
+        assert (oracle.decode(kl, d, L) == v).all()
+
+    def test_morton_prefix_is_octree_cell(self):
+        d = 12
+        rng = np.random.default_rng(1)
+        v = rng.integers(0, 2 ** d, (3000, 3)).astype(np.uint32)
+        k = oracle.encode(v, d, M)
+        for lvl in range(d + 1):
+            parent = oracle.encode(v >> lvl, d, M)
+            assert (k >> np.uint64(3 * lvl) == parent).all()
+
+    def test_linear_order_is_lexicographic(self):
+        d = 7
+        rng = np.random.default_rng(2)
+        v = rng.integers(0, 2 ** d, (4000, 3)).astype(np.uint32)
+        order_lex = np.lexsort((v[:, 2], v[:, 1], v[:, 0]))
+        k = oracle.encode(v, d, L)
+        assert (np.sort(k) == k[order_lex]).all()
+
+    def test_key2(self):
+        assert oracle.encode2([1, 0, 3], [0, 1, 3], 4, M).tolist() == [2, 1, 15]
+        assert oracle.encode2([1, 0, 3], [0, 1, 3], 4, L).tolist() == [16, 1, 51]
+
+
+# ------------------------------------------------------------------ build
+def _per_point_keys(xyz, grid):
+    return oracle.encode(oracle.quantize(xyz, grid), grid.depth, grid.key_mode)
+
+
+class TestBuild:
+    @pytest.mark.parametrize("mode", [M, L])
+    def test_equals_sort_unique(self, mode):
+        d = gen.c1_spheres(n=20000, nq=1)
+        g = d["grid"].with_mode(mode)
+        keys, counts = oracle.build(d["a"], g)
+        uk, uc = np.unique(_per_point_keys(d["a"], g), return_counts=True)
+        assert (keys == uk).all() and (counts == uc).all()
+        assert counts.sum() == len(d["a"])
+
+    def test_heavy_duplicates(self):
+        rng = np.random.default_rng(3)
+        xyz = rng.integers(0, 4, (5000, 3)).astype(np.float32)
+        keys, counts = oracle.build(xyz, int_grid(3, M))
+        assert len(keys) <= 64 and counts.sum() == 5000
+        uk, uc = np.unique(_per_point_keys(xyz, int_grid(3, M)), return_counts=True)
+        assert (keys == uk).all() and (counts == uc).all()
+
+    def test_empty(self):
+        keys, counts = oracle.build(np.zeros((0, 3), np.float32), int_grid(4, M))
+        assert len(keys) == 0 and len(counts) == 0
+
+    @pytest.mark.parametrize("name", ["soldier", "gt_madame"])
+    def test_table2_arrays(self, name):
+        pts = np.array(_gold("table2_points.json")[name], np.float32)
+        want = _gold("table2_derived.json")[name + "_arrays"]
+        for mode in (M, L):
+            keys, counts = oracle.build(pts, int_grid(8, mode))
+            assert len(keys) == 6 and (counts == 1).all()
+            arr = oracle.arrays(keys, 8, mode)
+            for k, v in want.items():
+                assert arr[k].tolist() == v, (name, mode, k)
+
+    def test_arrays_structure_random(self):
+        rng = np.random.default_rng(4)
+        d = 6
+        xyz = rng.integers(0, 2 ** d, (3000, 3)).astype(np.float32)
+        keys, _ = oracle.build(xyz, int_grid(d, L))
+        arr = oracle.arrays(keys, d, L)
+        vox = oracle.decode(keys, d, L)
+        # CSR expansion of the three levels reproduces the voxel set in order
+        xp, yp = arr["x_pointer"], arr["y_pointer"]
+        x_rep = np.repeat(arr["x_index"], np.diff(xp))
+        assert len(x_rep) == len(arr["y_index"])
+        xs = np.repeat(x_rep, np.diff(yp))
+        ys = np.repeat(arr["y_index"], np.diff(yp))
+        assert (np.stack([xs, ys, arr["z_index"]], 1) == vox).all()
+        assert xp[-1] == len(arr["y_index"]) and yp[-1] == len(keys)
+        assert len(np.unique(arr["x_index"])) == len(arr["x_index"])
+
+
+# ------------------------------------------------------------------ merge
+class TestMerge:
+    def _two(self, seed, n=3000, d=6):
+        rng = np.random.default_rng(seed)
+        a = rng.integers(0, 2 ** d, (n, 3)).astype(np.float32)
+        b = rng.integers(0, 2 ** d, (n, 3)).astype(np.float32)
+        return a, b
+
+    @pytest.mark.parametrize("mode", [M, L])
+    def test_union_invariants(self, mode):
+        a, b = self._two(7)
+        g = int_grid(6, mode)
+        ka, _ = oracle.build(a, g)
+        kb, _ = oracle.build(b, g)
+        u, src = oracle.merge(ka, kb, 6, mode)
+        assert (u == np.union1d(ka, kb)).all()
+        u2, src2 = oracle.merge(kb, ka, 6, mode)
+        assert (u2 == u).all()
+        assert ((src2 == 3) == (src == 3)).all() and ((src2 == 1) == (src == 2)).all()
+        inter = int((src == 3).sum())
+        assert len(u) == len(ka) + len(kb) - inter
+        assert inter == len(np.intersect1d(ka, kb))
+        assert np.isin(ka, u).all() and np.isin(kb, u).all()
+        uu, s = oracle.merge(ka, ka, 6, mode)
+        assert (uu == ka).all() and (s == 3).all()
+        ue, s = oracle.merge(ka, np.zeros(0, np.uint64), 6, mode)
+        assert (ue == ka).all() and (s == 1).all()
+
+    def test_table2_merge(self):
+        pts = _gold("table2_points.json")
+        g = int_grid(8, M)
+        ka, _ = oracle.build(np.array(pts["soldier"], np.float32), g)
+        kb, _ = oracle.build(np.array(pts["gt_madame"], np.float32), g)
+        u, src = oracle.merge(ka, kb, 8, M)
+        assert len(u) == _gold("table2_derived.json")["merge_size"]
+        assert (src[np.isin(u, ka)] == 1).all() and (src[np.isin(u, kb)] == 2).all()
+
+
+# ------------------------------------------------------------- projection
+class TestProject:
+    @pytest.mark.parametrize("mode", [M, L])
+    @pytest.mark.parametrize("axis", [0, 1, 2])
+    def test_invariants(self, mode, axis):
+        rng = np.random.default_rng(11 + axis)
+        d = 5
+        a = rng.integers(0, 2 ** d, (2000, 3)).astype(np.float32)
+        b = rng.integers(0, 2 ** d, (2000, 3)).astype(np.float32)
+        g = int_grid(d, mode)
+        ka, _ = oracle.build(a, g)
+        kb, _ = oracle.build(b, g)
+        pa, ca = oracle.project(ka, d, mode, axis)
+        pb, _ = oracle.project(kb, d, mode, axis)
+        u, _ = oracle.merge(ka, kb, d, mode)
+        pu, _ = oracle.project(u, d, mode, axis)
+        assert (pu == np.union1d(pa, pb)).all()  # P(A u B) = P(A) u P(B)
+        assert ca.sum() == len(ka) and len(pa) <= len(ka)
+        # independent route: drop the coordinate, encode, unique with counts
+        vox = oracle.decode(ka, d, mode)
+        keep = [i for i in range(3) if i != axis]
+        k2 = oracle.encode2(vox[:, keep[0]], vox[:, keep[1]], d, mode)
+        uk, uc = np.unique(k2, return_counts=True)
+        assert (pa == uk).all() and (ca == uc).all()
+
+    def test_linear_drop_z_is_xy_arrays(self):
+        rng = np.random.default_rng(12)
+        d = 6
+        a = rng.integers(0, 2 ** d, (4000, 3)).astype(np.float32)
+        keys, _ = oracle.build(a, int_grid(d, L))
+        arr = oracle.arrays(keys, d, L)
+        p, c = oracle.project(keys, d, L, 2)
+        xs = np.repeat(arr["x_index"], np.diff(arr["x_pointer"]))
+        assert (p == oracle.encode2(xs, arr["y_index"], d, L)).all()
+        assert (c == np.diff(arr["y_pointer"])).all()
+
+    def test_table2_projection(self):
+        pts = np.array(_gold("table2_points.json")["soldier"], np.float32)
+        want = _gold("table2_derived.json")
+        for mode in (M, L):
+            keys, _ = oracle.build(pts, int_grid(8, mode))
+            for axis, name in ((2, "soldier_project_drop_z"), (1, "soldier_project_drop_y")):
+                p, c = oracle.project(keys, 8, mode, axis)
+                pix = np.array(want[name]["pixels"], np.uint32)
+                wk = oracle.encode2(pix[:, 0], pix[:, 1], 8, mode)
+                order = np.argsort(wk)
+                assert (p == wk[order]).all()
+                assert (c == np.array(want[name]["counts"])[order]).all()
+            p, c = oracle.project(keys, 8, mode, 0)
+            assert len(p) == want["soldier_project_drop_x_size"] and (c == 1).all()
+
+
+# --------------------------------------------------------------------- kNN
+class TestKnn:
+    def test_table2_tie(self):
+        pts = np.array(_gold("table2_points.json")["soldier"], np.float32)
+        w = _gold("table2_derived.json")["soldier_knn"]
+        for mode in (M, L):
+            g = int_grid(8, mode)
+            keys, _ = oracle.build(pts, g)
+            q = np.array([w["query"]], np.float32)
+            for fn in (oracle.knn_brute, oracle.knn_kdtree):
+                idx, d2 = fn(keys, q, g, w["k"])
+                got = oracle.decode(keys[idx[0]], 8, mode).tolist()
+                assert got == w["neighbours"] and d2[0].tolist() == w["d2"]
+
+    @pytest.mark.parametrize("mode", [M, L])
+    @pytest.mark.parametrize("k", [1, 3, 8, 16])
+    def test_brute_matches_direct_and_kdtree(self, mode, k):
+        rng = np.random.default_rng(20 + k)
+        d = 5  # small grid: many exact distance ties
+        pts = rng.integers(0, 2 ** d, (600, 3)).astype(np.float32)
+        g = int_grid(d, mode)
+        keys, _ = oracle.build(pts, g)
+        q = rng.integers(0, 2 ** d, (300, 3)).astype(np.float32)
+        idx, d2 = oracle.knn_brute(keys, q, g, k)
+        # direct restatement with numpy: lexsort by (d2, index)
+        vox = oracle.decode(keys, d, mode).astype(np.int64)
+        qv = q.astype(np.int64)
+        for j in range(len(q)):
+            dd = ((vox - qv[j]) ** 2).sum(1)
+            order = np.lexsort((np.arange(len(vox)), dd))[:k]
+            assert (idx[j] == order).all() and (d2[j] == dd[order]).all()
+        ik, dk = oracle.knn_kdtree(keys, q, g, k)
+        assert (ik == idx).all() and (dk == d2).all()
+
+    def test_distances_match_scipy(self):
+        from scipy.spatial import cKDTree
+        rng = np.random.default_rng(30)
+        pts = rng.integers(0, 1000, (5000, 3)).astype(np.float32)
+        g = int_grid(10, M)
+        keys, _ = oracle.build(pts, g)
+        q = rng.integers(0, 1000, (500, 3)).astype(np.float32)
+        _, d2 = oracle.knn_kdtree(keys, q, g, 8)
+        vox = oracle.decode(keys, 10, M).astype(np.float64)
+        dist, _ = cKDTree(vox).query(q.astype(np.float64), k=8)
+        assert np.array_equal(np.rint(dist ** 2).astype(np.uint64), d2)
+
+    def test_occupied_and_padding(self):
+        rng = np.random.default_rng(31)
+        pts = rng.integers(0, 64, (50, 3)).astype(np.float32)
+        g = int_grid(6, M)
+        keys, _ = oracle.build(pts, g)
+        idx, d2 = oracle.knn_brute(keys, pts, g, 1)
+        assert (d2[:, 0] == 0).all()
+        assert (keys[idx[:, 0]] == oracle.encode(pts.astype(np.uint32), 6, M)).all()
+        u = len(keys)
+        idx, d2 = oracle.knn_kdtree(keys, pts[:5], g, u + 3)
+        assert (np.sort(idx[:, :u], 1) == np.arange(u)).all()
+        assert (idx[:, u:] == -1).all() and (d2[:, u:] == np.iinfo(np.uint64).max).all()
+        idx, d2 = oracle.knn_brute(np.zeros(0, np.uint64), pts[:2], g, 2)
+        assert (idx == -1).all()
+
+    @pytest.mark.parametrize("mode", [M, L])
+    def test_paper_cga_nn_matches_brute(self, mode):
+        rng = np.random.default_rng(40 + mode)
+        d = 6
+        pts = rng.integers(0, 2 ** d, (800, 3)).astype(np.float32)
+        g = int_grid(d, mode)
+        keys, _ = oracle.build(pts, g)
+        arr = oracle.arrays(keys, d, mode)
+        qv = rng.integers(0, 2 ** d, (400, 3)).astype(np.uint32)
+        pos, dd = oracle.nn_cga(arr, qv, d, mode)
+        idx, d2 = oracle.knn_brute(keys, qv.astype(np.float32), g, 1)
+        assert (dd == d2[:, 0]).all()
+        # positions are in (x, y, z) order; map the brute-force answer there
+        lin = oracle.encode(oracle.decode(keys[idx[:, 0]], d, mode), d, L)
+        lin_sorted = np.sort(oracle.encode(oracle.decode(keys, d, mode), d, L))
+        assert (np.searchsorted(lin_sorted, lin) == pos).all()
+
+    def test_nonfinite_query(self):
+        keys, _ = oracle.build(np.zeros((1, 3), np.float32), int_grid(4, M))
+        with pytest.raises(oracle.NonFinite):
+            oracle.knn_brute(keys, np.array([[np.nan, 0, 0]], np.float32), int_grid(4, M), 1)
+
+
+# ----------------------------------------------------------------- lookup
+def test_lower_bound_matches_searchsorted():
+    rng = np.random.default_rng(50)
+    keys = np.unique(rng.integers(0, 2 ** 48, 100000).astype(np.uint64))
+    q = np.concatenate([keys[rng.integers(0, len(keys), 5000)],
+                        rng.integers(0, 2 ** 48, 5000).astype(np.uint64),
+                        np.array([0, 2 ** 64 - 1], np.uint64)])
+    rank, found = oracle.lower_bound(keys, q)
+    assert (rank == np.searchsorted(keys, q, side="left")).all()
+    assert (found.astype(bool) == np.isin(q, keys)).all()
+    assert found[:5000].all()
+
+
+# -------------------------------------------------------------- MLP grads
+def test_mlp_gradient_matches_finite_differences():
+    rng = np.random.default_rng(60)
+    p = rng.normal(0, 1, 49)
+    x = rng.uniform(0, 1, 300)
+    t = np.sort(rng.uniform(0, 1, 300))
+    loss, g, kinks = oracle.mlp_loss_grad(p, x, t)
+    assert kinks == 0
+    # direct loss restatement
+    f = (np.maximum(0, np.outer(x, p[:16]) + p[16:32]) * p[32:48]).sum(1) + p[48]
+    assert abs(loss - ((f - t) ** 2).mean()) < 1e-12
+    h = 1e-6
+    for j in range(49):
+        e = np.zeros(49)
+        e[j] = h
+        num = (oracle.mlp_loss_grad(p + e, x, t)[0] - oracle.mlp_loss_grad(p - e, x, t)[0]) / (2 * h)
+        assert abs(num - g[j]) <= 1e-6 * max(1.0, abs(g[j])), j
