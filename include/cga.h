@@ -1,0 +1,182 @@
+/*
+ * cga.h -- C ABI of the MI355X (gfx950) compressed-geometric-array library.
+ *
+ * A compressed geometric array (CGA, Section V of "Compressed Geometric
+ * Arrays for Point Cloud Processing") stores the occupied voxels of a point
+ * cloud in ascending (x, y, z) order with the x and (x, y) prefixes run-length
+ * encoded.  This library keeps the same set as one sorted array of unique
+ * voxel keys -- LINEAR keys x<<2d | y<<d | z give exactly the paper's order,
+ * MORTON keys interleave the bits (x most significant within each bit
+ * triple) for octree locality -- and derives the paper's five coordinate
+ * arrays from it on demand (cga_to_arrays).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named d_* are device pointers owned by the caller; h_* and
+ *    *_host pointers are host pointers.  The library never allocates or frees
+ *    device memory; calls that need scratch space take a caller-owned
+ *    workspace (d_ws, ws_bytes) whose minimum size the matching
+ *    *_workspace_bytes function returns.  A workspace may be reused by later
+ *    calls on the same stream, never by two calls in flight at once.
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *    and the call returns without waiting, unless a *_host output pointer is
+ *    non-NULL: then the call synchronises the stream, fills it, and also
+ *    returns any error the device detected.
+ *  - Key arrays are uint32 when 3*depth <= 32 and uint64 otherwise
+ *    (cga_key_bytes); 2-D pixel keys are uint32 when 2*depth <= 32.
+ *  - Counts may live on the device: every array input has a host size n (an
+ *    upper bound, used to size launches) and an optional d_n (device int64
+ *    holding the actual size <= n).  Outputs report their size through an
+ *    optional d_n_out (device int64) and n_out_host.  This lets a whole
+ *    pipeline run, or be captured in a hipGraph, without host round trips.
+ *  - Device-detected errors (non-finite coordinates, an output larger than its
+ *    capacity) are recorded in the first word of the workspace; n_out_host
+ *    callers get them as the return value, others call cga_ws_status.
+ *    After CGA_ECAPACITY the output contents are unspecified.
+ *  - Return value: CGA_OK or a negative cga_status.  Arguments are validated
+ *    on the host before anything is enqueued.
+ *  - Sizes: n < 2^31 per array.
+ */
+#ifndef CGA_H
+#define CGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *cga_stream; /* hipStream_t */
+
+enum cga_status {
+    CGA_OK = 0,
+    CGA_EINVAL = -1,       /* bad argument (depth, k, axis, null pointer, n < 0 ...) */
+    CGA_ECAPACITY = -2,    /* an output exceeded the capacity the caller gave */
+    CGA_EMISMATCH = -3,    /* operands disagree (grid / key width / index header) */
+    CGA_ENONFINITE = -4,   /* a NaN or Inf coordinate */
+    CGA_EHIP = -5,         /* a HIP runtime error; see cga_last_hip_error */
+    CGA_EWORKSPACE = -6,   /* workspace smaller than required */
+    CGA_EUNSUPPORTED = -7  /* valid request this build does not implement */
+};
+
+enum cga_key_mode { CGA_KEY_MORTON = 0, CGA_KEY_LINEAR = 1 };
+
+/* Quantization frame.  Per axis a: voxel_a = clamp(floor(fl32(fl32(p_a -
+ * origin_a) * scale)), 0, 2^depth - 1), subtract and multiply each rounded
+ * to nearest float32 (never fused).  The cubic bounding box of all clouds
+ * that will be combined is the usual frame (Section II-E, bounding-box
+ * alignment); the paper's own data is already integer voxels (Table II).
+ * depth in [1, 21]; scale finite and > 0; origin finite. */
+typedef struct {
+    float origin[3];
+    float scale;
+    uint32_t depth;
+    uint32_t key_mode; /* cga_key_mode */
+} cga_grid;
+
+/* Optional launch tuning (NULL = built-in or autotuned defaults).  Never
+ * changes results.  radix_bits in [4, 11]; tile_items in {8, 12, 16}. */
+typedef struct {
+    uint32_t radix_bits;
+    uint32_t tile_items;
+} cga_tune;
+
+/* ---------------------------------------------------------------- helpers */
+const char *cga_strerror(int status);
+int cga_last_hip_error(void);
+size_t cga_key_bytes(const cga_grid *grid);  /* 4 or 8; 0 for an invalid grid */
+size_t cga_key2_bytes(const cga_grid *grid); /* 2-D pixel key width */
+/* Synchronise `stream` and return the error recorded in d_ws by the last
+ * call that used it (CGA_OK if none). */
+int cga_ws_status(const void *d_ws, cga_stream stream);
+
+/* ------------------------------------------------------------------ build
+ * CGA construction (Section V): quantize n float32 points (AoS x,y,z) by
+ * the grid rule, encode each voxel as a key, radix-sort the keys and collapse
+ * equal keys.  Output: the U unique keys ascending in d_keys (capacity cap)
+ * and, if d_counts is non-NULL, the number of input points in each voxel
+ * (uint32).  U goes to d_n_out / n_out_host.  n may be 0.
+ * Errors: CGA_ENONFINITE (device), CGA_ECAPACITY if U > cap (device). */
+size_t cga_build_workspace_bytes(const cga_grid *grid, int64_t n);
+int cga_build(const cga_grid *grid, const float *d_xyz, int64_t n, void *d_keys,
+              uint32_t *d_counts, int64_t cap, int64_t *d_n_out, int64_t *n_out_host,
+              void *d_ws, size_t ws_bytes, const cga_tune *tune, cga_stream stream);
+
+/* Quantize + encode only: the per-point key of each input point, in input
+ * order (no sort, no dedupe).  Exposed for parity tests of the encoder. */
+int cga_encode_keys(const cga_grid *grid, const float *d_xyz, int64_t n, void *d_keys,
+                    void *d_ws, size_t ws_bytes, cga_stream stream);
+
+/* Stable LSD radix sort of n keys of the grid's key width on their low
+ * `key_bits` bits (the significant bits of the grid's keys if 0).  Sorted
+ * keys go to d_out (may equal d_keys).  Exposed for parity tests. */
+size_t cga_sort_workspace_bytes(const cga_grid *grid, int64_t n);
+int cga_sort_keys(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,
+                  uint32_t key_bits, void *d_out, void *d_ws, size_t ws_bytes,
+                  const cga_tune *tune, cga_stream stream);
+
+/* The paper's five CGA arrays (Section V) from a LINEAR-mode key array of n
+ * unique ascending keys.  Readings of the definitions: all levels ascending;
+ * X_pointer is indexed by position in X_index (length n_x + 1) and counts the
+ * distinct y of each x; Y_pointer counts the z of each (x, y) pair (length
+ * n_xy + 1).  Outputs (capacity n each, pointers n + 1): d_x_index (uint32),
+ * d_x_ptr (int64), d_y_index (uint32), d_y_ptr (int64), d_z_index (uint32);
+ * n_x and n_xy go to the optional device/host outputs.
+ * CGA_EMISMATCH for a MORTON grid. */
+size_t cga_to_arrays_workspace_bytes(const cga_grid *grid, int64_t n);
+int cga_to_arrays(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,
+                  uint32_t *d_x_index, int64_t *d_x_ptr, uint32_t *d_y_index, int64_t *d_y_ptr,
+                  uint32_t *d_z_index, int64_t *d_n_x, int64_t *d_n_xy, int64_t *n_x_host,
+                  int64_t *n_xy_host, void *d_ws, size_t ws_bytes, cga_stream stream);
+
+/* ------------------------------------------------------------------ merge
+ * Merge, Eq. (1): the union of two CGAs of the same grid (sorted unique key
+ * arrays a, b) as one sorted unique key array.  d_src (nullable) receives a
+ * provenance byte per output key: 1 = only in a, 2 = only in b, 3 = both.
+ * Errors: CGA_ECAPACITY if the union exceeds cap (device). */
+size_t cga_merge_workspace_bytes(const cga_grid *grid, int64_t na, int64_t nb);
+int cga_merge(const cga_grid *grid, const void *d_a, int64_t na, const int64_t *d_na,
+              const void *d_b, int64_t nb, const int64_t *d_nb, void *d_out, uint8_t *d_src,
+              int64_t cap, int64_t *d_n_out, int64_t *n_out_host, void *d_ws, size_t ws_bytes,
+              cga_stream stream);
+
+/* ------------------------------------------------------------- projection
+ * Orthogonal projection, Eq. (3) with m_x = m_y = 1 (Section V-B), along
+ * axis drop_axis (0 = x, 1 = y, 2 = z): the set of 2-D pixels (u, v) -- the
+ * two remaining coordinates in x, y, z order -- hit by at least one voxel, as
+ * sorted unique 2-D keys (MORTON: u bit b -> 2b+1, v bit b -> 2b; LINEAR:
+ * u<<d | v), with the number of voxels on each pixel in d_counts (nullable).
+ * Errors: CGA_ECAPACITY (device). */
+size_t cga_project_workspace_bytes(const cga_grid *grid, int64_t n);
+int cga_project(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,
+                int drop_axis, void *d_out2d, uint32_t *d_counts, int64_t cap,
+                int64_t *d_n_out, int64_t *n_out_host, void *d_ws, size_t ws_bytes,
+                const cga_tune *tune, cga_stream stream);
+
+/* --------------------------------------------------------------------- kNN
+ * Nearest-neighbour search, Eq. (7)-(8), generalised to k: for each of nq
+ * float32 query points (AoS), quantized by the grid rule, the k voxels of the
+ * CGA smallest in (squared voxel distance, key).  Outputs row-major nq x k:
+ * d_idx (int64 position in the key array, -1 padding when fewer than k
+ * voxels exist) and d_d2 (uint64 squared distance, UINT64_MAX padding).
+ * k in [1, 32].  MORTON grids only in this build (LINEAR: CGA_EUNSUPPORTED).
+ * Errors: CGA_ENONFINITE for a non-finite query (device). */
+size_t cga_knn_workspace_bytes(const cga_grid *grid, int64_t n, int64_t nq);
+int cga_knn(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,
+            const float *d_q, int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2, void *d_ws,
+            size_t ws_bytes, cga_stream stream);
+
+/* ----------------------------------------------------------------- lookup
+ * Point location and range start over a sorted unique uint64 key array (the
+ * lookup of Section V-A; Table III): rank = number of keys < q (lower bound),
+ * found = (rank < n && keys[rank] == q).  Plain branch-free binary search;
+ * the judge of the learned index below.  d_found nullable. */
+int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n,
+                      const uint64_t *d_q, int64_t nq, int64_t *d_rank, uint8_t *d_found,
+                      cga_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGA_H */

@@ -1,0 +1,313 @@
+"""Python binding of libcga.so, the MI355X compressed-geometric-array library.
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory (tensors) and the stream.  Function names
+match the C entry points of include/cga.h.  Keys travel as int32 / int64
+tensors holding the uint32 / uint64 bit patterns.
+
+The library must be built (``python -m paper_2110_11616_amd._build`` or
+``__graft_entry__.build()``); importing without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcga.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2110_11616_amd._build.build()")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+KEY_MORTON = 0
+KEY_LINEAR = 1
+
+OK, EINVAL, ECAPACITY, EMISMATCH, ENONFINITE, EHIP, EWORKSPACE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+
+
+class cga_grid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_float * 3), ("scale", ctypes.c_float),
+                ("depth", ctypes.c_uint32), ("key_mode", ctypes.c_uint32)]
+
+
+class cga_tune(ctypes.Structure):
+    _fields_ = [("radix_bits", ctypes.c_uint32), ("tile_items", ctypes.c_uint32)]
+
+
+class CgaError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib.cga_strerror(status).decode()
+        if status == EHIP:
+            msg += f" (hipError {lib.cga_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{status}]")
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_GP = ctypes.POINTER(cga_grid)
+_TP = ctypes.POINTER(cga_tune)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+
+def _sig(name, restype, *args):
+    f = getattr(lib, name)
+    f.restype = restype
+    f.argtypes = list(args)
+    return f
+
+
+_sig("cga_strerror", ctypes.c_char_p, ctypes.c_int)
+_sig("cga_last_hip_error", ctypes.c_int)
+_sig("cga_key_bytes", _SZ, _GP)
+_sig("cga_key2_bytes", _SZ, _GP)
+_sig("cga_ws_status", ctypes.c_int, _P, _P)
+_sig("cga_build_workspace_bytes", _SZ, _GP, _I64)
+_sig("cga_build", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _I64P, _P, _SZ, _TP, _P)
+_sig("cga_encode_keys", ctypes.c_int, _GP, _P, _I64, _P, _P, _SZ, _P)
+_sig("cga_sort_workspace_bytes", _SZ, _GP, _I64)
+_sig("cga_sort_keys", ctypes.c_int, _GP, _P, _I64, _P, ctypes.c_uint32, _P, _P, _SZ, _TP, _P)
+_sig("cga_to_arrays_workspace_bytes", _SZ, _GP, _I64)
+_sig("cga_to_arrays", ctypes.c_int, _GP, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64P, _I64P,
+     _P, _SZ, _P)
+_sig("cga_merge_workspace_bytes", _SZ, _GP, _I64, _I64)
+_sig("cga_merge", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _P, _P, _I64, _P, _I64P, _P, _SZ,
+     _P)
+_sig("cga_project_workspace_bytes", _SZ, _GP, _I64)
+_sig("cga_project", ctypes.c_int, _GP, _P, _I64, _P, ctypes.c_int, _P, _P, _I64, _P, _I64P, _P,
+     _SZ, _TP, _P)
+_sig("cga_knn_workspace_bytes", _SZ, _GP, _I64, _I64)
+_sig("cga_knn", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, ctypes.c_int, _P, _P, _P, _SZ, _P)
+_sig("cga_binary_lookup", ctypes.c_int, _P, _I64, _P, _P, _I64, _P, _P, _P)
+
+
+# ------------------------------------------------------------------ helpers
+@dataclass(frozen=True)
+class Grid:
+    origin: tuple
+    scale: float
+    depth: int
+    key_mode: int = KEY_MORTON
+
+
+def grid_struct(g) -> cga_grid:
+    s = cga_grid()
+    for a in range(3):
+        s.origin[a] = float(g.origin[a])
+    s.scale = float(g.scale)
+    s.depth = int(g.depth)
+    s.key_mode = int(g.key_mode)
+    return s
+
+
+def tune_struct(t):
+    if t is None:
+        return None
+    s = cga_tune()
+    s.radix_bits, s.tile_items = int(t[0]), int(t[1])
+    return ctypes.byref(s)
+
+
+def key_dtype(g) -> torch.dtype:
+    return torch.int64 if 3 * g.depth > 32 else torch.int32
+
+
+def key2_dtype(g) -> torch.dtype:
+    return torch.int64 if 2 * g.depth > 32 else torch.int32
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise CgaError(rc, where)
+
+
+class Workspaces:
+    """Reusable device workspaces, grown on demand, one per name."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.bufs = {}
+
+    def get(self, name: str, nbytes: int) -> torch.Tensor:
+        b = self.bufs.get(name)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            self.bufs[name] = b
+        return b
+
+
+_default_ws = None
+
+
+def _ws(name, nbytes, ws):
+    global _default_ws
+    if ws is None:
+        if _default_ws is None:
+            _default_ws = Workspaces()
+        ws = _default_ws
+    return ws.get(name, nbytes)
+
+
+def _cap_tensor(n, dtype, device):
+    return torch.empty(max(int(n), 1), dtype=dtype, device=device)
+
+
+def _hostcount():
+    return ctypes.c_int64(0)
+
+
+# --------------------------------------------------------------- entry points
+def cga_build(xyz: torch.Tensor, grid, *, counts: bool = True, cap=None, tune=None, keys_out=None,
+              counts_out=None, d_n_out=None, sync: bool = True, ws=None, stream=None):
+    """CGA construction (Section V).  Returns (keys, counts) trimmed to U when
+    sync, else (keys, counts, d_n_out) untrimmed with the count on device."""
+    assert xyz.is_cuda and xyz.dtype == torch.float32 and xyz.is_contiguous()
+    n = xyz.shape[0]
+    g = grid_struct(grid)
+    cap = n if cap is None else int(cap)
+    keys = keys_out if keys_out is not None else _cap_tensor(cap, key_dtype(grid), xyz.device)
+    cnt = counts_out if counts_out is not None else (
+        _cap_tensor(cap, torch.int32, xyz.device) if counts else None)
+    wsb = _ws("build", lib.cga_build_workspace_bytes(ctypes.byref(g), n), ws)
+    h = _hostcount()
+    rc = lib.cga_build(ctypes.byref(g), _ptr(xyz), n, _ptr(keys), _ptr(cnt), cap, _ptr(d_n_out),
+                       ctypes.byref(h) if sync else None, _ptr(wsb), wsb.numel(),
+                       tune_struct(tune), _stream(stream))
+    _check(rc, "cga_build")
+    if sync:
+        u = h.value
+        return keys[:u], (cnt[:u] if cnt is not None else None)
+    return keys, cnt, d_n_out
+
+
+def cga_encode_keys(xyz: torch.Tensor, grid, ws=None, stream=None) -> torch.Tensor:
+    n = xyz.shape[0]
+    g = grid_struct(grid)
+    keys = _cap_tensor(n, key_dtype(grid), xyz.device)
+    wsb = _ws("encode", 256, ws)
+    _check(lib.cga_encode_keys(ctypes.byref(g), _ptr(xyz), n, _ptr(keys), _ptr(wsb), wsb.numel(),
+                               _stream(stream)), "cga_encode_keys")
+    _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_encode_keys")
+    return keys[:n]
+
+
+def cga_sort_keys(keys: torch.Tensor, grid, key_bits: int = 0, tune=None, ws=None, stream=None,
+                  out=None) -> torch.Tensor:
+    n = keys.shape[0]
+    g = grid_struct(grid)
+    out = out if out is not None else torch.empty_like(keys)
+    wsb = _ws("sort", lib.cga_sort_workspace_bytes(ctypes.byref(g), n), ws)
+    _check(lib.cga_sort_keys(ctypes.byref(g), _ptr(keys), n, None, key_bits, _ptr(out), _ptr(wsb),
+                             wsb.numel(), tune_struct(tune), _stream(stream)), "cga_sort_keys")
+    return out
+
+
+def cga_to_arrays(keys: torch.Tensor, grid, ws=None, stream=None) -> dict:
+    """The paper's X_index, X_pointer, Y_index, Y_pointer, Z_index (LINEAR)."""
+    n = keys.shape[0]
+    g = grid_struct(grid)
+    dev = keys.device
+    xi = _cap_tensor(n, torch.int32, dev)
+    xp = _cap_tensor(n + 1, torch.int64, dev)
+    yi = _cap_tensor(n, torch.int32, dev)
+    yp = _cap_tensor(n + 1, torch.int64, dev)
+    zi = _cap_tensor(n, torch.int32, dev)
+    nx, nxy = _hostcount(), _hostcount()
+    wsb = _ws("arrays", lib.cga_to_arrays_workspace_bytes(ctypes.byref(g), n), ws)
+    _check(lib.cga_to_arrays(ctypes.byref(g), _ptr(keys), n, None, _ptr(xi), _ptr(xp), _ptr(yi),
+                             _ptr(yp), _ptr(zi), None, None, ctypes.byref(nx), ctypes.byref(nxy),
+                             _ptr(wsb), wsb.numel(), _stream(stream)), "cga_to_arrays")
+    return dict(x_index=xi[:nx.value], x_pointer=xp[:nx.value + 1], y_index=yi[:nxy.value],
+                y_pointer=yp[:nxy.value + 1], z_index=zi[:n])
+
+
+def cga_merge(a: torch.Tensor, b: torch.Tensor, grid, *, src: bool = False, cap=None, na=None,
+              d_na=None, nb=None, d_nb=None, out=None, src_out=None, d_n_out=None,
+              sync: bool = True, ws=None, stream=None):
+    """Merge, Eq. (1).  Returns (union keys, provenance or None)."""
+    na = a.shape[0] if na is None else int(na)
+    nb = b.shape[0] if nb is None else int(nb)
+    g = grid_struct(grid)
+    cap = na + nb if cap is None else int(cap)
+    dev = a.device
+    out = out if out is not None else _cap_tensor(cap, key_dtype(grid), dev)
+    s = src_out if src_out is not None else (_cap_tensor(cap, torch.uint8, dev) if src else None)
+    wsb = _ws("merge", lib.cga_merge_workspace_bytes(ctypes.byref(g), na, nb), ws)
+    h = _hostcount()
+    rc = lib.cga_merge(ctypes.byref(g), _ptr(a), na, _ptr(d_na), _ptr(b), nb, _ptr(d_nb), _ptr(out),
+                       _ptr(s), cap, _ptr(d_n_out), ctypes.byref(h) if sync else None, _ptr(wsb),
+                       wsb.numel(), _stream(stream))
+    _check(rc, "cga_merge")
+    if sync:
+        u = h.value
+        return out[:u], (s[:u] if s is not None else None)
+    return out, s, d_n_out
+
+
+def cga_project(keys: torch.Tensor, grid, drop_axis: int, *, counts: bool = True, cap=None, n=None,
+                d_n=None, out=None, counts_out=None, d_n_out=None, tune=None, sync: bool = True,
+                ws=None, stream=None):
+    """Orthogonal projection, Eq. (3): (sorted unique 2-D keys, voxel counts)."""
+    n = keys.shape[0] if n is None else int(n)
+    g = grid_struct(grid)
+    cap = n if cap is None else int(cap)
+    dev = keys.device
+    out = out if out is not None else _cap_tensor(cap, key2_dtype(grid), dev)
+    cnt = counts_out if counts_out is not None else (
+        _cap_tensor(cap, torch.int32, dev) if counts else None)
+    wsb = _ws("project", lib.cga_project_workspace_bytes(ctypes.byref(g), n), ws)
+    h = _hostcount()
+    rc = lib.cga_project(ctypes.byref(g), _ptr(keys), n, _ptr(d_n), int(drop_axis), _ptr(out),
+                         _ptr(cnt), cap, _ptr(d_n_out), ctypes.byref(h) if sync else None,
+                         _ptr(wsb), wsb.numel(), tune_struct(tune), _stream(stream))
+    _check(rc, "cga_project")
+    if sync:
+        u = h.value
+        return out[:u], (cnt[:u] if cnt is not None else None)
+    return out, cnt, d_n_out
+
+
+def cga_knn(keys: torch.Tensor, queries: torch.Tensor, grid, k: int, *, n=None, d_n=None,
+            idx_out=None, d2_out=None, sync: bool = True, ws=None, stream=None):
+    """k-NN, Eq. (7)-(8): (int64 indices, uint64 squared distances as int64)."""
+    n = keys.shape[0] if n is None else int(n)
+    nq = queries.shape[0]
+    g = grid_struct(grid)
+    dev = queries.device
+    idx = idx_out if idx_out is not None else torch.empty((nq, k), dtype=torch.int64, device=dev)
+    d2 = d2_out if d2_out is not None else torch.empty((nq, k), dtype=torch.int64, device=dev)
+    wsb = _ws("knn", lib.cga_knn_workspace_bytes(ctypes.byref(g), n, nq), ws)
+    rc = lib.cga_knn(ctypes.byref(g), _ptr(keys), n, _ptr(d_n), _ptr(queries), nq, int(k),
+                     _ptr(idx), _ptr(d2), _ptr(wsb), wsb.numel(), _stream(stream))
+    _check(rc, "cga_knn")
+    if sync:
+        _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_knn")
+    return idx, d2
+
+
+def cga_binary_lookup(keys: torch.Tensor, q: torch.Tensor, *, n=None, d_n=None, rank_out=None,
+                      found_out=None, stream=None):
+    """Lower bound + membership by plain binary search."""
+    n = keys.shape[0] if n is None else int(n)
+    nq = q.shape[0]
+    rank = rank_out if rank_out is not None else torch.empty(nq, dtype=torch.int64, device=q.device)
+    found = found_out if found_out is not None else torch.empty(nq, dtype=torch.uint8,
+                                                                device=q.device)
+    _check(lib.cga_binary_lookup(_ptr(keys), n, _ptr(d_n), _ptr(q), nq, _ptr(rank), _ptr(found),
+                                 _stream(stream)), "cga_binary_lookup")
+    return rank, found

@@ -1,0 +1,248 @@
+// Shared device and host helpers of the CGA HIP library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/cga.h"
+
+namespace cga {
+
+// ------------------------------------------------------------------ host
+extern thread_local int g_last_hip_error;
+
+#define CGA_HIP(call)                                          \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) {                                \
+            ::cga::g_last_hip_error = (int)e_;                 \
+            return CGA_EHIP;                                   \
+        }                                                      \
+    } while (0)
+
+#define CGA_TRY(expr)              \
+    do {                           \
+        int r_ = (expr);           \
+        if (r_ != CGA_OK) return r_; \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over a caller workspace; every region 256-byte aligned.
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *p) : base((char *)p) {}
+    template <typename T>
+    T *take(size_t count) {
+        off = align_up(off, 256);
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t size() const { return align_up(off, 256); }
+};
+
+bool grid_valid(const cga_grid *g);
+inline bool wide_keys(uint32_t depth) { return 3 * depth > 32; }
+inline bool wide_keys2(uint32_t depth) { return 2 * depth > 32; }
+
+// Error bits recorded by kernels in the workspace status word.
+enum : uint32_t { ERR_NONFINITE = 1u, ERR_CAPACITY = 2u };
+int status_from_bits(uint32_t bits);
+
+// Control block at the start of every workspace.
+struct Control {
+    uint32_t err;           // ERR_* bits of the last call
+    uint32_t pad;
+    int64_t count;          // output size when the caller gives no d_n_out
+    int64_t count2;         // second output size (cga_to_arrays)
+    uint32_t tile_ctr[48];  // dynamic tile counters, one per kernel of a call
+};
+constexpr size_t kControlBytes = 256;
+static_assert(sizeof(Control) <= kControlBytes, "control block");
+
+// Enqueue the call prologue: zero the control block, optional regions, and
+// set an optional device count output to 0.
+int launch_begin(Control *ctl, void *z0, size_t z0_bytes, void *z1, size_t z1_bytes,
+                 int64_t *d_n_out, hipStream_t s, int64_t *zero2 = nullptr,
+                 int64_t *zero3 = nullptr, int64_t *zero4 = nullptr);
+// Synchronise and translate the control block's error bits.
+int finish_sync(const Control *ctl, hipStream_t s);
+
+// ---------------------------------------------------------------- device
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (uint64_t(1) << lane_id()) - 1;  // lane 0 -> 0
+}
+
+// Agent-scope (whole-GPU, across XCDs) relaxed atomics for chained scans.
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_agent(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void set_err(uint32_t *err, uint32_t bit) {
+    __hip_atomic_fetch_or(err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Inclusive wave scan (sum) with cross-lane shuffles.
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T u = __shfl_up(v, o, 64);
+        if (lane_id() >= o) v += u;
+    }
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_incl_max(T v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T u = __shfl_up(v, o, 64);
+        if (lane_id() >= o) v = v > u ? v : u;
+    }
+    return v;
+}
+
+// Block-wide exclusive sum of one value per thread.  `s_wave` holds
+// BLOCK/64 entries.  Returns the exclusive prefix; *total gets the sum.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_excl_sum(T v, T *s_wave, T *total) {
+    constexpr int WAVES = BLOCK / 64;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    T inc = wave_incl_sum(v);
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    T wbase = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        T x = s_wave[w];
+        if (w < wave) wbase += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return wbase + inc - v;
+}
+
+// Block-wide exclusive max (identity `lo`) of one value per thread.
+template <int BLOCK, typename T>
+__device__ __forceinline__ T block_excl_max(T v, T lo, T *s_wave, T *total) {
+    constexpr int WAVES = BLOCK / 64;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    T inc = wave_incl_max(v);
+    T exc = __shfl_up(inc, 1, 64);
+    if (lane == 0) exc = lo;
+    if (lane == 63) s_wave[wave] = inc;
+    __syncthreads();
+    T wbase = lo, tot = lo;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        T x = s_wave[w];
+        if (w < wave) wbase = wbase > x ? wbase : x;
+        tot = tot > x ? tot : x;
+    }
+    __syncthreads();
+    *total = tot;
+    return wbase > exc ? wbase : exc;
+}
+
+// Dynamic tile id: tiles are numbered in the order their workgroups start,
+// so a tile only ever waits on tiles that are already running.
+__device__ __forceinline__ uint32_t next_tile(uint32_t *ctr, uint32_t *s_slot) {
+    if (threadIdx.x == 0) *s_slot = atomicAdd(ctr, 1u);
+    __syncthreads();
+    return *s_slot;
+}
+
+__device__ __forceinline__ int64_t dev_count(int64_t n_host, const int64_t *d_n) {
+    return d_n ? *d_n : n_host;
+}
+
+// ------------------------------------------------------- key bit shuffles
+// Spread the low 21 bits of v so bit b lands at bit 3b.
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+    v &= 0x1FFFFFull;
+    v = (v | (v << 32)) & 0x1F00000000FFFFull;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+// Inverse of spread3: gather bits 3b into bit b.
+__device__ __forceinline__ uint32_t compact3(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10C30C30C30C30C3ull;
+    v = (v ^ (v >> 4)) & 0x100F00F00F00F00Full;
+    v = (v ^ (v >> 8)) & 0x1F0000FF0000FFull;
+    v = (v ^ (v >> 16)) & 0x1F00000000FFFFull;
+    v = (v ^ (v >> 32)) & 0x1FFFFFull;
+    return (uint32_t)v;
+}
+// Spread the low 32 bits so bit b lands at bit 2b.
+__device__ __forceinline__ uint64_t spread2(uint64_t v) {
+    v &= 0xFFFFFFFFull;
+    v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
+    v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
+    v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    v = (v | (v << 2)) & 0x3333333333333333ull;
+    v = (v | (v << 1)) & 0x5555555555555555ull;
+    return v;
+}
+
+struct Vox {
+    uint32_t x, y, z;
+};
+
+__device__ __forceinline__ uint64_t enc3(uint32_t x, uint32_t y, uint32_t z, uint32_t depth,
+                                         bool linear) {
+    if (linear)
+        return ((uint64_t)x << (2 * depth)) | ((uint64_t)y << depth) | (uint64_t)z;
+    return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+
+__device__ __forceinline__ Vox dec3(uint64_t k, uint32_t depth, bool linear) {
+    if (linear) {
+        const uint64_t m = (1ull << depth) - 1;
+        return Vox{(uint32_t)((k >> (2 * depth)) & m), (uint32_t)((k >> depth) & m),
+                   (uint32_t)(k & m)};
+    }
+    return Vox{compact3(k >> 2), compact3(k >> 1), compact3(k)};
+}
+
+// Grid rule: floor(fl32(fl32(p - o) * s)) clamped to [0, 2^d - 1], each
+// operation rounded separately (explicit round-to-nearest intrinsics, so no
+// contraction into an FMA).  Returns false for a non-finite coordinate.
+__device__ __forceinline__ bool quantize3(float px, float py, float pz, const float o[3],
+                                          float s, uint32_t depth, Vox &v) {
+    const float top = (float)((1u << depth) - 1u);
+    const float p[3] = {px, py, pz};
+    uint32_t r[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ok = ok && isfinite(p[a]);
+        float t = __fsub_rn(p[a], o[a]);
+        float u = __fmul_rn(t, s);
+        float f = floorf(u);
+        f = f >= 0.0f ? f : 0.0f;  // NaN-safe: comparison false -> 0
+        f = f <= top ? f : top;
+        r[a] = (uint32_t)f;
+    }
+    v = Vox{r[0], r[1], r[2]};
+    return ok;
+}
+
+}  // namespace cga

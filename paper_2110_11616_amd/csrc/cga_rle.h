@@ -1,0 +1,145 @@
+// Run-length compaction of a sorted key sequence: one pass that finds run
+// heads (v[i] != v[i-1]) and tails (v[i] != v[i+1]), numbers the runs with a
+// block scan plus a decoupled look-back over earlier tiles, and writes one
+// value per run and either the run length or the running end offset.
+//
+// The scanned pair is (heads so far, index of the latest head); the second
+// component lets a tail whose head lies in an earlier tile compute its run
+// length without a second pass.
+#pragma once
+
+#include "cga_common.h"
+
+namespace cga {
+
+constexpr int kRleBlock = 256;
+constexpr int kRleItems = 16;
+constexpr int kRleTile = kRleBlock * kRleItems;
+
+inline int64_t rle_tiles(int64_t n) { return n <= 0 ? 1 : (n + kRleTile - 1) / kRleTile; }
+
+// status word: [flag:2][heads:31][latest head index + 1:31]
+constexpr uint64_t kRleAgg = 1ull << 62;
+constexpr uint64_t kRleInc = 2ull << 62;
+__device__ __forceinline__ uint64_t rle_pack(uint64_t flag, uint32_t cnt, int32_t last) {
+    return flag | ((uint64_t)cnt << 31) | (uint64_t)(uint32_t)(last + 1);
+}
+__device__ __forceinline__ uint32_t rle_cnt(uint64_t s) { return (uint32_t)((s >> 31) & 0x7FFFFFFFu); }
+__device__ __forceinline__ int32_t rle_last(uint64_t s) { return (int32_t)(s & 0x7FFFFFFFu) - 1; }
+
+// v_i = in[i] >> shift.  Per run u (in order): vals[u] = v & out_mask, and
+// counts[u] = run length (COUNTS) or ends[u + 1] = one past the run's last
+// index with ends[0] = 0 (ENDS).  Either output pointer may be null.
+template <typename K, typename OV, bool ENDS>
+__global__ __launch_bounds__(kRleBlock) void k_rle(const K *__restrict__ in, int64_t n_host,
+                                                   const int64_t *d_n, int shift,
+                                                   uint64_t out_mask, OV *__restrict__ vals,
+                                                   uint32_t *__restrict__ counts,
+                                                   int64_t *__restrict__ ends, int64_t cap,
+                                                   int64_t *n_out, uint64_t *status,
+                                                   uint32_t *tile_ctr, uint32_t *err) {
+    __shared__ uint32_t s_tile;
+    // logical slot j lives at j + j/16, so the blocked per-thread reads below
+    // (16 consecutive slots per thread) do not all fall in one LDS bank
+    __shared__ K s_v[kRleTile + 2 + (kRleTile + 2) / 16 + 1];
+#define SV(j) s_v[(j) + ((j) >> 4)]
+    __shared__ uint32_t s_wc[kRleBlock / 64];
+    __shared__ int32_t s_wl[kRleBlock / 64];
+    __shared__ uint32_t s_pc;
+    __shared__ int32_t s_pl;
+
+    const int tid = threadIdx.x;
+    const uint32_t tile = next_tile(tile_ctr, &s_tile);
+    const int64_t n = dev_count(n_host, d_n);
+    const int64_t base = (int64_t)tile * kRleTile;
+    if (base >= n) return;
+
+    for (int j = tid; j < kRleTile; j += kRleBlock) {
+        int64_t i = base + j;
+        SV(1 + j) = i < n ? (K)(in[i] >> shift) : K(0);
+    }
+    if (tid == 0) SV(0) = base > 0 ? (K)(in[base - 1] >> shift) : K(0);
+    if (tid == 1) SV(kRleTile + 1) = base + kRleTile < n ? (K)(in[base + kRleTile] >> shift) : K(0);
+    __syncthreads();
+
+    const int j0 = tid * kRleItems;
+    uint32_t hc = 0;
+    int32_t hl = -1;
+#pragma unroll
+    for (int it = 0; it < kRleItems; ++it) {
+        int j = j0 + it;
+        int64_t i = base + j;
+        if (i < n && (i == 0 || SV(1 + j) != SV(j))) {
+            ++hc;
+            hl = (int32_t)i;
+        }
+    }
+    uint32_t tot_c;
+    int32_t tot_l;
+    uint32_t ex_c = block_excl_sum<kRleBlock>(hc, s_wc, &tot_c);
+    int32_t ex_l = block_excl_max<kRleBlock>(hl, (int32_t)-1, s_wl, &tot_l);
+
+    if (tid == 0) {
+        uint32_t pc = 0;
+        int32_t pl = -1;
+        if (tile == 0) {
+            st_agent(&status[tile], rle_pack(kRleInc, tot_c, tot_l));
+        } else {
+            st_agent(&status[tile], rle_pack(kRleAgg, tot_c, tot_l));
+            int64_t t = (int64_t)tile - 1;
+            for (;;) {
+                uint64_t st = ld_agent(&status[t]);
+                if ((st >> 62) == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                pc += rle_cnt(st);
+                int32_t l = rle_last(st);
+                pl = pl > l ? pl : l;
+                if (st & kRleInc) break;
+                --t;
+            }
+            int32_t il = pl > tot_l ? pl : tot_l;
+            st_agent(&status[tile], rle_pack(kRleInc, pc + tot_c, il));
+        }
+        s_pc = pc;
+        s_pl = pl;
+        if (ENDS && tile == 0 && ends) ends[0] = 0;
+    }
+    __syncthreads();
+
+    uint32_t rc = s_pc + ex_c;
+    int32_t rl = s_pl > ex_l ? s_pl : ex_l;
+    bool over = false;
+#pragma unroll
+    for (int it = 0; it < kRleItems; ++it) {
+        int j = j0 + it;
+        int64_t i = base + j;
+        if (i < n) {
+            K v = SV(1 + j);
+            if (i == 0 || v != SV(j)) {
+                ++rc;
+                rl = (int32_t)i;
+                if ((int64_t)rc <= cap) {
+                    if (vals) vals[rc - 1] = (OV)((uint64_t)v & out_mask);
+                } else {
+                    over = true;
+                }
+            }
+            if (i == n - 1 || v != SV(2 + j)) {
+                if ((int64_t)rc <= cap) {
+                    if (ENDS) {
+                        if (ends) ends[rc] = i + 1;
+                    } else if (counts) {
+                        counts[rc - 1] = (uint32_t)(i + 1 - rl);
+                    }
+                }
+                if (i == n - 1 && n_out) *n_out = rc;
+            }
+        }
+    }
+    if (over) set_err(err, ERR_CAPACITY);
+#undef SV
+}
+
+}  // namespace cga

@@ -1,0 +1,323 @@
+// LSD radix sort of voxel keys for gfx950: one upfront histogram of every
+// digit, then one "onesweep" kernel per digit (Adinets & Merrill, 2022): each
+// workgroup ranks a tile of keys by digit with wave64 ballots, finds the
+// global position of each of its digit buckets by a decoupled look-back over
+// the tiles before it (Merrill & Garland, 2016), stages the tile in LDS in
+// digit order and scatters it.  Stable, so passes compose.
+#pragma once
+
+#include "cga_common.h"
+
+namespace cga {
+
+constexpr int kSortBlock = 256;
+constexpr int kMaxPasses = 16;  // 64 bits at 4 bits per digit
+
+// Look-back status word: 2-bit flag + 30-bit count.
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagInc = 2u << 30;
+constexpr uint32_t kValMask = (1u << 30) - 1;
+
+struct SortCfg {
+    int radix_bits = 8;
+    int items = 16;
+};
+
+inline int sort_passes(int key_bits, int radix_bits) {
+    return key_bits <= 0 ? 0 : (key_bits + radix_bits - 1) / radix_bits;
+}
+inline int64_t sort_tiles(int64_t n, int items) {
+    int64_t t = (int64_t)kSortBlock * items;
+    return n <= 0 ? 1 : (n + t - 1) / t;
+}
+
+// ------------------------------------------------------------ histogram
+// Adds key's digits of every pass into LDS counters s_h[p][digit].
+template <int RB, typename K>
+__device__ __forceinline__ void hist_add(uint32_t *s_h, K key, int passes) {
+    constexpr uint32_t RADIX = 1u << RB;
+    for (int p = 0; p < passes; ++p) {
+        uint32_t d = (uint32_t)(key >> (p * RB)) & (RADIX - 1);
+        atomicAdd(&s_h[p * RADIX + d], 1u);
+    }
+}
+
+template <int RB>
+__device__ __forceinline__ void hist_flush(const uint32_t *s_h, uint32_t *g_h, int passes) {
+    constexpr uint32_t RADIX = 1u << RB;
+    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += blockDim.x) {
+        uint32_t c = s_h[i];
+        if (c) atomicAdd(&g_h[i], c);
+    }
+}
+
+template <typename K, int RB>
+__global__ __launch_bounds__(kSortBlock) void k_histogram(const K *__restrict__ in, int64_t n_host,
+                                                          const int64_t *d_n, int passes,
+                                                          uint32_t *__restrict__ hist) {
+    constexpr uint32_t RADIX = 1u << RB;
+    extern __shared__ uint32_t s_h[];
+    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const int64_t n = dev_count(n_host, d_n);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        hist_add<RB>(s_h, in[i], passes);
+    __syncthreads();
+    hist_flush<RB>(s_h, hist, passes);
+}
+
+// Exclusive scan of each pass's histogram in place (one block per pass).
+template <int RB>
+__global__ __launch_bounds__(kSortBlock) void k_hist_scan(uint32_t *hist) {
+    constexpr int RADIX = 1 << RB;
+    constexpr int DPT = RADIX > kSortBlock ? RADIX / kSortBlock : 1;
+    __shared__ uint32_t s_w[kSortBlock / 64];
+    uint32_t *h = hist + (size_t)blockIdx.x * RADIX;
+    uint32_t v[DPT], sum = 0;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        int d = t * DPT + j;
+        v[j] = d < RADIX ? h[d] : 0u;
+        sum += v[j];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_sum<kSortBlock>(sum, s_w, &tot);
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        int d = t * DPT + j;
+        if (d < RADIX) h[d] = ex;
+        ex += v[j];
+    }
+}
+
+// --------------------------------------------------------- onesweep pass
+// One LSD pass on digit bits [shift, shift + RB).  `look` holds one status
+// word per (tile, digit) and must be zero on entry; each tile also zeroes its
+// own slots of `look_next`, the status array of the following pass.
+template <typename K, int RB, int ITEMS>
+__global__ __launch_bounds__(kSortBlock) void k_onesweep(
+    const K *__restrict__ in, K *__restrict__ out, int64_t n_host, const int64_t *d_n, int shift,
+    const uint32_t *__restrict__ digit_base, uint32_t *look, uint32_t *look_next,
+    uint32_t *tile_ctr) {
+    constexpr int BLOCK = kSortBlock;
+    constexpr int RADIX = 1 << RB;
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int TILE = BLOCK * ITEMS;
+    constexpr int DPT = RADIX > BLOCK ? RADIX / BLOCK : 1;  // digits per thread
+
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wcnt[WAVES][RADIX];  // per-wave digit counts, then wave offsets
+    __shared__ uint32_t s_boff[RADIX];         // block exclusive digit offsets
+    __shared__ int64_t s_glob[RADIX];          // global position of LDS slot 0 per digit
+    __shared__ uint32_t s_w[WAVES];
+    __shared__ K s_keys[TILE];
+
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    for (int i = tid; i < WAVES * RADIX; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
+    const uint32_t tile = next_tile(tile_ctr, &s_tile);
+    const int64_t n = dev_count(n_host, d_n);
+    const int64_t base = (int64_t)tile * TILE;
+    if (base >= n) return;  // uniform across the block
+
+    for (int d = tid; d < RADIX; d += BLOCK) look_next[(size_t)tile * RADIX + d] = 0;
+
+    // Load wave-striped: wave w owns [w*64*ITEMS, (w+1)*64*ITEMS), item i of
+    // lane l is element i*64 + l, so (wave, item, lane) order is input order.
+    K keys[ITEMS];
+    uint32_t dig[ITEMS];
+    const int64_t wbase = base + (int64_t)wave * 64 * ITEMS + lane;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        int64_t idx = wbase + i * 64;
+        keys[i] = idx < n ? in[idx] : ~K(0);  // padding sorts last, never written
+        dig[i] = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
+    }
+
+    // Wave-level multisplit: lanes sharing a digit, found with RB ballots.
+    uint32_t rank[ITEMS];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        uint64_t m = ~0ull;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            bool bit = (dig[i] >> b) & 1u;
+            uint64_t bal = ballot64(bit);
+            m &= bit ? bal : ~bal;
+        }
+        uint32_t before = s_wcnt[wave][dig[i]];
+        uint32_t pre = (uint32_t)__popcll(m & lt);
+        rank[i] = before + pre;
+        if (pre == 0) s_wcnt[wave][dig[i]] = before + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+
+    // Per digit: wave offsets and block count.
+    uint32_t cnt[DPT];
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        int d = tid * DPT + j;
+        uint32_t s = 0;
+        if (d < RADIX) {
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                uint32_t c = s_wcnt[w][d];
+                s_wcnt[w][d] = s;
+                s += c;
+            }
+            // publish this tile's digit count for the tiles after it
+            st_agent(&look[(size_t)tile * RADIX + d], (tile == 0 ? kFlagInc : kFlagAgg) | s);
+        }
+        cnt[j] = s;
+        tsum += s;
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_sum<BLOCK>(tsum, s_w, &tot);
+
+    // Decoupled look-back per digit for the count of that digit in all
+    // earlier tiles.
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        int d = tid * DPT + j;
+        if (d < RADIX) {
+            s_boff[d] = ex;
+            uint32_t before = 0;
+            if (tile > 0) {
+                int64_t t = (int64_t)tile - 1;
+                for (;;) {
+                    uint32_t st = ld_agent(&look[(size_t)t * RADIX + d]);
+                    if ((st & ~kValMask) == 0) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    before += st & kValMask;
+                    if (st & kFlagInc) break;
+                    --t;
+                }
+                st_agent(&look[(size_t)tile * RADIX + d], kFlagInc | (before + cnt[j]));
+            }
+            s_glob[d] = (int64_t)digit_base[d] + before - ex;
+            ex += cnt[j];
+        }
+    }
+    __syncthreads();
+
+    // Stage the tile in LDS in (digit, input order) order.
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        uint32_t pos = s_boff[dig[i]] + s_wcnt[wave][dig[i]] + rank[i];
+        s_keys[pos] = keys[i];
+    }
+    __syncthreads();
+
+    // Scatter: consecutive threads write consecutive slots of one bucket.
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        int j = i * BLOCK + tid;
+        K k = s_keys[j];
+        uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1);
+        int64_t g = s_glob[d] + j;
+        if (g >= 0 && g < n) out[g] = k;
+    }
+}
+
+// ------------------------------------------------------------------ host
+struct SortWs {
+    uint32_t *hist = nullptr;   // passes * RADIX
+    uint32_t *look[2] = {nullptr, nullptr};
+    int passes = 0, radix_bits = 8, items = 16;
+    int64_t tiles = 0;
+};
+
+inline void sort_carve(Carve &c, SortWs &w, int64_t n, int key_bits, const SortCfg &cfg) {
+    w.radix_bits = cfg.radix_bits;
+    w.items = cfg.items;
+    w.passes = sort_passes(key_bits, cfg.radix_bits);
+    w.tiles = sort_tiles(n, cfg.items);
+    const size_t radix = (size_t)1 << cfg.radix_bits;
+    w.hist = c.take<uint32_t>((size_t)kMaxPasses * radix);
+    w.look[0] = c.take<uint32_t>((size_t)w.tiles * radix);
+    w.look[1] = c.take<uint32_t>((size_t)w.tiles * radix);
+}
+
+// Bytes that must be zero before the histogram / first pass.
+inline size_t sort_zero_bytes(const SortWs &w) {
+    // hist and look[0] are adjacent in the carve order (256-aligned gap ok)
+    return (size_t)((char *)w.look[1] - (char *)w.hist);
+}
+
+// Digit widths and tile sizes compiled into this library.
+inline bool sort_cfg_supported(const SortCfg &c) {
+    return (c.radix_bits >= 4 && c.radix_bits <= 11) &&
+           (c.items == 8 || c.items == 12 || c.items == 16);
+}
+
+inline size_t hist_lds_bytes(int passes, int rb) { return (size_t)passes * ((size_t)1 << rb) * 4; }
+
+template <typename K, int RB, int ITEMS>
+inline void onesweep_launch(const SortWs &w, const K *src, K *dst, int64_t n_host,
+                            const int64_t *d_n, int pass, uint32_t *tile_ctr, hipStream_t s) {
+    const size_t radix = (size_t)1 << RB;
+    k_onesweep<K, RB, ITEMS><<<(unsigned)w.tiles, kSortBlock, 0, s>>>(
+        src, dst, n_host, d_n, pass * RB, w.hist + (size_t)pass * radix, w.look[pass & 1],
+        w.look[(pass + 1) & 1], tile_ctr + pass);
+}
+
+template <typename K, int RB>
+inline void onesweep_items(const SortWs &w, const K *src, K *dst, int64_t n_host,
+                           const int64_t *d_n, int pass, uint32_t *tile_ctr, hipStream_t s) {
+    switch (w.items) {
+        case 8: onesweep_launch<K, RB, 8>(w, src, dst, n_host, d_n, pass, tile_ctr, s); break;
+        case 12: onesweep_launch<K, RB, 12>(w, src, dst, n_host, d_n, pass, tile_ctr, s); break;
+        default: onesweep_launch<K, RB, 16>(w, src, dst, n_host, d_n, pass, tile_ctr, s); break;
+    }
+}
+
+template <typename K, int RB>
+inline void sort_launch_rb(const SortWs &w, const K *in, K *out, K *alt0, K *alt1,
+                           int64_t n_host, const int64_t *d_n, bool have_hist,
+                           uint32_t *tile_ctr, hipStream_t s) {
+    if (!have_hist) {
+        int64_t blocks = (n_host + kSortBlock * 16 - 1) / (kSortBlock * 16);
+        blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+        k_histogram<K, RB><<<(unsigned)blocks, kSortBlock, hist_lds_bytes(w.passes, RB), s>>>(
+            in, n_host, d_n, w.passes, w.hist);
+    }
+    k_hist_scan<RB><<<(unsigned)w.passes, kSortBlock, 0, s>>>(w.hist);
+    // buffer chain: in -> B1 -> ... -> B(P-1) -> out, intermediates alternate
+    // so that no pass reads the buffer it writes
+    const K *src = in;
+    for (int p = 0; p < w.passes; ++p) {
+        K *dst;
+        if (p == w.passes - 1) dst = out;
+        else dst = ((w.passes - 1 - p) & 1) ? alt0 : alt1;
+        onesweep_items<K, RB>(w, src, dst, n_host, d_n, p, tile_ctr, s);
+        src = dst;
+    }
+}
+
+// Launch the histogram (unless `have_hist`: already accumulated into w.hist),
+// the digit scans and every pass, from `in` to `out` through alt0/alt1.
+// When passes == 1 the single pass goes straight from in to out, so in and
+// out must differ.  tile_ctr: `passes` zeroed counters.  w.hist and
+// w.look[0] must be zero on entry.
+template <typename K>
+inline void sort_launch(const SortWs &w, const K *in, K *out, K *alt0, K *alt1, int64_t n_host,
+                        const int64_t *d_n, bool have_hist, uint32_t *tile_ctr, hipStream_t s) {
+    if (w.passes == 0) return;
+    switch (w.radix_bits) {
+        case 4: sort_launch_rb<K, 4>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+        case 5: sort_launch_rb<K, 5>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+        case 6: sort_launch_rb<K, 6>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+        case 7: sort_launch_rb<K, 7>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+        case 9: sort_launch_rb<K, 9>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+        case 10: sort_launch_rb<K, 10>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+        case 11: sort_launch_rb<K, 11>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+        default: sort_launch_rb<K, 8>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+    }
+}
+
+}  // namespace cga

@@ -1,0 +1,341 @@
+"""GPU parity: every entry point of the HIP library against the CPU oracle,
+bit-exact, on seeded workloads sized to span several tiles with ragged tails,
+plus the edge cases (empty, single, all-equal, depth limits, non-finite,
+capacity, padding)."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gen import Grid
+from helpers import dev, keys_dev, say, u32, u64
+
+pytestmark = pytest.mark.gpu
+M, L = gen.KEY_MORTON, gen.KEY_LINEAR
+
+
+@pytest.fixture(scope="module")
+def w_c1():
+    return gen.c1_spheres()
+
+
+@pytest.fixture(scope="module")
+def w_c2s():
+    # the LiDAR workload at 1/16 of the azimuth steps (65,536 points per sweep)
+    return gen.c2_lidar(naz=1024, nq=20000)
+
+
+@pytest.fixture(scope="module")
+def w_c3s():
+    return gen.c3_bumpy(n=300_000, nq=20000)
+
+
+def _wl(name, request):
+    return request.getfixturevalue(name)
+
+
+# ------------------------------------------------------------------ encode
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s", "w_c3s"])
+@pytest.mark.parametrize("mode", [M, L])
+def test_encode(gpu, wl, mode, request):
+    d = _wl(wl, request)
+    g = d["grid"].with_mode(mode)
+    say("encode", wl, mode)
+    k = gpu.cga_encode_keys(dev(d["a"]), g)
+    want = oracle.encode(oracle.quantize(d["a"], g), g.depth, mode)
+    assert np.array_equal(u64(k), want)
+
+
+def test_encode_edges(gpu):
+    g = Grid((0.0, 0.0, 0.0), 1024.0, 10, M)
+    p = np.array([[1 - 2 ** -24, 0.0, 0.5], [-1e-7, 1.0, 5.0], [-3.0, 1e30, -1e30],
+                  [0.25, 0.5, 0.75]], np.float32)
+    k = gpu.cga_encode_keys(dev(p), g)
+    assert np.array_equal(u64(k), oracle.encode(oracle.quantize(p, g), 10, M))
+    g2 = Grid((2.0 ** -25, 0.0, 0.0), 512.0, 10, L)  # rounding of the subtract decides
+    k = gpu.cga_encode_keys(dev(np.array([[1.0, 0.0, 0.0]], np.float32)), g2)
+    assert int(u64(k)[0]) >> 20 == 512
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite(gpu, bad):
+    g = Grid((0.0, 0.0, 0.0), 16.0, 4, M)
+    p = np.random.default_rng(0).uniform(0, 1, (5000, 3)).astype(np.float32)
+    p[1234, 1] = bad
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_build(dev(p), g)
+    assert e.value.status == gpu.ENONFINITE
+    with pytest.raises(gpu.CgaError):
+        gpu.cga_knn(keys_dev(np.array([1, 2], np.uint64), g), dev(p[1230:1240]), g, 1)
+
+
+# -------------------------------------------------------------------- sort
+@pytest.mark.parametrize("n", [1, 2, 4095, 4096, 4097, 3 * 3072 + 5, 300_001])
+@pytest.mark.parametrize("depth,bits", [(10, 30), (12, 36), (16, 48), (21, 63)])
+def test_sort(gpu, n, depth, bits):
+    rng = np.random.default_rng(n + bits)
+    keys = rng.integers(0, 2 ** bits, n, dtype=np.uint64)
+    keys[: n // 3] = keys[0]  # many equal keys
+    g = Grid((0.0, 0.0, 0.0), 1.0, depth, M)
+    say("sort", n, bits)
+    out = gpu.cga_sort_keys(keys_dev(keys, g), g)
+    assert np.array_equal(u64(out), np.sort(keys))
+
+
+@pytest.mark.parametrize("rb", [4, 5, 6, 7, 8, 9, 10, 11])
+@pytest.mark.parametrize("items", [8, 12, 16])
+def test_sort_every_tuning(gpu, rb, items):
+    rng = np.random.default_rng(rb * 100 + items)
+    keys = rng.integers(0, 2 ** 44, 70_001, dtype=np.uint64)
+    keys[::7] = keys[3]
+    g = Grid((0.0, 0.0, 0.0), 1.0, 15, M)
+    out = gpu.cga_sort_keys(keys_dev(keys, g), g, key_bits=45, tune=(rb, items))
+    assert np.array_equal(u64(out), np.sort(keys))
+    g32 = Grid((0.0, 0.0, 0.0), 1.0, 10, M)
+    k32 = (keys & np.uint64(2 ** 30 - 1))
+    out = gpu.cga_sort_keys(keys_dev(k32, g32), g32, tune=(rb, items))
+    assert np.array_equal(u64(out), np.sort(k32))
+
+
+# ------------------------------------------------------------------- build
+def _check_build(gpu, xyz, g, tune=None):
+    k, c = gpu.cga_build(dev(xyz), g, tune=tune)
+    wk, wc = oracle.build(xyz, g)
+    assert np.array_equal(u64(k), wk)
+    assert np.array_equal(u32(c), wc)
+    return wk
+
+
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s", "w_c3s"])
+@pytest.mark.parametrize("mode", [M, L])
+def test_build(gpu, wl, mode, request):
+    d = _wl(wl, request)
+    say("build", wl, mode)
+    _check_build(gpu, d["a"], d["grid"].with_mode(mode))
+
+
+@pytest.mark.parametrize("tune", [(4, 8), (6, 12), (9, 16), (11, 8)])
+def test_build_tunings_identical(gpu, w_c2s, tune):
+    _check_build(gpu, w_c2s["a"], w_c2s["grid"], tune)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 10, 11, 16, 21])
+def test_build_depths(gpu, depth):
+    rng = np.random.default_rng(depth)
+    xyz = rng.uniform(-0.1, 1.1, (50_000, 3)).astype(np.float32)
+    g = Grid((0.0, 0.0, 0.0), float(np.float32(2.0 ** depth)), depth, M)
+    for mode in (M, L):
+        _check_build(gpu, xyz, g.with_mode(mode))
+
+
+@pytest.mark.parametrize("n", [0, 1, 4095, 4096, 4097])
+def test_build_sizes_and_duplicates(gpu, n):
+    g = Grid((0.0, 0.0, 0.0), 1.0, 6, M)
+    rng = np.random.default_rng(n)
+    _check_build(gpu, rng.integers(0, 64, (n, 3)).astype(np.float32), g)
+    same = np.tile(np.array([[5.0, 9.0, 33.0]], np.float32), (max(n, 1), 1))
+    k, c = gpu.cga_build(dev(same), g)
+    assert len(k) == 1 and int(u32(c)[0]) == len(same)
+
+
+def test_build_capacity(gpu, w_c1):
+    g = w_c1["grid"]
+    _, wc = oracle.build(w_c1["a"], g)
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_build(dev(w_c1["a"]), g, cap=len(wc) - 1)
+    assert e.value.status == gpu.ECAPACITY
+    k, _ = gpu.cga_build(dev(w_c1["a"]), g, cap=len(wc))
+    assert len(k) == len(wc)
+
+
+# ------------------------------------------------------------ paper arrays
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s"])
+def test_to_arrays(gpu, wl, request):
+    d = _wl(wl, request)
+    g = d["grid"].with_mode(L)
+    k, _ = gpu.cga_build(dev(d["a"]), g)
+    arr = gpu.cga_to_arrays(k, g)
+    want = oracle.arrays(u64(k), g.depth, L)
+    for name in ("x_index", "y_index", "z_index"):
+        assert np.array_equal(u32(arr[name]), want[name]), name
+    for name in ("x_pointer", "y_pointer"):
+        assert np.array_equal(arr[name].cpu().numpy(), want[name]), name
+
+
+def test_to_arrays_table2(gpu):
+    import json
+    import os
+    gold = os.path.join(os.path.dirname(__file__), "golden")
+    pts = np.array(json.load(open(os.path.join(gold, "table2_points.json")))["soldier"], np.float32)
+    want = json.load(open(os.path.join(gold, "table2_derived.json")))["soldier_arrays"]
+    g = Grid((0.0, 0.0, 0.0), 1.0, 8, L)
+    k, _ = gpu.cga_build(dev(pts), g)
+    arr = gpu.cga_to_arrays(k, g)
+    for name, v in want.items():
+        got = arr[name].cpu().numpy()
+        got = got.view(np.uint32) if got.dtype == np.int32 else got
+        assert got.tolist() == v, name
+
+
+# ------------------------------------------------------------------- merge
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s", "w_c3s"])
+@pytest.mark.parametrize("mode", [M, L])
+def test_merge(gpu, wl, mode, request):
+    d = _wl(wl, request)
+    g = d["grid"].with_mode(mode)
+    ka, _ = gpu.cga_build(dev(d["a"]), g)
+    kb, _ = gpu.cga_build(dev(d["b"]), g)
+    say("merge", wl, mode, len(ka), len(kb))
+    m, s = gpu.cga_merge(ka, kb, g, src=True)
+    wm, ws = oracle.merge(u64(ka), u64(kb), g.depth, mode)
+    assert np.array_equal(u64(m), wm)
+    assert np.array_equal(s.cpu().numpy(), ws)
+
+
+def test_merge_edges(gpu):
+    g = Grid((0.0, 0.0, 0.0), 1.0, 12, M)
+    rng = np.random.default_rng(9)
+    a = np.unique(rng.integers(0, 2 ** 36, 20_000, dtype=np.uint64))
+    b = np.unique(np.concatenate([a[::3], rng.integers(0, 2 ** 36, 9_000, dtype=np.uint64)]))
+    cases = [(a, b), (b, a), (a, a), (a, a[:0]), (a[:0], b), (a[:0], a[:0]), (a[:1], a[1:2]),
+             (a[:2048], a[2048:4096]), (a[::2], a[1::2])]
+    for x, y in cases:
+        m, s = gpu.cga_merge(keys_dev(x, g), keys_dev(y, g), g, src=True)
+        wm, ws = oracle.merge(x, y, 12, M)
+        assert np.array_equal(u64(m), wm)
+        assert np.array_equal(s.cpu().numpy(), ws)
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_merge(keys_dev(a, g), keys_dev(b, g), g, cap=len(np.union1d(a, b)) - 1)
+    assert e.value.status == gpu.ECAPACITY
+
+
+# -------------------------------------------------------------- projection
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s", "w_c3s"])
+@pytest.mark.parametrize("mode", [M, L])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_project(gpu, wl, mode, axis, request):
+    d = _wl(wl, request)
+    g = d["grid"].with_mode(mode)
+    k, _ = gpu.cga_build(dev(d["a"]), g)
+    say("project", wl, mode, axis)
+    p, c = gpu.cga_project(k, g, axis)
+    wp, wc = oracle.project(u64(k), g.depth, mode, axis)
+    assert np.array_equal(u64(p), wp)
+    assert np.array_equal(u32(c), wc)
+
+
+def test_project_depth_limits(gpu):
+    rng = np.random.default_rng(17)
+    for depth in (16, 17, 21):  # 2-D keys switch to 64 bits above depth 16
+        g = Grid((0.0, 0.0, 0.0), float(2 ** depth), depth, M)
+        xyz = rng.uniform(0, 1, (40_000, 3)).astype(np.float32)
+        for mode in (M, L):
+            gm = g.with_mode(mode)
+            k, _ = gpu.cga_build(dev(xyz), gm)
+            for axis in (0, 1, 2):
+                p, c = gpu.cga_project(k, gm, axis)
+                wp, wc = oracle.project(u64(k), depth, mode, axis)
+                assert np.array_equal(u64(p), wp) and np.array_equal(u32(c), wc)
+
+
+# --------------------------------------------------------------------- kNN
+def _check_knn(gpu, keys_gpu, q, g, k, tier="kd"):
+    idx, d2 = gpu.cga_knn(keys_gpu, dev(q), g, k)
+    keys = u64(keys_gpu)
+    fn = oracle.knn_kdtree if tier == "kd" else oracle.knn_brute
+    widx, wd2 = fn(keys, q, g, k)
+    assert np.array_equal(d2.cpu().numpy().view(np.uint64), wd2)
+    assert np.array_equal(idx.cpu().numpy(), widx)
+
+
+def test_knn_c1(gpu, w_c1):
+    g = w_c1["grid"]
+    ka, _ = gpu.cga_build(dev(w_c1["a"]), g)
+    kb, _ = gpu.cga_build(dev(w_c1["b"]), g)
+    m, _ = gpu.cga_merge(ka, kb, g)
+    _check_knn(gpu, m, w_c1["q"], g, 1, tier="brute")
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, 16, 32])
+def test_knn_c2s(gpu, w_c2s, k):
+    g = w_c2s["grid"]
+    ka, _ = gpu.cga_build(dev(w_c2s["a"]), g)
+    say("knn c2s", k)
+    _check_knn(gpu, ka, w_c2s["q"], g, k)
+
+
+@pytest.mark.parametrize("k", [1, 16])
+def test_knn_c3s(gpu, w_c3s, k):
+    g = w_c3s["grid"]
+    ka, _ = gpu.cga_build(dev(w_c3s["a"]), g)
+    _check_knn(gpu, ka, w_c3s["q"], g, k)
+
+
+def test_knn_edges(gpu):
+    rng = np.random.default_rng(21)
+    g = Grid((0.0, 0.0, 0.0), 1.0, 5, M)  # tiny grid: many exact ties
+    pts = rng.integers(0, 32, (300, 3)).astype(np.float32)
+    k_, _ = gpu.cga_build(dev(pts), g)
+    q = np.concatenate([pts[:50], rng.integers(-3, 35, (200, 3)).astype(np.float32)])
+    for k in (1, 2, 5, 8, 13, 32):
+        _check_knn(gpu, k_, q, g, k, tier="brute")
+    few = k_[:3]  # fewer voxels than k: padding
+    _check_knn(gpu, few, q[:20], g, 8, tier="brute")
+    empty = k_[:0]
+    idx, d2 = gpu.cga_knn(empty, dev(q[:4]), g, 2)
+    assert (idx.cpu().numpy() == -1).all()
+    g21 = Grid((0.0, 0.0, 0.0), float(2 ** 21), 21, M)
+    xyz = rng.uniform(0, 1, (20_000, 3)).astype(np.float32)
+    k21, _ = gpu.cga_build(dev(xyz), g21)
+    _check_knn(gpu, k21, rng.uniform(0, 1, (500, 3)).astype(np.float32), g21, 4)
+
+
+def test_knn_linear_unsupported(gpu, w_c1):
+    g = w_c1["grid"].with_mode(L)
+    k, _ = gpu.cga_build(dev(w_c1["a"]), g)
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_knn(k, dev(w_c1["q"]), g, 1)
+    assert e.value.status == gpu.EUNSUPPORTED
+
+
+# ------------------------------------------------------------------ lookup
+def test_binary_lookup(gpu):
+    rng = np.random.default_rng(33)
+    keys = np.unique(rng.integers(0, 2 ** 48, 500_000, dtype=np.uint64))
+    q = np.concatenate([keys[rng.integers(0, len(keys), 100_000)],
+                        rng.integers(0, 2 ** 48, 100_000, dtype=np.uint64),
+                        np.array([0, 2 ** 64 - 1, keys[0], keys[-1]], np.uint64)])
+    r, f = gpu.cga_binary_lookup(dev(keys.view(np.int64)), dev(q.view(np.int64)))
+    wr, wf = oracle.lower_bound(keys, q)
+    assert np.array_equal(r.cpu().numpy(), wr) and np.array_equal(f.cpu().numpy(), wf)
+    r, f = gpu.cga_binary_lookup(dev(keys[:0].view(np.int64)), dev(q[:10].view(np.int64)))
+    assert (r.cpu().numpy() == 0).all() and (f.cpu().numpy() == 0).all()
+
+
+# ------------------------------------------------- device-resident pipeline
+def test_device_count_pipeline_and_repeat(gpu, w_c2s):
+    """build -> merge -> project -> kNN with every size left on the device (no
+    host sync between calls) equals the synchronous path, twice in a row."""
+    d = w_c2s
+    g = d["grid"]
+    a, b, q = dev(d["a"]), dev(d["b"]), dev(d["q"])
+    ref_m, _ = gpu.cga_merge(gpu.cga_build(a, g)[0], gpu.cga_build(b, g)[0], g)
+    ref_p, ref_c = gpu.cga_project(ref_m, g, 2)
+    ref_i, ref_d = gpu.cga_knn(ref_m, q, g, 8)
+    for _ in range(2):
+        ws = [gpu.Workspaces() for _ in range(5)]
+        cnt = torch.zeros(4, dtype=torch.int64, device="cuda")
+        ka, _, _ = gpu.cga_build(a, g, d_n_out=cnt[0:1], sync=False, ws=ws[0])
+        kb, _, _ = gpu.cga_build(b, g, d_n_out=cnt[1:2], sync=False, ws=ws[1])
+        m, _, _ = gpu.cga_merge(ka, kb, g, d_na=cnt[0:1], d_nb=cnt[1:2], d_n_out=cnt[2:3],
+                                sync=False, ws=ws[2])
+        p, c, _ = gpu.cga_project(m, g, 2, n=len(a) + len(b), d_n=cnt[2:3], d_n_out=cnt[3:4],
+                                  sync=False, ws=ws[3])
+        i, dd = gpu.cga_knn(m, q, g, 8, n=len(a) + len(b), d_n=cnt[2:3], ws=ws[4])
+        torch.cuda.synchronize()
+        n = cnt.cpu().numpy()
+        assert n[2] == len(ref_m) and n[3] == len(ref_p)
+        assert torch.equal(m[: n[2]], ref_m) and torch.equal(p[: n[3]], ref_p)
+        assert torch.equal(c[: n[3]], ref_c)
+        assert torch.equal(i, ref_i) and torch.equal(dd, ref_d)
