@@ -176,6 +176,19 @@ int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n,
                       const uint64_t *d_q, int64_t nq, int64_t *d_rank, uint8_t *d_found,
                       cga_stream stream);
 
+/* ---------------------------------------------------------------- timing
+ * Per-kernel launch timing for measurement.  After cga_prof_enable, each
+ * launch of a kernel whose label is in the comma-separated `filter` (NULL or
+ * "" = every kernel) is bracketed by two HIP events on the launch's own
+ * stream.  cga_prof_read waits for all pending events and returns the summed
+ * duration and launch count of one label since the last reset.  Labels:
+ * begin, encode, histogram, hist_scan, onesweep, rle, arrays,
+ * merge_partition, merge, rekey, knn, binary_lookup.  Not for graph capture. */
+int cga_prof_enable(const char *filter);
+int cga_prof_disable(void);
+int cga_prof_reset(void);
+int cga_prof_read(const char *label, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -85,6 +85,10 @@ _sig("cga_project", ctypes.c_int, _GP, _P, _I64, _P, ctypes.c_int, _P, _P, _I64,
 _sig("cga_knn_workspace_bytes", _SZ, _GP, _I64, _I64)
 _sig("cga_knn", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, ctypes.c_int, _P, _P, _P, _SZ, _P)
 _sig("cga_binary_lookup", ctypes.c_int, _P, _I64, _P, _P, _I64, _P, _P, _P)
+_sig("cga_prof_enable", ctypes.c_int, ctypes.c_char_p)
+_sig("cga_prof_disable", ctypes.c_int)
+_sig("cga_prof_reset", ctypes.c_int)
+_sig("cga_prof_read", ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), _I64P)
 
 
 # ------------------------------------------------------------------ helpers
@@ -311,3 +315,25 @@ def cga_binary_lookup(keys: torch.Tensor, q: torch.Tensor, *, n=None, d_n=None, 
     _check(lib.cga_binary_lookup(_ptr(keys), n, _ptr(d_n), _ptr(q), nq, _ptr(rank), _ptr(found),
                                  _stream(stream)), "cga_binary_lookup")
     return rank, found
+
+
+# ------------------------------------------------------------------ timing
+def cga_prof_enable(labels=None):
+    """Bracket launches of the given kernel labels (None = all) with events."""
+    f = ",".join(labels) if labels else None
+    _check(lib.cga_prof_enable(f.encode() if f else None), "cga_prof_enable")
+
+
+def cga_prof_disable():
+    lib.cga_prof_disable()
+
+
+def cga_prof_reset():
+    _check(lib.cga_prof_reset(), "cga_prof_reset")
+
+
+def cga_prof_read(label: str):
+    """(total milliseconds, launches) of one kernel label since the reset."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib.cga_prof_read(label.encode(), ctypes.byref(ms), ctypes.byref(n)), "cga_prof_read")
+    return ms.value, n.value

@@ -52,6 +52,7 @@ int launch_begin(Control *ctl, void *z0, size_t z0_bytes, void *z1, size_t z1_by
     size_t blocks = (m + 255) / 256;
     blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
     ZeroPtrs zp{{d_n_out, zero2, zero3, zero4}};
+    CGA_PROF("begin", s);
     k_begin<<<(unsigned)blocks, 256, 0, s>>>((uint32_t *)ctl, (uint4 *)z0, n0, (uint4 *)z1, n1, zp);
     CGA_HIP(hipGetLastError());
     return CGA_OK;
@@ -126,6 +127,7 @@ static void encode_launch(const cga_grid *g, const float *xyz, int64_t n, K *key
                           uint32_t *hist, uint32_t *err, hipStream_t s) {
     int64_t blocks = (n + 256 * 8 - 1) / (256 * 8);
     blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+    CGA_PROF("encode", s);
     k_encode<K, RB><<<(unsigned)blocks, 256, hist_lds_bytes(passes, RB), s>>>(
         xyz, n, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth,
         g->key_mode == CGA_KEY_LINEAR, keys, passes, hist, err);
@@ -188,6 +190,7 @@ static void build_enqueue(const cga_grid *g, const float *xyz, int64_t n, K *key
     const SortWs &w = L.sort;
     encode_dispatch<K>(g, xyz, n, a, w.radix_bits, w.passes, w.hist, &L.ctl->err, s);
     K *fin = sort_chain<K>(w, a, b, n, nullptr, true, L.ctl->tile_ctr, s);
+    CGA_PROF("rle", s);
     k_rle<K, K, false><<<(unsigned)rle_tiles(n), kRleBlock, 0, s>>>(
         fin, n, nullptr, 0, ~0ull, keys, counts, nullptr, cap, n_out, L.rle_status,
         &L.ctl->tile_ctr[kMaxPasses], &L.ctl->err);
@@ -246,6 +249,7 @@ static void arrays_enqueue(const cga_grid *g, const K *keys, int64_t n, const in
     const uint64_t m = (1ull << d) - 1;
     K *xy = (K *)L.xy;
     const unsigned tiles = (unsigned)rle_tiles(n);
+    CGA_PROF("arrays", s);
     k_rle<K, K, true><<<tiles, kRleBlock, 0, s>>>(keys, n, d_n, d, ~0ull, xy, nullptr, yp, n, nxy,
                                                    L.st_xy, &L.ctl->tile_ctr[0], &L.ctl->err);
     k_rle<K, uint32_t, true><<<tiles, kRleBlock, 0, s>>>(xy, n, nxy, d, m, xi, nullptr, xp, n, nx,

@@ -72,6 +72,19 @@ int launch_begin(Control *ctl, void *z0, size_t z0_bytes, void *z1, size_t z1_by
 // Synchronise and translate the control block's error bits.
 int finish_sync(const Control *ctl, hipStream_t s);
 
+// Optional per-kernel timing.  When enabled (cga_prof_enable), a launch
+// whose label matches the filter is bracketed by HIP events recorded on the
+// launch's own stream; cga_prof_read waits for them and sums the durations.
+struct ProfScope {
+    int slot = -1;
+    hipStream_t stream = nullptr;
+    ProfScope(const char *label, hipStream_t s);
+    ~ProfScope();
+};
+#define CGA_PROF_CAT2(a, b) a##b
+#define CGA_PROF_CAT(a, b) CGA_PROF_CAT2(a, b)
+#define CGA_PROF(label, s) ::cga::ProfScope CGA_PROF_CAT(prof_scope_, __LINE__)(label, s)
+
 // ---------------------------------------------------------------- device
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

@@ -2,24 +2,39 @@
 // unique MORTON key array, and plain binary-search point lookup.
 //
 // Morton keys make every octree cell a contiguous key range: cell (prefix,
-// L) holds exactly the keys in [prefix << 3L, (prefix + 1) << 3L).  A query
-// (one thread each) first takes the keys around its own key's insertion point
-// as candidates, which bounds the k-th squared distance by some D.  Every
-// better point then lies in the box of half-width floor(sqrt(D)) around the
-// query, which at most 2 x 2 x 2 cells of the smallest level whose cell edge
-// covers the box contain.  Each such cell is walked in key order as an
-// implicit octree without a stack: a cell whose nearest point is farther
-// than the current k-th distance is skipped (strictly farther, so ties
-// survive), a cell with at most kScan keys is scanned exactly, any other is
-// split into its eight children.  The key array position of the next cell
-// is found by galloping search from the current one.  Candidates are kept in
-// registers ordered by (squared distance, key); key order is array order.
+// L) holds exactly the keys in [prefix << 3L, (prefix + 1) << 3L).  One thread
+// answers one query:
+//  1. Binary-search the query's own key, then gallop outward from that
+//     position to get the key range of every cell that contains the query,
+//     from the voxel (level 0) up to the root -- O(log n) probes in total, all
+//     near one place in the array.
+//  2. Scan the query's voxel, then for each containing cell from the bottom
+//     up visit its other seven children nearest-first (the child on the
+//     query's side first, then those across one, two, three faces).  Inside a
+//     visited child the same nearest-first order recurses without a stack:
+//     the order of a child among its siblings follows from its own index bits
+//     and the query's, and the key range of each open ancestor is kept per
+//     level in LDS.  A cell whose nearest point is farther than the current
+//     k-th distance is skipped (strictly farther, so ties survive); a cell
+//     with at most a threshold number of keys is scanned exactly.
+//  3. Stop climbing as soon as every point outside the finished cell is
+//     farther than the current k-th distance.
+// Candidates are kept in registers ordered by (squared distance, key); key
+// order is array order.
+#include <cstdlib>
+
 #include "cga_common.h"
+#include "cga_sort.h"
 
 namespace cga {
 
 constexpr int kKnnBlock = 256;
-constexpr int kScan = 16;  // scan a cell outright when it holds at most this many keys
+constexpr int kScanDefault = 32;  // scan a cell outright when it holds at most this many keys
+// Queries are answered in the order of the top kOrderBits of their own keys,
+// so that the lanes of a wave walk neighbouring cells (sorted by index with
+// the onesweep sort when there are at least kOrderMin queries).
+constexpr int kOrderBits = 24;
+constexpr int64_t kOrderMin = 4096;
 
 struct Cand {
     uint64_t d;
@@ -30,8 +45,8 @@ __device__ __forceinline__ bool cand_lt(uint64_t d, int32_t i, const Cand &c) {
     return d < c.d || (d == c.d && i < c.i);
 }
 
-// Ascending list of KT candidates, the last KT - k of which are the answer;
-// the first slots hold (0, -1) sentinels that no real candidate precedes.
+// Ascending list of KT candidates, the last k of which are the answer; the
+// first KT - k slots hold (0, -1) sentinels that no real candidate precedes.
 template <int KT>
 __device__ __forceinline__ void cand_insert(Cand (&e)[KT], uint64_t d, int32_t i) {
     if (!cand_lt(d, i, e[KT - 1])) return;
@@ -58,28 +73,60 @@ __device__ __forceinline__ int64_t lower_bound_dev(const K *keys, int64_t n, K q
     return lo + (keys[lo] < q ? 1 : 0);
 }
 
-// First index >= lo whose key is >= t, given keys[lo - 1] < t.
+// First index in [lo, hi) whose key is >= t (hi if none).
 template <typename K>
-__device__ __forceinline__ int64_t gallop(const K *keys, int64_t n, int64_t lo, K t) {
-    if (lo >= n || keys[lo] >= t) return lo;
-    int64_t prev = lo, step = 1, hi;
+__device__ __forceinline__ int32_t lower_bound_in(const K *keys, int32_t lo, int32_t hi, uint64_t t) {
+    while (lo < hi) {
+        int32_t mid = (int32_t)(((uint32_t)lo + (uint32_t)hi) >> 1);
+        if ((uint64_t)keys[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// First index >= lo whose key is >= t, given every key before lo is < t.
+template <typename K>
+__device__ __forceinline__ int64_t gallop_up(const K *keys, int64_t n, int64_t lo, uint64_t t) {
+    if (lo >= n || (uint64_t)keys[lo] >= t) return lo;
+    int64_t bad = lo, step = 1, good = n;  // keys[bad] < t, keys[good] >= t (or good == n)
     for (;;) {
-        int64_t nx = prev + step;
-        if (nx >= n) {
-            hi = n;
+        int64_t nx = bad + step;
+        if (nx >= n) break;
+        if ((uint64_t)keys[nx] >= t) {
+            good = nx;
             break;
         }
-        if (keys[nx] >= t) {
-            hi = nx;
-            break;
-        }
-        prev = nx;
+        bad = nx;
         step <<= 1;
     }
-    int64_t a = prev + 1, b = hi;  // answer in [a, b]
+    int64_t a = bad + 1, b = good;
     while (a < b) {
         int64_t mid = (a + b) >> 1;
-        if (keys[mid] < t) a = mid + 1;
+        if ((uint64_t)keys[mid] < t) a = mid + 1;
+        else b = mid;
+    }
+    return a;
+}
+
+// First index whose key is >= t, given every key from hi on is >= t.
+template <typename K>
+__device__ __forceinline__ int64_t gallop_down(const K *keys, int64_t hi, uint64_t t) {
+    if (hi <= 0 || (uint64_t)keys[hi - 1] < t) return hi;
+    int64_t good = hi - 1, step = 1, bad = -1;  // keys[good] >= t, keys[bad] < t (or -1)
+    for (;;) {
+        int64_t nx = good - step;
+        if (nx < 0) break;
+        if ((uint64_t)keys[nx] < t) {
+            bad = nx;
+            break;
+        }
+        good = nx;
+        step <<= 1;
+    }
+    int64_t a = bad + 1, b = good;
+    while (a < b) {
+        int64_t mid = (a + b) >> 1;
+        if ((uint64_t)keys[mid] < t) a = mid + 1;
         else b = mid;
     }
     return a;
@@ -94,27 +141,34 @@ __device__ __forceinline__ uint64_t axis_gap(uint32_t q, uint32_t lo, uint32_t h
     return q < lo ? (uint64_t)(lo - q) : (q > hi ? (uint64_t)(q - hi) : 0ull);
 }
 
-__device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
-    uint64_t r = (uint64_t)sqrt((double)v);
-    while (r * r > v) --r;
-    while ((r + 1) * (r + 1) <= v) ++r;
-    return (uint32_t)r;
-}
+// Visiting order of the 8 children: by the number of axes on which the child
+// lies across from the query (0, 1, 1, 1, 2, 2, 2, 3).  Self-inverse.
+__device__ __forceinline__ uint32_t near_order(uint32_t s) { return s == 3 ? 4u : (s == 4 ? 3u : s); }
 
 template <typename K, int KT>
 __global__ __launch_bounds__(kKnnBlock) void k_knn(const K *__restrict__ keys, int64_t n_host,
                                                    const int64_t *d_n, const float *__restrict__ q,
                                                    int64_t nq, float o0, float o1, float o2,
                                                    float scale, uint32_t depth, int k,
+                                                   int scan_max,
+                                                   const uint64_t *__restrict__ order,
                                                    int64_t *__restrict__ idx_out,
                                                    uint64_t *__restrict__ d2_out, uint32_t *err) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nq) return;
+    // key range [lo, hi) of the open cell at each level, one column per thread
+    extern __shared__ int32_t s_rng[];
+    int32_t *LO = s_rng + threadIdx.x;
+    int32_t *HI = s_rng + (depth + 1) * kKnnBlock + threadIdx.x;
+#define RLO(l) LO[(l) * kKnnBlock]
+#define RHI(l) HI[(l) * kKnnBlock]
+
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nq) return;
+    const int64_t j = order ? (int64_t)(order[t] >> kOrderBits) : t;
     const int64_t n = dev_count(n_host, d_n);
     const float o[3] = {o0, o1, o2};
     Vox qv;
     if (!quantize3(q[3 * j], q[3 * j + 1], q[3 * j + 2], o, scale, depth, qv)) {
-        set_err(err, ERR_NONFINITE);
+        if (!order) set_err(err, ERR_NONFINITE);  // else reported by the ordering pass
         for (int s = 0; s < k; ++s) {
             idx_out[j * k + s] = -1;
             d2_out[j * k + s] = ~0ull;
@@ -126,87 +180,113 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(const K *__restrict__ keys, i
 #pragma unroll
     for (int s = 0; s < KT; ++s) e[s] = s < KT - k ? Cand{0, -1} : Cand{~0ull, 0x7FFFFFFF};
 
-    // seed: keys around the query's own insertion point
-    const K qkey = (K)enc3(qv.x, qv.y, qv.z, depth, false);
-    const int64_t p = lower_bound_dev(keys, n, qkey);
-    const int64_t w = k > 4 ? k : 4;
-    const int64_t seed_lo = p > w ? p - w : 0, seed_hi = p + w < n ? p + w : n;
-    for (int64_t i = seed_lo; i < seed_hi; ++i) {
-        Vox v = dec3(keys[i], depth, false);
-        cand_insert<KT>(e, sq_dist(v, qv.x, qv.y, qv.z), (int32_t)i);
-    }
+    const uint64_t qkey = enc3(qv.x, qv.y, qv.z, depth, false);
+    // query's octant bits below each level: child index of the cell holding q
+    auto qo = [&](int l) -> uint32_t {
+        return (((qv.x >> l) & 1u) << 2) | (((qv.y >> l) & 1u) << 1) | ((qv.z >> l) & 1u);
+    };
 
-    // start level: cells at least as wide as the box that can still hold a
-    // better point
-    const uint32_t top = (1u << depth) - 1;
-    int ls = (int)depth;
-    uint32_t r = 0;
-    if (e[KT - 1].d != ~0ull) {
-        r = isqrt64(e[KT - 1].d);
-        if (r < top) {
-            ls = 0;
-            while (ls < (int)depth && ((1u << ls) < 2 * r + 1)) ++ls;
-        }
-    }
-    uint32_t clo[3], chi[3];
+    // 1. range of the query's own voxel; the ranges of larger cells that
+    // contain the query are galloped out from it as the climb needs them
+    int64_t glo, ghi;
     {
-        const uint32_t qc[3] = {qv.x, qv.y, qv.z};
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            uint32_t lo = qc[a] > r ? qc[a] - r : 0;
-            uint32_t hi = (uint64_t)qc[a] + r < top ? qc[a] + r : top;
-            clo[a] = lo >> ls;
-            chi[a] = hi >> ls;
-        }
+        const int64_t p = lower_bound_dev(keys, n, (K)qkey);
+        glo = gallop_down(keys, p, qkey);
+        ghi = gallop_up(keys, n, p, qkey + 1);
+        RLO(0) = (int32_t)glo;
+        RHI(0) = (int32_t)ghi;
     }
 
-    for (uint32_t cx = clo[0]; cx <= chi[0]; ++cx)
-        for (uint32_t cy = clo[1]; cy <= chi[1]; ++cy)
-            for (uint32_t cz = clo[2]; cz <= chi[2]; ++cz) {
-                // walk the subtree of cell (cx, cy, cz) at level ls in key order
-                uint64_t prefix = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
-                int L = ls;
-                int64_t cur = -1;  // lower bound position of the current cell, once known
-                for (;;) {
-                    bool visit = true;
-                    {
-                        const uint32_t bx = compact3(prefix >> 2) << L, by = compact3(prefix >> 1) << L,
-                                       bz = compact3(prefix) << L;
-                        const uint32_t ext = (1u << L) - 1;
-                        const uint64_t gx = axis_gap(qv.x, bx, bx + ext), gy = axis_gap(qv.y, by, by + ext),
-                                       gz = axis_gap(qv.z, bz, bz + ext);
-                        if (gx * gx + gy * gy + gz * gz > e[KT - 1].d) visit = false;
-                    }
-                    if (visit) {
-                        const int sh = 3 * L;
-                        const K ks = (K)(prefix << sh);
-                        // exclusive end; at most 2^63 since 3 * depth <= 63
-                        const uint64_t ke64 = (prefix + 1) << sh;
-                        cur = cur < 0 ? lower_bound_dev(keys, n, ks) : gallop(keys, n, cur, ks);
-                        auto in_cell = [&](int64_t i) {
-                            return i < n && (uint64_t)keys[i] < ke64;
-                        };
-                        if (in_cell(cur)) {
-                            if (L > 0 && in_cell(cur + kScan)) {
-                                prefix <<= 3;
-                                --L;
-                                continue;
-                            }
-                            for (; in_cell(cur); ++cur) {
-                                if (cur >= seed_lo && cur < seed_hi) continue;
-                                Vox v = dec3(keys[cur], depth, false);
-                                cand_insert<KT>(e, sq_dist(v, qv.x, qv.y, qv.z), (int32_t)cur);
-                            }
+    auto scan = [&](int32_t lo, int32_t hi) {
+        for (int32_t i = lo; i < hi; ++i) {
+            Vox v = dec3(keys[i], depth, false);
+            cand_insert<KT>(e, sq_dist(v, qv.x, qv.y, qv.z), i);
+        }
+    };
+    auto pruned = [&](uint64_t prefix, int l) {
+        const uint32_t bx = compact3(prefix >> 2) << l, by = compact3(prefix >> 1) << l,
+                       bz = compact3(prefix) << l;
+        const uint32_t ext = (1u << l) - 1;
+        const uint64_t gx = axis_gap(qv.x, bx, bx + ext), gy = axis_gap(qv.y, by, by + ext),
+                       gz = axis_gap(qv.z, bz, bz + ext);
+        return gx * gx + gy * gy + gz * gz > e[KT - 1].d;
+    };
+
+    // 2. the query's voxel, then the other children of each containing cell
+    scan(RLO(0), RHI(0));
+    for (int lp = 1; lp <= (int)depth; ++lp) {
+        // 3. every point outside the finished cell (level lp - 1) is at least
+        // this far along some axis
+        {
+            const int lc = lp - 1;
+            const uint32_t c[3] = {qv.x, qv.y, qv.z};
+            uint64_t m = ~0ull;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t b = (c[a] >> lc) << lc;
+                const uint64_t below = (uint64_t)(c[a] - b) + 1, above = (uint64_t)b + (1u << lc) - c[a];
+                const bool has_below = b > 0, has_above = (uint64_t)b + (1u << lc) <= ((1ull << depth) - 1);
+                if (has_below && below < m) m = below;
+                if (has_above && above < m) m = above;
+            }
+            if (m == ~0ull || (e[KT - 1].d != ~0ull && m * m > e[KT - 1].d)) break;
+        }
+        {
+            const uint64_t cs = (qkey >> (3 * lp)) << (3 * lp);
+            const uint64_t ce = cs + (1ull << (3 * lp));
+            glo = gallop_down(keys, glo, cs);
+            ghi = gallop_up(keys, n, ghi, ce);
+            RLO(lp) = (int32_t)glo;
+            RHI(lp) = (int32_t)ghi;
+        }
+        if (RHI(lp) - RLO(lp) == RHI(lp - 1) - RLO(lp - 1)) continue;  // no other keys here
+        const uint64_t parent = qkey >> (3 * lp);
+        const uint32_t qc = qo(lp - 1);
+        for (uint32_t sidx = 1; sidx < 8; ++sidx) {
+            // walk the subtree of sibling `sidx` (level lr = lp - 1) nearest-first
+            const int lr = lp - 1;
+            uint64_t prefix = (parent << 3) | (near_order(sidx) ^ qc);
+            int l = lr;
+            for (;;) {
+                if (!pruned(prefix, l)) {
+                    const int sh = 3 * l;
+                    const uint64_t cs = prefix << sh, ce = (prefix + 1) << sh;
+                    const int32_t lo = lower_bound_in(keys, RLO(l + 1), RHI(l + 1), cs);
+                    const int32_t hi = lower_bound_in(keys, lo, RHI(l + 1), ce);
+                    if (hi > lo) {
+                        if (l == 0 || hi - lo <= scan_max) {
+                            scan(lo, hi);
+                        } else {
+                            RLO(l) = lo;
+                            RHI(l) = hi;
+                            prefix = (prefix << 3) | qo(l - 1);  // first child: the query's side
+                            --l;
+                            continue;
                         }
                     }
-                    while (L < ls && (prefix & 7) == 7) {
-                        prefix >>= 3;
-                        ++L;
-                    }
-                    if (L == ls) break;
-                    ++prefix;
                 }
+                // next cell: following sibling in nearest-first order, climbing
+                // out of finished parents, until the subtree root is done
+                bool done = false;
+                for (;;) {
+                    if (l == lr) {
+                        done = true;
+                        break;
+                    }
+                    const uint32_t so = near_order((uint32_t)(prefix & 7) ^ qo(l));
+                    if (so < 7) {
+                        prefix = (prefix & ~7ull) | (near_order(so + 1) ^ qo(l));
+                        break;
+                    }
+                    prefix >>= 3;
+                    ++l;
+                }
+                if (done) break;
             }
+        }
+    }
+#undef RLO
+#undef RHI
 
 #pragma unroll
     for (int s = 0; s < KT; ++s) {
@@ -219,25 +299,98 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(const K *__restrict__ keys, i
     }
 }
 
+// Query ordering key: query index above the top kOrderBits of its Morton key,
+// with the digit histogram of the 8-bit sort passes over those bits.
+__global__ __launch_bounds__(256) void k_knn_order(const float *__restrict__ q, int64_t nq, float o0,
+                                                   float o1, float o2, float scale,
+                                                   uint32_t depth, uint64_t *__restrict__ out,
+                                                   uint32_t *hist, uint32_t *err) {
+    constexpr int RB = 8, PASSES = kOrderBits / RB;
+    __shared__ uint32_t s_h[PASSES << RB];
+    __shared__ int s_bad;
+    for (int i = threadIdx.x; i < (PASSES << RB); i += blockDim.x) s_h[i] = 0;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    const float o[3] = {o0, o1, o2};
+    const int drop = 3 * (int)depth > kOrderBits ? 3 * (int)depth - kOrderBits : 0;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        Vox v;
+        bad |= !quantize3(q[3 * i], q[3 * i + 1], q[3 * i + 2], o, scale, depth, v);
+        const uint64_t top = enc3(v.x, v.y, v.z, depth, false) >> drop;
+        const uint64_t packed = ((uint64_t)i << kOrderBits) | top;
+        out[i] = packed;
+        hist_add<RB>(s_h, packed, PASSES);
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+    hist_flush<RB>(s_h, hist, PASSES);
+    if (threadIdx.x == 0 && s_bad) set_err(err, ERR_NONFINITE);
+}
+
+// Launch knobs (never change results): CGA_KNN_SCAN = scan threshold,
+// CGA_KNN_ORDER = 1 to answer queries in the order of their Morton keys
+// (measured slower here: it gathers the costliest queries into the same waves).
+struct KnnKnobs {
+    int scan = kScanDefault;
+    bool order = false;
+};
+static KnnKnobs knn_knobs() {
+    KnnKnobs k;
+    if (const char *e = getenv("CGA_KNN_SCAN")) {
+        int v = atoi(e);
+        if (v >= 1 && v <= 4096) k.scan = v;
+    }
+    if (const char *e = getenv("CGA_KNN_ORDER")) k.order = atoi(e) != 0;
+    return k;
+}
+
+struct KnnLayout {
+    Control *ctl;
+    SortWs sort;
+    uint64_t *a, *b;
+    size_t bytes;
+};
+
+static KnnLayout knn_layout(void *ws, int64_t nq) {
+    KnnLayout L;
+    Carve c(ws);
+    L.ctl = c.take<Control>(1);
+    L.a = L.b = nullptr;
+    if (nq >= kOrderMin && knn_knobs().order) {
+        SortCfg cfg;
+        cfg.radix_bits = 8;
+        cfg.items = 16;
+        sort_carve(c, L.sort, nq, kOrderBits, cfg);
+        L.a = c.take<uint64_t>((size_t)nq);
+        L.b = c.take<uint64_t>((size_t)nq);
+    }
+    L.bytes = c.size();
+    return L;
+}
+
 template <typename K, int KT>
 static void knn_launch(const cga_grid *g, const K *keys, int64_t n, const int64_t *d_n,
-                       const float *q, int64_t nq, int k, int64_t *idx, uint64_t *d2, uint32_t *err,
-                       hipStream_t s) {
-    k_knn<K, KT><<<(unsigned)((nq + kKnnBlock - 1) / kKnnBlock), kKnnBlock, 0, s>>>(
-        keys, n, d_n, q, nq, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth, k, idx,
-        d2, err);
+                       const float *q, int64_t nq, int k, const uint64_t *order, int64_t *idx,
+                       uint64_t *d2, uint32_t *err, hipStream_t s) {
+    CGA_PROF("knn", s);
+    const size_t lds = (size_t)(g->depth + 1) * kKnnBlock * 2 * sizeof(int32_t);
+    k_knn<K, KT><<<(unsigned)((nq + kKnnBlock - 1) / kKnnBlock), kKnnBlock, lds, s>>>(
+        keys, n, d_n, q, nq, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth, k,
+        knn_knobs().scan, order, idx, d2, err);
 }
 
 template <typename K>
 static void knn_dispatch(const cga_grid *g, const K *keys, int64_t n, const int64_t *d_n,
-                         const float *q, int64_t nq, int k, int64_t *idx, uint64_t *d2,
-                         uint32_t *err, hipStream_t s) {
-    if (k <= 1) knn_launch<K, 1>(g, keys, n, d_n, q, nq, k, idx, d2, err, s);
-    else if (k <= 2) knn_launch<K, 2>(g, keys, n, d_n, q, nq, k, idx, d2, err, s);
-    else if (k <= 4) knn_launch<K, 4>(g, keys, n, d_n, q, nq, k, idx, d2, err, s);
-    else if (k <= 8) knn_launch<K, 8>(g, keys, n, d_n, q, nq, k, idx, d2, err, s);
-    else if (k <= 16) knn_launch<K, 16>(g, keys, n, d_n, q, nq, k, idx, d2, err, s);
-    else knn_launch<K, 32>(g, keys, n, d_n, q, nq, k, idx, d2, err, s);
+                         const float *q, int64_t nq, int k, const uint64_t *order, int64_t *idx,
+                         uint64_t *d2, uint32_t *err, hipStream_t s) {
+    if (k <= 1) knn_launch<K, 1>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
+    else if (k <= 2) knn_launch<K, 2>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
+    else if (k <= 4) knn_launch<K, 4>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
+    else if (k <= 8) knn_launch<K, 8>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
+    else if (k <= 16) knn_launch<K, 16>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
+    else knn_launch<K, 32>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
 }
 
 // ---------------------------------------------------------- binary lookup
@@ -263,7 +416,7 @@ extern "C" {
 
 size_t cga_knn_workspace_bytes(const cga_grid *g, int64_t n, int64_t nq) {
     if (!grid_valid(g) || n < 0 || nq < 0) return 0;
-    return kControlBytes;
+    return knn_layout(nullptr, nq).bytes;
 }
 
 int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n, const float *d_q,
@@ -274,17 +427,35 @@ int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n
     if (n > 0 && !d_keys) return CGA_EINVAL;
     if (g->key_mode != CGA_KEY_MORTON) return CGA_EUNSUPPORTED;
     if (n >= ((int64_t)1 << 31) - 1) return CGA_EUNSUPPORTED;
-    if (ws_bytes < kControlBytes) return CGA_EWORKSPACE;
+    if (nq >= ((int64_t)1 << (64 - kOrderBits))) return CGA_EUNSUPPORTED;
+    KnnLayout L = knn_layout(d_ws, nq);
+    if (ws_bytes < L.bytes) return CGA_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    Control *ctl = (Control *)d_ws;
-    CGA_TRY(launch_begin(ctl, nullptr, 0, nullptr, 0, nullptr, s));
+    Control *ctl = L.ctl;
+    const bool ordered = L.a != nullptr;
+    CGA_TRY(launch_begin(ctl, ordered ? L.sort.hist : nullptr, ordered ? sort_zero_bytes(L.sort) : 0,
+                         nullptr, 0, nullptr, s));
     if (nq > 0) {
+        const uint64_t *order = nullptr;
+        if (ordered) {
+            int64_t blocks = (nq + 256 * 8 - 1) / (256 * 8);
+            blocks = blocks > 1024 ? 1024 : blocks;
+            {
+                CGA_PROF("knn_order", s);
+                k_knn_order<<<(unsigned)blocks, 256, 0, s>>>(d_q, nq, g->origin[0], g->origin[1],
+                                                              g->origin[2], g->scale, g->depth, L.a,
+                                                              L.sort.hist, &ctl->err);
+            }
+            // 3 passes: a -> b -> a -> b
+            sort_launch<uint64_t>(L.sort, L.a, L.b, L.a, L.b, nq, nullptr, true, ctl->tile_ctr, s);
+            order = L.b;
+        }
         if (wide_keys(g->depth))
-            knn_dispatch<uint64_t>(g, (const uint64_t *)d_keys, n, d_n, d_q, nq, k, d_idx, d_d2,
-                                   &ctl->err, s);
+            knn_dispatch<uint64_t>(g, (const uint64_t *)d_keys, n, d_n, d_q, nq, k, order, d_idx,
+                                   d_d2, &ctl->err, s);
         else
-            knn_dispatch<uint32_t>(g, (const uint32_t *)d_keys, n, d_n, d_q, nq, k, d_idx, d_d2,
-                                   &ctl->err, s);
+            knn_dispatch<uint32_t>(g, (const uint32_t *)d_keys, n, d_n, d_q, nq, k, order, d_idx,
+                                   d_d2, &ctl->err, s);
         CGA_HIP(hipGetLastError());
     }
     return CGA_OK;
@@ -296,6 +467,7 @@ int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n, con
     if ((n > 0 && !d_keys) || (nq > 0 && (!d_q || !d_rank))) return CGA_EINVAL;
     if (nq == 0) return CGA_OK;
     hipStream_t s = (hipStream_t)stream;
+    CGA_PROF("binary_lookup", s);
     k_binary_lookup<<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(d_keys, n, d_n, d_q, nq, d_rank,
                                                                 d_found);
     CGA_HIP(hipGetLastError());

@@ -195,8 +195,12 @@ static void merge_enqueue(const K *a, int64_t na, const int64_t *d_na, const K *
                           const MergeLayout &L, hipStream_t s) {
     const int64_t tiles = merge_tiles(na + nb);
     const int64_t nparts = tiles + 1;
+    {
+    CGA_PROF("merge_partition", s);
     k_merge_partition<K><<<(unsigned)((nparts + 255) / 256), 256, 0, s>>>(a, na, d_na, b, nb, d_nb,
                                                                           L.part, nparts);
+    }
+    CGA_PROF("merge", s);
     k_merge<K><<<(unsigned)tiles, kMergeBlock, 0, s>>>(a, na, d_na, b, nb, d_nb, L.part, out, src,
                                                        cap, n_out, L.status, &L.ctl->tile_ctr[0],
                                                        &L.ctl->err);

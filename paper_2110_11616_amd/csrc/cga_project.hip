@@ -38,6 +38,7 @@ static void rekey_launch(const K *in, int64_t n, const int64_t *d_n, const cga_g
                          K2 *out, int passes, uint32_t *hist, hipStream_t s) {
     int64_t blocks = (n + 256 * 8 - 1) / (256 * 8);
     blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+    CGA_PROF("rekey", s);
     k_rekey<K, K2, RB><<<(unsigned)blocks, 256, hist_lds_bytes(passes, RB), s>>>(
         in, n, d_n, g->depth, g->key_mode == CGA_KEY_LINEAR, drop, out, passes, hist);
 }
@@ -85,6 +86,7 @@ static void project_enqueue(const cga_grid *g, const K *keys, int64_t n, const i
     const uint32_t d = g->depth;
     if (g->key_mode == CGA_KEY_LINEAR && drop == 2) {
         // (x<<2d | y<<d | z) >> d = x<<d | y: already ascending, just collapse
+        CGA_PROF("rle", s);
         k_rle<K, K2, false><<<(unsigned)rle_tiles(n), kRleBlock, 0, s>>>(
             keys, n, d_n, (int)d, ~0ull, out, counts, nullptr, cap, n_out, L.rle_status,
             &L.ctl->tile_ctr[kMaxPasses], &L.ctl->err);
@@ -96,6 +98,7 @@ static void project_enqueue(const cga_grid *g, const K *keys, int64_t n, const i
     K2 *fin = (w.passes & 1) ? b : a;
     K2 *other = (w.passes & 1) ? a : b;
     sort_launch<K2>(w, a, fin, other, fin, n, d_n, true, L.ctl->tile_ctr, s);
+    CGA_PROF("rle", s);
     k_rle<K2, K2, false><<<(unsigned)rle_tiles(n), kRleBlock, 0, s>>>(
         fin, n, d_n, 0, ~0ull, out, counts, nullptr, cap, n_out, L.rle_status,
         &L.ctl->tile_ctr[kMaxPasses], &L.ctl->err);

@@ -261,6 +261,7 @@ template <typename K, int RB, int ITEMS>
 inline void onesweep_launch(const SortWs &w, const K *src, K *dst, int64_t n_host,
                             const int64_t *d_n, int pass, uint32_t *tile_ctr, hipStream_t s) {
     const size_t radix = (size_t)1 << RB;
+    CGA_PROF("onesweep", s);
     k_onesweep<K, RB, ITEMS><<<(unsigned)w.tiles, kSortBlock, 0, s>>>(
         src, dst, n_host, d_n, pass * RB, w.hist + (size_t)pass * radix, w.look[pass & 1],
         w.look[(pass + 1) & 1], tile_ctr + pass);
@@ -283,10 +284,14 @@ inline void sort_launch_rb(const SortWs &w, const K *in, K *out, K *alt0, K *alt
     if (!have_hist) {
         int64_t blocks = (n_host + kSortBlock * 16 - 1) / (kSortBlock * 16);
         blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+        CGA_PROF("histogram", s);
         k_histogram<K, RB><<<(unsigned)blocks, kSortBlock, hist_lds_bytes(w.passes, RB), s>>>(
             in, n_host, d_n, w.passes, w.hist);
     }
-    k_hist_scan<RB><<<(unsigned)w.passes, kSortBlock, 0, s>>>(w.hist);
+    {
+        CGA_PROF("hist_scan", s);
+        k_hist_scan<RB><<<(unsigned)w.passes, kSortBlock, 0, s>>>(w.hist);
+    }
     // buffer chain: in -> B1 -> ... -> B(P-1) -> out, intermediates alternate
     // so that no pass reads the buffer it writes
     const K *src = in;
