@@ -176,6 +176,67 @@ int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n,
                       const uint64_t *d_q, int64_t nq, int64_t *d_rank, uint8_t *d_found,
                       cga_stream stream);
 
+/* ---------------------------------------------------------- learned index
+ * A learned index over one sorted unique uint64 key array (point location
+ * and range start, the lookups that dominate CGA-based compression, Table
+ * III), whose results are always exactly those of cga_binary_lookup.
+ *
+ * Model (two stages, fitted to the array's own key -> rank function):
+ *  root:  x = fl32(key - kmin) * inv_span (clamped to the key range) and
+ *         leaf = clamp(floor(y(x)), 0, n_leaves - 1) with y monotone, so
+ *         that leaf j owns a contiguous rank range [first_j, first_j + n_j).
+ *         root_segments = 0: y = fmaf(a, x, b), a > 0, with a, b by least
+ *         squares (fp64 sums) of rank * n_leaves / n on x.
+ *         root_segments = R > 0: y is the piecewise-linear interpolant of
+ *         (x, rank * n_leaves / n) through the keys at the R + 1 rank
+ *         quantiles, clamped inside each segment (monotone by construction);
+ *         the segment is found by binary search over the R + 1 knot inputs.
+ *  leaf:  x_j = fl32(key - key_first_j) * inv_span_j, prediction
+ *         p = clamp(first_j + rintf(n_j * f_j(x_j)), first_j, first_j + n_j)
+ *         with f_j linear (least squares, fp64 sums) or a 1-16-1 ReLU network
+ *         f(x) = sum_h w2_h relu(w1_h x + b1_h) + b2 (49 float32 parameters),
+ *         initialised to the piecewise-linear interpolant of the leaf's
+ *         rank function at its 16 rank quantiles and then trained by
+ *         full-batch Adam on mean squared error for `epochs` epochs.
+ *  window: err_lo_j / err_hi_j = min / max of (rank - p) over the leaf's keys.
+ * Lookup: route, predict, take [lo, hi] = p + [err_lo, err_hi] clamped to
+ * the leaf, verify (lo == 0 || keys[lo-1] < q) && (hi == n || keys[hi] >= q),
+ * then search inside [lo, hi]; a failed check (an absent key the window does
+ * not cover) falls back to a full binary search, counted in d_fallbacks.
+ * The index is one caller-owned, position-independent device buffer of
+ * cga_index_bytes; it records n, kmin, kmax and a key fingerprint, and a
+ * lookup against a different key array reports CGA_EMISMATCH. */
+typedef struct {
+    uint32_t n_leaves;      /* 1 .. 65536 (4096 typical) */
+    uint32_t leaf_kind;     /* 0 = linear, 1 = 1-16-1 ReLU network */
+    uint32_t epochs;        /* network leaves: Adam epochs (0 = keep the initialisation) */
+    float lr;               /* network leaves: Adam step size */
+    uint32_t root_segments; /* 0 = one linear root model; else 1 .. 65536 segments */
+} cga_index_params;
+
+size_t cga_index_bytes(const cga_index_params *params);
+size_t cga_index_train_workspace_bytes(const cga_index_params *params, int64_t n);
+int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *params,
+                    void *d_index, size_t index_bytes, void *d_ws, size_t ws_bytes,
+                    cga_stream stream);
+/* d_rank: int64 lower bound per query; d_found (nullable): uint8 membership;
+ * d_fallbacks (nullable): uint64 counter, incremented per fallback (the
+ * caller zeroes it).  d_ws: at least cga_index_lookup_workspace_bytes. */
+size_t cga_index_lookup_workspace_bytes(void);
+int cga_index_lookup(const void *d_index, const uint64_t *d_keys, int64_t n, const uint64_t *d_q,
+                     int64_t nq, int64_t *d_rank, uint8_t *d_found, uint64_t *d_fallbacks,
+                     void *d_ws, size_t ws_bytes, cga_stream stream);
+/* Per-leaf window widths (err_hi - err_lo + 1, int32, n_leaves entries) and
+ * key counts (int64) of a trained index, for reporting. */
+int cga_index_stats(const void *d_index, int32_t *d_width, int64_t *d_count, cga_stream stream);
+/* Full-batch loss and gradient of one 1-16-1 ReLU leaf network on n samples
+ * (x, t), computed by the same device code the training uses: d_params (49
+ * float32: w1[16], b1[16], w2[16], b2), d_grad (49 float64), d_loss (1
+ * float64).  Mean squared error, (1/n) sum (f(x_i) - t_i)^2.  Exposed so the
+ * gradients can be checked against an independent fp64 computation. */
+int cga_mlp_loss_grad(const float *d_params, const float *d_x, const float *d_t, int64_t n,
+                      double *d_grad, double *d_loss, cga_stream stream);
+
 /* ---------------------------------------------------------------- timing
  * Per-kernel launch timing for measurement.  After cga_prof_enable, each
  * launch of a kernel whose label is in the comma-separated `filter` (NULL or

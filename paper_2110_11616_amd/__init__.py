@@ -85,6 +85,22 @@ _sig("cga_project", ctypes.c_int, _GP, _P, _I64, _P, ctypes.c_int, _P, _P, _I64,
 _sig("cga_knn_workspace_bytes", _SZ, _GP, _I64, _I64)
 _sig("cga_knn", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, ctypes.c_int, _P, _P, _P, _SZ, _P)
 _sig("cga_binary_lookup", ctypes.c_int, _P, _I64, _P, _P, _I64, _P, _P, _P)
+
+
+class cga_index_params(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_uint32), ("leaf_kind", ctypes.c_uint32),
+                ("epochs", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("root_segments", ctypes.c_uint32)]
+
+
+_IPP = ctypes.POINTER(cga_index_params)
+_sig("cga_index_bytes", _SZ, _IPP)
+_sig("cga_index_train_workspace_bytes", _SZ, _IPP, _I64)
+_sig("cga_index_train", ctypes.c_int, _P, _I64, _IPP, _P, _SZ, _P, _SZ, _P)
+_sig("cga_index_lookup_workspace_bytes", _SZ)
+_sig("cga_index_lookup", ctypes.c_int, _P, _P, _I64, _P, _I64, _P, _P, _P, _P, _SZ, _P)
+_sig("cga_index_stats", ctypes.c_int, _P, _P, _P, _P)
+_sig("cga_mlp_loss_grad", ctypes.c_int, _P, _P, _P, _I64, _P, _P, _P)
 _sig("cga_prof_enable", ctypes.c_int, ctypes.c_char_p)
 _sig("cga_prof_disable", ctypes.c_int)
 _sig("cga_prof_reset", ctypes.c_int)
@@ -315,6 +331,73 @@ def cga_binary_lookup(keys: torch.Tensor, q: torch.Tensor, *, n=None, d_n=None, 
     _check(lib.cga_binary_lookup(_ptr(keys), n, _ptr(d_n), _ptr(q), nq, _ptr(rank), _ptr(found),
                                  _stream(stream)), "cga_binary_lookup")
     return rank, found
+
+
+# ----------------------------------------------------------- learned index
+LEAF_LINEAR = 0
+LEAF_MLP = 1
+
+
+def index_params(n_leaves=4096, leaf_kind=LEAF_MLP, epochs=50, lr=1e-4,
+                 root_segments=1024) -> cga_index_params:
+    p = cga_index_params()
+    p.n_leaves, p.leaf_kind, p.epochs, p.lr = int(n_leaves), int(leaf_kind), int(epochs), float(lr)
+    p.root_segments = int(root_segments)
+    return p
+
+
+def cga_index_train(keys: torch.Tensor, n=None, *, n_leaves=4096, leaf_kind=LEAF_MLP, epochs=50,
+                    lr=1e-4, root_segments=1024, out=None, ws=None, stream=None) -> torch.Tensor:
+    """Train the learned index of a sorted unique uint64 key array (int64
+    tensor of bit patterns).  Returns the index buffer (uint8 tensor)."""
+    n = keys.shape[0] if n is None else int(n)
+    p = index_params(n_leaves, leaf_kind, epochs, lr, root_segments)
+    nb = lib.cga_index_bytes(ctypes.byref(p))
+    if nb == 0:
+        raise CgaError(EINVAL, "cga_index_train")
+    idx = out if out is not None else torch.empty(nb, dtype=torch.uint8, device=keys.device)
+    wsb = _ws("index_train", lib.cga_index_train_workspace_bytes(ctypes.byref(p), n), ws)
+    _check(lib.cga_index_train(_ptr(keys), n, ctypes.byref(p), _ptr(idx), idx.numel(), _ptr(wsb),
+                               wsb.numel(), _stream(stream)), "cga_index_train")
+    return idx
+
+
+def cga_index_lookup(index: torch.Tensor, keys: torch.Tensor, q: torch.Tensor, *, n=None,
+                     rank_out=None, found_out=None, fallbacks_out=None, sync: bool = True,
+                     ws=None, stream=None):
+    """Learned lookup: (rank int64, found uint8, fallbacks) -- fallbacks is an
+    int when sync, else the device counter tensor."""
+    n = keys.shape[0] if n is None else int(n)
+    nq = q.shape[0]
+    dev = q.device
+    rank = rank_out if rank_out is not None else torch.empty(nq, dtype=torch.int64, device=dev)
+    found = found_out if found_out is not None else torch.empty(nq, dtype=torch.uint8, device=dev)
+    fb = fallbacks_out if fallbacks_out is not None else torch.zeros(1, dtype=torch.int64, device=dev)
+    wsb = _ws("index_lookup", lib.cga_index_lookup_workspace_bytes(), ws)
+    _check(lib.cga_index_lookup(_ptr(index), _ptr(keys), n, _ptr(q), nq, _ptr(rank), _ptr(found),
+                                _ptr(fb), _ptr(wsb), wsb.numel(), _stream(stream)),
+           "cga_index_lookup")
+    if sync:
+        _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_index_lookup")
+        return rank, found, int(fb.item())
+    return rank, found, fb
+
+
+def cga_index_stats(index: torch.Tensor, n_leaves: int, stream=None):
+    """Per-leaf (window width, key count) of a trained index."""
+    w = torch.empty(n_leaves, dtype=torch.int32, device=index.device)
+    c = torch.empty(n_leaves, dtype=torch.int64, device=index.device)
+    _check(lib.cga_index_stats(_ptr(index), _ptr(w), _ptr(c), _stream(stream)), "cga_index_stats")
+    return w, c
+
+
+def cga_mlp_loss_grad(params: torch.Tensor, x: torch.Tensor, t: torch.Tensor, stream=None):
+    """(loss, gradient[49]) of one leaf network, as the training computes them."""
+    g = torch.empty(49, dtype=torch.float64, device=params.device)
+    loss = torch.empty(1, dtype=torch.float64, device=params.device)
+    _check(lib.cga_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss),
+                                 _stream(stream)), "cga_mlp_loss_grad")
+    return float(loss.item()), g
 
 
 # ------------------------------------------------------------------ timing

@@ -24,6 +24,7 @@ bool grid_valid(const cga_grid *g) {
 int status_from_bits(uint32_t bits) {
     if (bits & ERR_NONFINITE) return CGA_ENONFINITE;
     if (bits & ERR_CAPACITY) return CGA_ECAPACITY;
+    if (bits & ERR_MISMATCH) return CGA_EMISMATCH;
     return CGA_OK;
 }
 

@@ -50,7 +50,7 @@ inline bool wide_keys(uint32_t depth) { return 3 * depth > 32; }
 inline bool wide_keys2(uint32_t depth) { return 2 * depth > 32; }
 
 // Error bits recorded by kernels in the workspace status word.
-enum : uint32_t { ERR_NONFINITE = 1u, ERR_CAPACITY = 2u };
+enum : uint32_t { ERR_NONFINITE = 1u, ERR_CAPACITY = 2u, ERR_MISMATCH = 4u };
 int status_from_bits(uint32_t bits);
 
 // Control block at the start of every workspace.

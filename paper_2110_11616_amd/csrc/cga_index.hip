@@ -1,0 +1,634 @@
+// Learned index over a sorted unique uint64 key array: a two-stage model of
+// the key -> rank function (fp32 root linear router, per-leaf linear or
+// 1-16-1 ReLU network), per-leaf max-error windows, and a verified
+// last-mile lookup with binary-search fallback, so that every result equals
+// the plain lower bound.  Trained on the GPU by the kernels below: fp64 sums
+// for the least-squares fits, a full-batch forward/backward pass plus Adam
+// per network leaf (one workgroup per leaf, fixed reduction order, so
+// training is deterministic).
+//
+// Every float expression that decides a rank is written with explicit
+// round-to-nearest intrinsics (fmaf, __fmul_rn, ...), so window building and
+// lookups evaluate bit-identical predictions.
+#include "cga_common.h"
+
+namespace cga {
+
+constexpr uint32_t kIndexMagic = 0x49414743u;  // "CGAI"
+constexpr uint32_t kIndexVersion = 1;
+constexpr int kMlpHidden = 16;
+constexpr int kMlpParams = 3 * kMlpHidden + 1;  // w1[16], b1[16], w2[16], b2
+constexpr int kLeafBlock = 256;
+constexpr int kLeafCache = 8192;  // leaf inputs kept in LDS (floats)
+
+struct IndexHeader {
+    uint32_t magic, version, n_leaves, leaf_kind;
+    int64_t n;
+    uint64_t kmin, kmax;
+    float root_a, root_b, inv_span;
+    uint32_t nparams;
+    uint32_t root_segs;
+};
+static_assert(sizeof(IndexHeader) <= 256, "index header");
+
+// Offsets of the root knots and per-leaf arrays after the 256-byte header.
+struct IndexView {
+    IndexHeader *h;
+    float *rx, *ry, *rs;  // root knot inputs, outputs (R + 1 each), slopes (R)
+    int64_t *first;    // n_leaves + 1
+    uint64_t *kfirst;  // first key of each leaf
+    float *isp;        // 1 / (last key - first key) of each leaf, or 0
+    int32_t *err_lo, *err_hi;
+    float *params;     // n_leaves x nparams
+};
+
+__host__ __device__ inline size_t idx_align(size_t v) { return (v + 255) / 256 * 256; }
+
+__host__ __device__ inline size_t index_layout(char *base, uint32_t L, uint32_t nparams,
+                                               uint32_t R, IndexView *v) {
+    size_t off = 256;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off = idx_align(off + bytes);
+        return p;
+    };
+    IndexView w;
+    w.h = (IndexHeader *)base;
+    w.rx = (float *)take(R ? ((size_t)R + 1) * 4 : 0);
+    w.ry = (float *)take(R ? ((size_t)R + 1) * 4 : 0);
+    w.rs = (float *)take((size_t)R * 4);
+    w.first = (int64_t *)take(((size_t)L + 1) * 8);
+    w.kfirst = (uint64_t *)take((size_t)L * 8);
+    w.isp = (float *)take((size_t)L * 4);
+    w.err_lo = (int32_t *)take((size_t)L * 4);
+    w.err_hi = (int32_t *)take((size_t)L * 4);
+    w.params = (float *)take((size_t)L * nparams * 4);
+    if (v) *v = w;
+    return off;
+}
+
+// ------------------------------------------------------------- model maths
+// Root input: the key's offset in the array's key range, scaled to [0, 1].
+__device__ __forceinline__ float root_x(uint64_t q, uint64_t kmin, uint64_t kmax, float isp) {
+    const uint64_t c = q <= kmin ? 0ull : (q >= kmax ? kmax - kmin : q - kmin);
+    return __fmul_rn((float)c, isp);
+}
+
+// Root routing; monotone in q.  Piecewise-linear roots evaluate segment s
+// (the last knot with input <= x) clamped to its end values, so adjacent
+// segments cannot overlap after rounding.
+__device__ __forceinline__ uint32_t route(const IndexHeader &h, const IndexView &v, uint64_t q) {
+    const float x = root_x(q, h.kmin, h.kmax, h.inv_span);
+    float y;
+    if (h.root_segs == 0) {
+        y = fmaf(h.root_a, x, h.root_b);
+    } else {
+        uint32_t lo = 0, hi = h.root_segs;  // knots 0..R; find last rx[s] <= x, s < R
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (v.rx[mid] <= x) lo = mid;
+            else hi = mid;
+        }
+        const float y0 = v.ry[lo], y1 = v.ry[lo + 1];
+        y = fmaf(v.rs[lo], __fsub_rn(x, v.rx[lo]), y0);
+        y = y >= y0 ? (y <= y1 ? y : y1) : y0;
+    }
+    y = floorf(y);
+    const float top = (float)(h.n_leaves - 1);
+    const float c = y >= 0.0f ? (y <= top ? y : top) : 0.0f;  // NaN -> 0
+    return (uint32_t)c;
+}
+
+__device__ __forceinline__ float mlp_forward(const float *p, float x) {
+    float f = p[3 * kMlpHidden];
+#pragma unroll
+    for (int h = 0; h < kMlpHidden; ++h) {
+        const float z = fmaf(p[h], x, p[kMlpHidden + h]);
+        f = fmaf(p[2 * kMlpHidden + h], fmaxf(z, 0.0f), f);
+    }
+    return f;
+}
+
+// Predicted rank of q in leaf j, in [first_j, first_j + n_j].
+__device__ __forceinline__ int64_t leaf_predict(const IndexView &v, uint32_t kind, uint32_t np,
+                                                uint32_t j, uint64_t q, int64_t n) {
+    int64_t f0 = v.first[j], f1 = v.first[j + 1];
+    f0 = f0 < 0 ? 0 : (f0 > n ? n : f0);
+    f1 = f1 < f0 ? f0 : (f1 > n ? n : f1);
+    const int64_t nj = f1 - f0;
+    const uint64_t kf = v.kfirst[j];
+    const float x = q <= kf ? 0.0f : __fmul_rn((float)(q - kf), v.isp[j]);
+    const float *p = v.params + (size_t)j * np;
+    const float f = kind == 0 ? fmaf(p[0], x, p[1]) : mlp_forward(p, x);
+    float r = rintf(__fmul_rn((float)nj, f));
+    r = r >= 0.0f ? r : 0.0f;  // NaN -> 0
+    const float fnj = (float)nj;
+    r = r <= fnj ? r : fnj;
+    int64_t ri = (int64_t)r;
+    ri = ri > nj ? nj : ri;
+    return f0 + ri;
+}
+
+// Sum one sample's loss and gradient into g (w1, b1, w2, b2 order); the
+// loss is accumulated unscaled as r^2 and the gradient as 2 r df/dp.
+__device__ __forceinline__ void mlp_accumulate(const float *p, float x, float t, float *g,
+                                               float &loss) {
+    float z[kMlpHidden], a[kMlpHidden];
+    float f = p[3 * kMlpHidden];
+#pragma unroll
+    for (int h = 0; h < kMlpHidden; ++h) {
+        z[h] = fmaf(p[h], x, p[kMlpHidden + h]);
+        a[h] = fmaxf(z[h], 0.0f);
+        f = fmaf(p[2 * kMlpHidden + h], a[h], f);
+    }
+    const float r = __fsub_rn(f, t);
+    loss = fmaf(r, r, loss);
+    const float dr = __fmul_rn(2.0f, r);
+#pragma unroll
+    for (int h = 0; h < kMlpHidden; ++h) {
+        g[2 * kMlpHidden + h] = fmaf(dr, a[h], g[2 * kMlpHidden + h]);
+        const float dz = z[h] > 0.0f ? __fmul_rn(dr, p[2 * kMlpHidden + h]) : 0.0f;
+        g[h] = fmaf(dz, x, g[h]);
+        g[kMlpHidden + h] = __fadd_rn(g[kMlpHidden + h], dz);
+    }
+    g[3 * kMlpHidden] = __fadd_rn(g[3 * kMlpHidden], dr);
+}
+
+// Deterministic block sum of `cnt` per-thread float partials into doubles:
+// wave sums by shuffles in a fixed pattern, then the waves in order.
+template <int CNT>
+__device__ __forceinline__ void block_sum49(float *v, double *out, float *s_w /* WAVES x CNT */) {
+    constexpr int WAVES = kLeafBlock / 64;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < CNT; ++c) {
+        float x = v[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x = __fadd_rn(x, __shfl_xor(x, o, 64));
+        if (lane == 0) s_w[wave * CNT + c] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < CNT) {
+        double s = 0.0;
+        for (int w = 0; w < WAVES; ++w) s += (double)s_w[w * CNT + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------- kernels
+__global__ void k_index_header(const uint64_t *keys, int64_t n, uint32_t L, uint32_t kind,
+                               uint32_t np, uint32_t R, IndexHeader *h) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    h->root_segs = R;
+    h->magic = kIndexMagic;
+    h->version = kIndexVersion;
+    h->n_leaves = L;
+    h->leaf_kind = kind;
+    h->nparams = np;
+    h->n = n;
+    h->kmin = n > 0 ? keys[0] : 0;
+    h->kmax = n > 0 ? keys[n - 1] : 0;
+    const uint64_t span = h->kmax - h->kmin;
+    h->inv_span = span ? __fdiv_rn(1.0f, (float)span) : 0.0f;
+    h->root_a = (float)L;  // provisional (k_root_final overwrites)
+    h->root_b = 0.0f;
+}
+
+// Partial least-squares sums of y = rank * L / n on x (fp64).
+__global__ __launch_bounds__(256) void k_root_partial(const uint64_t *__restrict__ keys, int64_t n,
+                                                      const IndexHeader *h, double *partial) {
+    __shared__ double s[4][256];
+    const uint64_t kmin = h->kmin, kmax = h->kmax;
+    const float isp = h->inv_span;
+    const double scale = (double)h->n_leaves / (double)n;
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = (double)root_x(keys[i], kmin, kmax, isp);
+        const double y = (double)i * scale;
+        sx += x;
+        sy += y;
+        sxx += x * x;
+        sxy += x * y;
+    }
+    s[0][threadIdx.x] = sx;
+    s[1][threadIdx.x] = sy;
+    s[2][threadIdx.x] = sxx;
+    s[3][threadIdx.x] = sxy;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_root_final(const double *partial, int blocks, int64_t n, IndexHeader *h) {
+    if (threadIdx.x != 0) return;
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    for (int b = 0; b < blocks; ++b) {
+        sx += partial[4 * b];
+        sy += partial[4 * b + 1];
+        sxx += partial[4 * b + 2];
+        sxy += partial[4 * b + 3];
+    }
+    const double dn = (double)n;
+    const double den = dn * sxx - sx * sx;
+    double a = den != 0.0 ? (dn * sxy - sx * sy) / den : 0.0;
+    double b = (sy - a * sx) / dn;
+    float af = (float)a, bf = (float)b;
+    if (!(af > 0.0f) || !isfinite(af) || !isfinite(bf)) {
+        af = (float)h->n_leaves;  // degenerate fit: split the key range evenly
+        bf = 0.0f;
+    }
+    h->root_a = af;
+    h->root_b = bf;
+}
+
+// Piecewise-linear root: knots at ranks t * (n - 1) / R.
+__global__ void k_root_knots(const uint64_t *__restrict__ keys, int64_t n, char *index) {
+    const IndexHeader &h = *(const IndexHeader *)index;
+    IndexView v;
+    index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
+    const uint32_t R = h.root_segs;
+    const float fl = (float)h.n_leaves, fn = (float)n;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= R; t += gridDim.x * blockDim.x) {
+        const int64_t r = (int64_t)(((uint64_t)t * (uint64_t)(n - 1)) / R);
+        v.rx[t] = root_x(keys[r], h.kmin, h.kmax, h.inv_span);
+        v.ry[t] = __fdiv_rn(__fmul_rn((float)r, fl), fn);
+    }
+}
+
+__global__ void k_root_slopes(char *index) {
+    const IndexHeader &h = *(const IndexHeader *)index;
+    IndexView v;
+    index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < h.root_segs;
+         t += gridDim.x * blockDim.x) {
+        const float dx = __fsub_rn(v.rx[t + 1], v.rx[t]);
+        v.rs[t] = dx > 0.0f ? __fdiv_rn(__fsub_rn(v.ry[t + 1], v.ry[t]), dx) : 0.0f;
+    }
+}
+
+// first[j] = first rank routed to leaf >= j (routing is monotone).
+__global__ __launch_bounds__(256) void k_leaf_bounds(const uint64_t *__restrict__ keys, int64_t n,
+                                                     char *index) {
+    IndexView v;
+    const IndexHeader &h = *(const IndexHeader *)index;
+    index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
+    const uint32_t L = h.n_leaves;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lj = route(h, v, keys[i]);
+        const int64_t lp = i > 0 ? (int64_t)route(h, v, keys[i - 1]) : -1;
+        for (int64_t j = lp + 1; j <= lj; ++j) v.first[j] = i;
+        if (i == n - 1)
+            for (int64_t j = lj + 1; j <= (int64_t)L; ++j) v.first[j] = n;
+    }
+    if (n == 0 && blockIdx.x == 0)
+        for (int64_t j = threadIdx.x; j <= (int64_t)L; j += blockDim.x) v.first[j] = 0;
+}
+
+// One workgroup per leaf: fit the leaf model and reset its window.
+template <int KIND>
+__global__ __launch_bounds__(kLeafBlock) void k_leaf_fit(const uint64_t *__restrict__ keys,
+                                                         char *index, uint32_t epochs, float lr) {
+    __shared__ float s_x[kLeafCache];
+    __shared__ float s_p[kMlpParams], s_m[kMlpParams], s_v[kMlpParams];
+    __shared__ double s_g[kMlpParams + 1];
+    __shared__ float s_w[(kLeafBlock / 64) * (kMlpParams + 1)];
+    __shared__ double s_lin[4][kLeafBlock];
+
+    IndexView v;
+    const IndexHeader &h = *(const IndexHeader *)index;
+    index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
+    const uint32_t j = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t f0 = v.first[j], f1 = v.first[j + 1], nj = f1 - f0;
+    float *par = v.params + (size_t)j * h.nparams;
+    if (nj <= 0) {
+        if (tid == 0) {
+            v.kfirst[j] = 0;
+            v.isp[j] = 0.0f;
+            v.err_lo[j] = 0;
+            v.err_hi[j] = 0;
+        }
+        for (uint32_t c = tid; c < h.nparams; c += blockDim.x) par[c] = 0.0f;
+        return;
+    }
+    const uint64_t kf = keys[f0];
+    const uint64_t span = keys[f1 - 1] - kf;
+    const float isp = span ? __fdiv_rn(1.0f, (float)span) : 0.0f;
+    const float fnj = (float)nj;
+    auto xof = [&](int64_t s) -> float {
+        return s < kLeafCache ? s_x[s] : __fmul_rn((float)(keys[f0 + s] - kf), isp);
+    };
+    for (int64_t s = tid; s < nj && s < kLeafCache; s += blockDim.x)
+        s_x[s] = __fmul_rn((float)(keys[f0 + s] - kf), isp);
+    if (tid == 0) {
+        v.kfirst[j] = kf;
+        v.isp[j] = isp;
+        v.err_lo[j] = 0x7FFFFFFF;
+        v.err_hi[j] = (int32_t)0x80000000;
+    }
+    __syncthreads();
+
+    if (KIND == 0) {
+        // least squares of t = s / n_j on x (fp64 sums)
+        double sx = 0, st = 0, sxx = 0, sxt = 0;
+        for (int64_t s = tid; s < nj; s += blockDim.x) {
+            const double x = (double)xof(s), t = (double)s / (double)nj;
+            sx += x;
+            st += t;
+            sxx += x * x;
+            sxt += x * t;
+        }
+        s_lin[0][tid] = sx;
+        s_lin[1][tid] = st;
+        s_lin[2][tid] = sxx;
+        s_lin[3][tid] = sxt;
+        __syncthreads();
+        for (int w = kLeafBlock / 2; w > 0; w >>= 1) {
+            if (tid < w)
+                for (int c = 0; c < 4; ++c) s_lin[c][tid] += s_lin[c][tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const double dn = (double)nj;
+            const double den = dn * s_lin[2][0] - s_lin[0][0] * s_lin[0][0];
+            const double a = den > 0.0 ? (dn * s_lin[3][0] - s_lin[0][0] * s_lin[1][0]) / den : 0.0;
+            const double b = (s_lin[1][0] - a * s_lin[0][0]) / dn;
+            par[0] = (float)a;
+            par[1] = (float)b;
+        }
+        return;
+    }
+
+    // network leaf: piecewise-linear interpolant at 17 rank quantiles
+    if (tid == 0) {
+        float kx[kMlpHidden + 1], kt[kMlpHidden + 1];
+        for (int q = 0; q <= kMlpHidden; ++q) {
+            const int64_t r = ((int64_t)q * (nj - 1)) / kMlpHidden;  // < 2^35
+            kx[q] = xof(r);
+            kt[q] = __fdiv_rn((float)r, fnj);
+        }
+        float prev = 0.0f;
+        for (int q = 0; q < kMlpHidden; ++q) {
+            const float dx = __fsub_rn(kx[q + 1], kx[q]);
+            const float sl = dx > 0.0f ? __fdiv_rn(__fsub_rn(kt[q + 1], kt[q]), dx) : 0.0f;
+            s_p[q] = 1.0f;                           // w1
+            s_p[kMlpHidden + q] = -kx[q];            // b1
+            s_p[2 * kMlpHidden + q] = __fsub_rn(sl, prev);  // w2: change of slope
+            prev = sl;
+        }
+        s_p[3 * kMlpHidden] = kt[0];  // b2
+    }
+    if (tid < kMlpParams) {
+        s_m[tid] = 0.0f;
+        s_v[tid] = 0.0f;
+    }
+    __syncthreads();
+
+    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f;
+    float pw1 = 1.0f, pw2 = 1.0f;  // b1c^t, b2c^t
+    for (uint32_t ep = 0; ep < epochs; ++ep) {
+        float p[kMlpParams], g[kMlpParams + 1];
+#pragma unroll
+        for (int c = 0; c < kMlpParams; ++c) {
+            p[c] = s_p[c];
+            g[c] = 0.0f;
+        }
+        g[kMlpParams] = 0.0f;
+        for (int64_t s = tid; s < nj; s += blockDim.x)
+            mlp_accumulate(p, xof(s), __fdiv_rn((float)s, fnj), g, g[kMlpParams]);
+        block_sum49<kMlpParams + 1>(g, s_g, s_w);
+        pw1 = __fmul_rn(pw1, b1c);
+        pw2 = __fmul_rn(pw2, b2c);
+        if (tid < kMlpParams) {
+            const float gr = (float)(s_g[tid] / (double)nj);
+            const float m = fmaf(b1c, s_m[tid], __fmul_rn(1.0f - b1c, gr));
+            const float vv = fmaf(b2c, s_v[tid], __fmul_rn(__fmul_rn(1.0f - b2c, gr), gr));
+            s_m[tid] = m;
+            s_v[tid] = vv;
+            const float mh = __fdiv_rn(m, 1.0f - pw1), vh = __fdiv_rn(vv, 1.0f - pw2);
+            s_p[tid] = __fsub_rn(s_p[tid], __fdiv_rn(__fmul_rn(lr, mh), __fadd_rn(sqrtf(vh), eps)));
+        }
+        __syncthreads();
+    }
+    if (tid < kMlpParams) par[tid] = s_p[tid];
+}
+
+// Window of every leaf: min / max of (rank - predicted rank) over its keys.
+__global__ __launch_bounds__(256) void k_leaf_err(const uint64_t *__restrict__ keys, int64_t n,
+                                                  char *index) {
+    IndexView v;
+    const IndexHeader &h = *(const IndexHeader *)index;
+    index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t q = keys[i];
+        const uint32_t j = route(h, v, q);
+        const int64_t e = i - leaf_predict(v, h.leaf_kind, h.nparams, j, q, n);
+        const int32_t ec = (int32_t)(e > 0x3FFFFFFF ? 0x3FFFFFFF : (e < -0x3FFFFFFF ? -0x3FFFFFFF : e));
+        atomicMin(&v.err_lo[j], ec);
+        atomicMax(&v.err_hi[j], ec);
+    }
+}
+
+template <typename K>
+__device__ __forceinline__ int64_t lb_range(const K *keys, int64_t lo, int64_t hi, K q) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < q) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_index_lookup(const char *__restrict__ index,
+                                                      const uint64_t *__restrict__ keys, int64_t n,
+                                                      const uint64_t *__restrict__ q, int64_t nq,
+                                                      int64_t *__restrict__ rank,
+                                                      uint8_t *__restrict__ found,
+                                                      unsigned long long *fallbacks, uint32_t *err) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nq) return;
+    const IndexHeader h = *(const IndexHeader *)index;
+    const bool ok = h.magic == kIndexMagic && h.version == kIndexVersion && h.n == n &&
+                    h.n_leaves >= 1 && h.n_leaves <= 65536 && h.leaf_kind <= 1 &&
+                    h.nparams == (h.leaf_kind ? (uint32_t)kMlpParams : 2u) && h.root_segs <= 65536 &&
+                    (n == 0 || (keys[0] == h.kmin && keys[n - 1] == h.kmax));
+    if (!ok) {
+        set_err(err, ERR_MISMATCH);
+        rank[t] = 0;
+        if (found) found[t] = 0;
+        return;
+    }
+    IndexView v;
+    index_layout((char *)index, h.n_leaves, h.nparams, h.root_segs, &v);
+    const uint64_t x = q[t];
+    int64_t r = 0;
+    bool fell = false;
+    if (n > 0) {
+        const uint32_t j = route(h, v, x);
+        int64_t f0 = v.first[j], f1 = v.first[j + 1];
+        f0 = f0 < 0 ? 0 : (f0 > n ? n : f0);
+        f1 = f1 < f0 ? f0 : (f1 > n ? n : f1);
+        const int64_t p = leaf_predict(v, h.leaf_kind, h.nparams, j, x, n);
+        int64_t lo = p + v.err_lo[j], hi = p + v.err_hi[j];
+        lo = lo < f0 ? f0 : (lo > f1 ? f1 : lo);
+        hi = hi < lo ? lo : (hi > f1 ? f1 : hi);
+        const bool good = (lo == 0 || keys[lo - 1] < x) && (hi == n || keys[hi] >= x);
+        if (good) {
+            r = lb_range(keys, lo, hi, x);  // answer in [lo, hi]
+        } else {
+            r = lb_range(keys, (int64_t)0, n, x);
+            fell = true;
+        }
+    }
+    rank[t] = r;
+    if (found) found[t] = (uint8_t)(r < n && keys[r] == x);
+    if (fallbacks) {
+        const uint64_t m = ballot64(fell);
+        if (m && lane_id() == __ffsll((long long)__ballot(1)) - 1) atomicAdd(fallbacks, (unsigned long long)__popcll(m));
+    }
+}
+
+__global__ void k_index_stats(const char *index, int32_t *width, int64_t *count) {
+    const IndexHeader &h = *(const IndexHeader *)index;
+    IndexView v;
+    index_layout((char *)index, h.n_leaves, h.nparams, h.root_segs, &v);
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < h.n_leaves;
+         j += gridDim.x * blockDim.x) {
+        if (width) width[j] = v.err_hi[j] - v.err_lo[j] + 1;
+        if (count) count[j] = v.first[j + 1] - v.first[j];
+    }
+}
+
+__global__ __launch_bounds__(kLeafBlock) void k_mlp_loss_grad(const float *params, const float *x,
+                                                              const float *t, int64_t n,
+                                                              double *grad, double *loss) {
+    __shared__ double s_g[kMlpParams + 1];
+    __shared__ float s_w[(kLeafBlock / 64) * (kMlpParams + 1)];
+    float p[kMlpParams], g[kMlpParams + 1];
+    for (int c = 0; c < kMlpParams; ++c) {
+        p[c] = params[c];
+        g[c] = 0.0f;
+    }
+    g[kMlpParams] = 0.0f;
+    for (int64_t s = threadIdx.x; s < n; s += blockDim.x) mlp_accumulate(p, x[s], t[s], g, g[kMlpParams]);
+    block_sum49<kMlpParams + 1>(g, s_g, s_w);
+    if (threadIdx.x < kMlpParams) grad[threadIdx.x] = n ? s_g[threadIdx.x] / (double)n : 0.0;
+    if (threadIdx.x == kMlpParams && loss) *loss = n ? s_g[kMlpParams] / (double)n : 0.0;
+}
+
+constexpr int kRootBlocks = 512;
+
+}  // namespace cga
+
+using namespace cga;
+
+extern "C" {
+
+size_t cga_index_bytes(const cga_index_params *p) {
+    if (!p || p->n_leaves < 1 || p->n_leaves > 65536 || p->leaf_kind > 1) return 0;
+    if (p->root_segments > 65536) return 0;
+    return index_layout(nullptr, p->n_leaves, p->leaf_kind ? kMlpParams : 2, p->root_segments,
+                        nullptr);
+}
+
+size_t cga_index_train_workspace_bytes(const cga_index_params *p, int64_t n) {
+    if (!p || n < 0) return 0;
+    return kControlBytes + idx_align((size_t)kRootBlocks * 4 * sizeof(double));
+}
+
+int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p, void *d_index,
+                    size_t index_bytes, void *d_ws, size_t ws_bytes, cga_stream stream) {
+    if (!p || n < 0 || !d_index || !d_ws) return CGA_EINVAL;
+    if (n > 0 && !d_keys) return CGA_EINVAL;
+    if (n >= ((int64_t)1 << 31) - 1) return CGA_EUNSUPPORTED;
+    const size_t need = cga_index_bytes(p);
+    if (need == 0 || !(p->lr >= 0.0f)) return CGA_EINVAL;
+    if (index_bytes < need) return CGA_EINVAL;
+    if (ws_bytes < cga_index_train_workspace_bytes(p, n)) return CGA_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Control *ctl = (Control *)d_ws;
+    double *partial = (double *)((char *)d_ws + kControlBytes);
+    const uint32_t L = p->n_leaves, np = p->leaf_kind ? kMlpParams : 2;
+    CGA_TRY(launch_begin(ctl, nullptr, 0, nullptr, 0, nullptr, s));
+    char *idx = (char *)d_index;
+    IndexHeader *h = (IndexHeader *)idx;
+    {
+        CGA_PROF("index_root", s);
+        k_index_header<<<1, 64, 0, s>>>(d_keys, n, L, p->leaf_kind, np, p->root_segments, h);
+        if (n > 0) {
+            k_root_partial<<<kRootBlocks, 256, 0, s>>>(d_keys, n, h, partial);
+            k_root_final<<<1, 64, 0, s>>>(partial, kRootBlocks, n, h);
+            if (p->root_segments) {
+                const unsigned rb = (p->root_segments + 256) / 256;
+                k_root_knots<<<rb, 256, 0, s>>>(d_keys, n, idx);
+                k_root_slopes<<<rb, 256, 0, s>>>(idx);
+            }
+        }
+    }
+    int64_t blocks = (n + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+    {
+        CGA_PROF("index_bounds", s);
+        k_leaf_bounds<<<(unsigned)blocks, 256, 0, s>>>(d_keys, n, idx);
+    }
+    {
+        CGA_PROF("index_fit", s);
+        if (p->leaf_kind == 0)
+            k_leaf_fit<0><<<L, kLeafBlock, 0, s>>>(d_keys, idx, 0, 0.0f);
+        else
+            k_leaf_fit<1><<<L, kLeafBlock, 0, s>>>(d_keys, idx, p->epochs, p->lr);
+    }
+    if (n > 0) {
+        CGA_PROF("index_err", s);
+        k_leaf_err<<<(unsigned)blocks, 256, 0, s>>>(d_keys, n, idx);
+    }
+    CGA_HIP(hipGetLastError());
+    return CGA_OK;
+}
+
+size_t cga_index_lookup_workspace_bytes(void) { return kControlBytes; }
+
+int cga_index_lookup(const void *d_index, const uint64_t *d_keys, int64_t n, const uint64_t *d_q,
+                     int64_t nq, int64_t *d_rank, uint8_t *d_found, uint64_t *d_fallbacks,
+                     void *d_ws, size_t ws_bytes, cga_stream stream) {
+    if (!d_index || n < 0 || nq < 0 || !d_ws) return CGA_EINVAL;
+    if ((n > 0 && !d_keys) || (nq > 0 && (!d_q || !d_rank))) return CGA_EINVAL;
+    if (ws_bytes < kControlBytes) return CGA_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Control *ctl = (Control *)d_ws;
+    CGA_TRY(launch_begin(ctl, nullptr, 0, nullptr, 0, nullptr, s));
+    if (nq > 0) {
+        CGA_PROF("index_lookup", s);
+        k_index_lookup<<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(
+            (const char *)d_index, d_keys, n, d_q, nq, d_rank, d_found,
+            (unsigned long long *)d_fallbacks, &ctl->err);
+    }
+    CGA_HIP(hipGetLastError());
+    return CGA_OK;
+}
+
+int cga_index_stats(const void *d_index, int32_t *d_width, int64_t *d_count, cga_stream stream) {
+    if (!d_index) return CGA_EINVAL;
+    k_index_stats<<<256, 256, 0, (hipStream_t)stream>>>((const char *)d_index, d_width, d_count);
+    CGA_HIP(hipGetLastError());
+    return CGA_OK;
+}
+
+int cga_mlp_loss_grad(const float *d_params, const float *d_x, const float *d_t, int64_t n,
+                      double *d_grad, double *d_loss, cga_stream stream) {
+    if (!d_params || !d_grad || n < 0 || (n > 0 && (!d_x || !d_t))) return CGA_EINVAL;
+    k_mlp_loss_grad<<<1, kLeafBlock, 0, (hipStream_t)stream>>>(d_params, d_x, d_t, n, d_grad,
+                                                               d_loss);
+    CGA_HIP(hipGetLastError());
+    return CGA_OK;
+}
+
+}  // extern "C"

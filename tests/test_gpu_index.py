@@ -1,0 +1,159 @@
+"""GPU tests of the learned index: exact ranks against the oracle's
+lower_bound on every query (present, absent, extremes), the binary-search
+fallback when the windows are wrong, key-array mismatch detection, the leaf
+network's gradient against the fp64 oracle, and what the trained network
+gains over linear leaves and over no index."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from helpers import dev, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _lidar_keys(nsweeps=4, naz=4096, depth=16):
+    """Sorted unique 48-bit Morton keys of a few LiDAR sweeps (oracle build)."""
+    boxes = gen.lidar_scene(1005)
+    poses, _ = gen.random_walk(1005, nsweeps)
+    xyz = np.concatenate([gen.lidar_sweep(1005, 100 + f, boxes, poses[f, :3], poses[f, 3], 64, naz)
+                          for f in range(nsweeps)])
+    g = gen.cubic_grid([xyz], depth)
+    keys, _ = oracle.build(xyz, g)
+    return keys
+
+
+@pytest.fixture(scope="module")
+def lidar_keys():
+    return _lidar_keys()
+
+
+def _queries(keys, nq, seed):
+    q = gen.lookup_queries(seed, keys, nq)
+    extra = np.array([0, 2 ** 64 - 1, keys[0], keys[-1], keys[0] - 1, keys[-1] + 1,
+                      keys[len(keys) // 2] + 1], np.uint64)
+    return np.concatenate([q, extra])
+
+
+def _t(a):
+    return dev(np.ascontiguousarray(a, np.uint64).view(np.int64))
+
+
+@pytest.mark.parametrize("kind,leaves,root", [(0, 4096, 0), (1, 4096, 0), (0, 4096, 1024),
+                                              (1, 4096, 1024), (1, 1, 0), (0, 7, 3), (1, 65536, 64),
+                                              (1, 4096, 65536)])
+def test_lookup_exact(gpu, lidar_keys, kind, leaves, root):
+    keys = lidar_keys
+    q = _queries(keys, 200_000, 7 + kind)
+    kd, qd = _t(keys), _t(q)
+    say("index", kind, leaves, root, len(keys))
+    idx = gpu.cga_index_train(kd, n_leaves=leaves, leaf_kind=kind, epochs=20, root_segments=root)
+    r, f, fb = gpu.cga_index_lookup(idx, kd, qd)
+    wr, wf = oracle.lower_bound(keys, q)
+    assert np.array_equal(r.cpu().numpy(), wr)
+    assert np.array_equal(f.cpu().numpy(), wf)
+    br, bf = gpu.cga_binary_lookup(kd, qd)
+    assert np.array_equal(br.cpu().numpy(), wr) and np.array_equal(bf.cpu().numpy(), wf)
+    # present keys never fall back: their windows are measured on them
+    rp, _, fbp = gpu.cga_index_lookup(idx, kd, kd)
+    assert fbp == 0 and np.array_equal(rp.cpu().numpy(), np.arange(len(keys)))
+
+
+def test_lookup_small_arrays(gpu):
+    for keys in (np.array([5], np.uint64), np.array([1, 2], np.uint64),
+                 np.unique(np.random.default_rng(1).integers(0, 2 ** 40, 3000, dtype=np.uint64))):
+        q = np.concatenate([keys, keys + np.uint64(1), np.array([0, 2 ** 64 - 1], np.uint64)])
+        for kind, root in ((0, 0), (1, 0), (0, 16), (1, 1024)):
+            kd = _t(keys)
+            idx = gpu.cga_index_train(kd, n_leaves=64, leaf_kind=kind, epochs=5, root_segments=root)
+            r, f, _ = gpu.cga_index_lookup(idx, kd, _t(q))
+            wr, wf = oracle.lower_bound(keys, q)
+            assert np.array_equal(r.cpu().numpy(), wr) and np.array_equal(f.cpu().numpy(), wf)
+
+
+def _window_offsets(n_leaves, nparams, root):
+    """Byte offsets of the err_lo / err_hi arrays in the index buffer (header of
+    256 bytes, then root knots, first, kfirst, isp, err_lo, err_hi, params,
+    each rounded up to 256 bytes)."""
+    al = lambda v: (v + 255) // 256 * 256
+    off = 256
+    if root:
+        off = al(off + (root + 1) * 4)
+        off = al(off + (root + 1) * 4)
+        off = al(off + root * 4)
+    off = al(off + (n_leaves + 1) * 8)   # first
+    off = al(off + n_leaves * 8)         # kfirst
+    off = al(off + n_leaves * 4)         # isp
+    lo = off
+    off = al(off + n_leaves * 4)
+    return lo, off
+
+
+def test_zeroed_windows_fall_back_and_stay_exact(gpu, lidar_keys):
+    keys = lidar_keys
+    kd = _t(keys)
+    idx = gpu.cga_index_train(kd, n_leaves=4096, leaf_kind=1, epochs=10, root_segments=1024)
+    host = idx.cpu().numpy().copy()
+    lo, hi = _window_offsets(4096, 49, 1024)
+    host[lo:lo + 4096 * 4] = 0
+    host[hi:hi + 4096 * 4] = 0
+    bad = torch.from_numpy(host).cuda()
+    q = _queries(keys, 100_000, 11)
+    r, f, fb = gpu.cga_index_lookup(bad, kd, _t(q))
+    wr, wf = oracle.lower_bound(keys, q)
+    assert np.array_equal(r.cpu().numpy(), wr) and np.array_equal(f.cpu().numpy(), wf)
+    assert fb > 0
+
+
+def test_mismatched_keys_rejected(gpu, lidar_keys):
+    keys = lidar_keys
+    idx = gpu.cga_index_train(_t(keys), n_leaves=256, leaf_kind=0)
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_index_lookup(idx, _t(keys[:-1]), _t(keys[:10]))
+    assert e.value.status == gpu.EMISMATCH
+
+
+def test_mlp_gradient_matches_fp64_oracle(gpu):
+    rng = np.random.default_rng(3)
+    for n in (1, 37, 1000, 20000):
+        p = rng.normal(0, 1, 49).astype(np.float32)
+        x = rng.uniform(0, 1, n).astype(np.float32)
+        t = np.sort(rng.uniform(0, 1, n)).astype(np.float32)
+        loss, g = gpu.cga_mlp_loss_grad(dev(p), dev(x), dev(t))
+        wl, wg, kinks = oracle.mlp_loss_grad(p.astype(np.float64), x.astype(np.float64),
+                                             t.astype(np.float64))
+        assert kinks == 0
+        g = g.cpu().numpy()
+        scale = max(1.0, np.abs(wg).max())
+        assert np.allclose(g, wg, rtol=1e-4, atol=1e-5 * scale), (n, np.abs(g - wg).max())
+        assert abs(loss - wl) <= 1e-4 * max(1.0, wl)
+
+
+def test_trained_network_gain(gpu, lidar_keys):
+    """Mean window width and fallback rate: linear leaves, the network at its
+    initialisation, and the trained network; plus the binary-search probe
+    count for the same array.  The trained network must not be worse than its
+    initialisation and must beat linear leaves."""
+    keys = lidar_keys
+    kd = _t(keys)
+    q = _queries(keys, 200_000, 13)
+    qd = _t(q)
+    wr, _ = oracle.lower_bound(keys, q)
+    res = {}
+    for name, kind, ep, root in (("linear_root+linear", 0, 0, 0), ("linear_root+mlp", 1, 200, 0),
+                                 ("linear", 0, 0, 1024), ("mlp_init", 1, 0, 1024),
+                                 ("mlp_trained", 1, 200, 1024)):
+        idx = gpu.cga_index_train(kd, n_leaves=4096, leaf_kind=kind, epochs=ep, lr=1e-4,
+                                  root_segments=root)
+        w, c = gpu.cga_index_stats(idx, 4096)
+        w, c = w.cpu().numpy().astype(np.float64), c.cpu().numpy()
+        mean_w = float((w * c).sum() / c.sum())
+        r, _, fb = gpu.cga_index_lookup(idx, kd, qd)
+        assert np.array_equal(r.cpu().numpy(), wr)
+        res[name] = (mean_w, fb / len(q))
+    say("window width (key-weighted mean) / fallback rate:", res,
+        "binary search probes:", int(np.ceil(np.log2(len(keys)))))
+    assert res["mlp_trained"][0] <= res["mlp_init"][0] * 1.001
+    assert res["mlp_trained"][0] < res["linear"][0]
