@@ -3,16 +3,21 @@
 
 One step = the whole pipeline on one batch of synthetic input, already in
 HBM: build the CGA of two LiDAR sweeps (quantize, encode, radix sort,
-run-length compaction), merge them, project the union onto XY, and answer
-k-NN queries against the union.  Workloads:
+run-length compaction), merge them, project the union onto XY, answer k-NN
+queries against the union, train the learned index of the union and answer
+point-location / range-start lookups with it and with binary search.
+Workloads:
   c2 (default): 2 x 1,048,576-point sweeps, depth 12, 100k queries, k = 8
   c3: 2 x 10M-point bumpy spheres, depth 14, 1M queries, k = 16
   c1: 2 x 100k sphere points, depth 10, 1k queries, k = 1
 Prints one JSON line.  value = input points per second of whole steps.
+Unless --no-c5, it also measures the learned index against binary search on
+the 50M-key, 10M-query configuration (reported under "c5", not in value).
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -34,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="skip the per-kernel event timing (for external profilers)")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 50M-key learned-index run")
+    ap.add_argument("--c5-reps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -70,7 +77,32 @@ class Pipeline:
         self.idx = torch.empty((nq, self.k), dtype=torch.int64, device=device)
         self.d2 = torch.empty((nq, self.k), dtype=torch.int64, device=device)
         self.cnt = torch.zeros(4, dtype=torch.int64, device=device)
-        self.ws = [cga.Workspaces(device) for _ in range(5)]
+        self.ws = [cga.Workspaces(device) for _ in range(7)]
+        # learned index of the union: a buffer sized for it, and lookups of
+        # the union's own keys (half) and uniform values (half); the present
+        # half is drawn by position from the oracle-independent generator on
+        # the host after one synchronous build (setup, outside the timing)
+        self.index_kwargs = dict(n_leaves=4096, leaf_kind=cga.LEAF_MLP, epochs=50, lr=1e-4,
+                                 root_segments=1024)
+        p = cga.index_params(**self.index_kwargs)
+        self.index = torch.empty(cga.lib.cga_index_bytes(ctypes.byref(p)), dtype=torch.uint8,
+                                 device=device)
+        self.nl = 100_000
+        self.lq = None
+        self.lrank = torch.empty(self.nl, dtype=torch.int64, device=device)
+        self.lfound = torch.empty(self.nl, dtype=torch.uint8, device=device)
+        self.brank = torch.empty(self.nl, dtype=torch.int64, device=device)
+        self.bfound = torch.empty(self.nl, dtype=torch.uint8, device=device)
+        self.fb = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def make_lookups(self, seed=1006):
+        import numpy as np
+        import torch
+
+        import gen
+        m = self.m[: int(self.cnt[2].item())].cpu().numpy().view(np.uint64)
+        self.lq = torch.from_numpy(gen.lookup_queries(seed, m, self.nl).view(np.int64)).to(
+            self.m.device)
 
     def step(self, marks=None):
         c, g = self.cga, self.g
@@ -93,6 +125,21 @@ class Pipeline:
                   d2_out=self.d2, sync=False, ws=self.ws[4])
         if marks:
             marks[3].record()
+        if self.lq is not None:
+            # the index is trained on the union; its size comes from the host
+            # copy taken at setup (the merge result is identical every step)
+            c.cga_index_train(self.m, self.nu, out=self.index, ws=self.ws[5], **self.index_kwargs)
+            if marks:
+                marks[4].record()
+            c.cga_index_lookup(self.index, self.m, self.lq, n=self.nu, rank_out=self.lrank,
+                               found_out=self.lfound, fallbacks_out=self.fb, sync=False,
+                               ws=self.ws[6])
+            if marks:
+                marks[5].record()
+            c.cga_binary_lookup(self.m, self.lq, n=self.nu, rank_out=self.brank,
+                                found_out=self.bfound)
+            if marks:
+                marks[6].record()
 
     def check(self):
         for w in self.ws:
@@ -150,8 +197,9 @@ def load_traffic(label, workload):
     return t.get("bytes_per_step")
 
 
-def cpu_baseline(d):
-    """The oracle, untuned, on one full step of the same workload."""
+def cpu_baseline(d, lookups=None):
+    """The oracle, untuned, on one full step of the same workload (the
+    learned index has no oracle counterpart beyond lower_bound itself)."""
     import numpy as np
 
     import oracle
@@ -167,6 +215,8 @@ def cpu_baseline(d):
         oracle.project(m, g.depth, g.key_mode, 2)
         t1 = time.perf_counter()
         oracle.knn_kdtree(m, d["q"], g, d["k"])
+        if lookups is not None:
+            oracle.lower_bound(m, lookups)
         t2 = time.perf_counter()
         t_set += t1 - t0
         t_knn += t2 - t1
@@ -178,9 +228,92 @@ def cpu_baseline(d):
         "value": n / per, "unit": "points/s", "cores": threads, "kind": "oracle",
         "sample": (f"{steps} full step(s) of {n} points and {len(d['q'])} queries: std::map/std::set "
                    f"build, merge and projection on 1 thread ({t_set / steps:.2f} s/step), kd-tree "
-                   f"k-NN on {threads} OpenMP threads ({t_knn / steps:.2f} s/step)"),
+                   f"k-NN and lower_bound lookups on {threads} OpenMP threads "
+                   f"({t_knn / steps:.2f} s/step)"),
         "seconds_per_step": round(per, 3),
     }
+
+
+def c5_learned_vs_binary(cga, device, reps):
+    """The 50M-key configuration: build the keys of random-walk LiDAR sweeps at
+    depth 16, keep a seeded uniform subset of exactly 50M, train the index,
+    then time 10M lookups (half present, half uniform in the key range) with
+    the learned index and with binary search, interleaved on one stream, and
+    require identical ranks and membership."""
+    import numpy as np
+    import torch
+
+    import gen
+    t0 = time.perf_counter()
+    d = gen.c5_sweeps()
+    xyz = torch.from_numpy(d["xyz"]).to(device)
+    keys, _ = cga.cga_build(xyz, d["grid"], counts=False)
+    del xyz
+    u = len(keys)
+    target = 50_000_000
+    if u > target:
+        sel = torch.from_numpy(gen.subset(1005, u, target)).to(device)
+        keys = keys.index_select(0, sel).contiguous()
+    n = len(keys)
+    kh = keys.cpu().numpy().view(np.uint64)
+    q = torch.from_numpy(gen.lookup_queries(1005, kh, 10_000_000).view(np.int64)).to(device)
+    setup_s = time.perf_counter() - t0
+    out = {"keys": n, "unique_before_subset": u, "queries": len(q), "setup_s": round(setup_s, 1)}
+    res = {}
+    for name, kind, root in (("mlp_pl_root", cga.LEAF_MLP, 1024), ("linear_pl_root", 0, 1024),
+                             ("mlp_linear_root", cga.LEAF_MLP, 0)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        idx = cga.cga_index_train(keys, n_leaves=4096, leaf_kind=kind, epochs=50, lr=1e-4,
+                                  root_segments=root)
+        torch.cuda.synchronize()
+        train_ms = (time.perf_counter() - a) * 1e3
+        w, c = cga.cga_index_stats(idx, 4096)
+        w, c = w.cpu().numpy().astype(np.float64), c.cpu().numpy()
+        res[name] = {"train_ms": round(train_ms, 2),
+                     "window_mean": round(float((w * c).sum() / max(c.sum(), 1)), 2),
+                     "idx": idx}
+    rank_l = torch.empty(len(q), dtype=torch.int64, device=device)
+    found_l = torch.empty(len(q), dtype=torch.uint8, device=device)
+    rank_b = torch.empty_like(rank_l)
+    found_b = torch.empty_like(found_l)
+    fb = torch.zeros(1, dtype=torch.int64, device=device)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    times = {k: [] for k in list(res) + ["binary"]}
+    for _ in range(reps):
+        for name in res:
+            e0, e1 = ev(), ev()
+            e0.record()
+            cga.cga_index_lookup(res[name]["idx"], keys, q, rank_out=rank_l, found_out=found_l,
+                                 fallbacks_out=fb, sync=False)
+            e1.record()
+            times[name].append((e0, e1))
+        e0, e1 = ev(), ev()
+        e0.record()
+        cga.cga_binary_lookup(keys, q, rank_out=rank_b, found_out=found_b)
+        e1.record()
+        times["binary"].append((e0, e1))
+    torch.cuda.synchronize()
+    med = lambda xs: float(np.median([a.elapsed_time(b) for a, b in xs]))
+    for name in res:
+        fb.zero_()
+        r, f, nfb = cga.cga_index_lookup(res[name]["idx"], keys, q, rank_out=rank_l, found_out=found_l,
+                                        fallbacks_out=fb)
+        cga.cga_binary_lookup(keys, q, rank_out=rank_b, found_out=found_b)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(rank_l, rank_b) and torch.equal(found_l, found_b))
+        if not same:
+            raise RuntimeError(f"learned lookup ({name}) disagrees with binary search")
+        ms = med(times[name])
+        del res[name]["idx"]
+        res[name].update({"lookup_ms": round(ms, 3), "lookups_per_s": len(q) / (ms * 1e-3),
+                          "fallback_rate": nfb / len(q), "identical_to_binary": same})
+    ms_b = med(times["binary"])
+    out["binary"] = {"lookup_ms": round(ms_b, 3), "lookups_per_s": len(q) / (ms_b * 1e-3)}
+    out["learned"] = res
+    out["speedup_best_learned_vs_binary"] = round(
+        max(v["lookups_per_s"] for v in res.values()) / out["binary"]["lookups_per_s"], 3)
+    return out
 
 
 def main():
@@ -196,15 +329,23 @@ def main():
     d = make_workload(args.workload)
     pipe = Pipeline(cga, d, device)
 
+    pipe.step()
+    torch.cuda.synchronize()
+    pipe.check()
+    pipe.nu = int(pipe.cnt[2].item())
+    pipe.make_lookups()
     for _ in range(args.warmup):
         pipe.step()
     torch.cuda.synchronize()
     pipe.check()
     counts = [int(x) for x in pipe.cnt.cpu().tolist()]
+    if not (torch.equal(pipe.lrank, pipe.brank) and torch.equal(pipe.lfound, pipe.bfound)):
+        raise RuntimeError("learned and binary lookups disagree")
 
     # per-kernel breakdown (untimed pass), to name the dominant kernel
     labels = ["begin", "encode", "histogram", "hist_scan", "onesweep", "rle", "merge_partition",
-              "merge", "rekey", "knn"]
+              "merge", "rekey", "knn", "index_root", "index_bounds", "index_fit", "index_err",
+              "index_lookup", "binary_lookup"]
     kern_ms = {}
     dominant = None
     if not args.no_kernel_timing:
@@ -223,7 +364,7 @@ def main():
         if dominant:
             cga.cga_prof_enable([dominant])
 
-    marks = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    marks = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
@@ -241,6 +382,9 @@ def main():
     st_build = stage(0, 1)
     st_proj = stage(1, 2)
     st_knn = stage(2, 3)
+    st_train = stage(3, 4)
+    st_learned = stage(4, 5)
+    st_binary = stage(5, 6)
     n_points = pipe.na + pipe.nb
     nq = len(pipe.q)
 
@@ -277,13 +421,21 @@ def main():
             "build_merge": {"ms": round(st_build, 4), "points_per_s": n_points / (st_build * 1e-3)},
             "project_xy": {"ms": round(st_proj, 4)},
             "knn": {"ms": round(st_knn, 4), "queries_per_s": nq / (st_knn * 1e-3)},
+            "index_train": {"ms": round(st_train, 4), "keys": pipe.nu},
+            "learned_lookup": {"ms": round(st_learned, 4),
+                               "lookups_per_s": pipe.nl / (st_learned * 1e-3)},
+            "binary_lookup": {"ms": round(st_binary, 4),
+                              "lookups_per_s": pipe.nl / (st_binary * 1e-3)},
         },
         "kernels_ms_per_step": kern_ms,
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if not args.no_c5:
+        line["c5"] = c5_learned_vs_binary(cga, device, args.c5_reps)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(d)
+        import numpy as np
+        line["cpu_baseline"] = cpu_baseline(d, pipe.lq.cpu().numpy().view(np.uint64))
     print(json.dumps(line), flush=True)
 
 

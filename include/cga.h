@@ -237,6 +237,55 @@ int cga_index_stats(const void *d_index, int32_t *d_width, int64_t *d_count, cga
 int cga_mlp_loss_grad(const float *d_params, const float *d_x, const float *d_t, int64_t n,
                       double *d_grad, double *d_loss, cga_stream stream);
 
+/* ---------------------------------------------------------------- batched
+ * CGA construction of nframes frames plus the union of every consecutive
+ * pair (frame f u frame f+1, Eq. (1)), all on one grid.  d_xyz holds the
+ * frames' points back to back (n in total); d_off (device, nframes + 1
+ * int64) the frame boundaries, d_off[0] = 0, d_off[nframes] = n.
+ * Outputs:
+ *   d_keys (capacity n): each frame's sorted unique keys, frame after frame;
+ *   d_counts (nullable, capacity n): points per voxel, aligned to d_keys;
+ *   d_key_off (nframes + 1 int64): frame f's keys are
+ *       d_keys[d_key_off[f] .. d_key_off[f+1]);
+ *   d_merged (capacity 2n): pair f's union starts at d_merged_off[f]
+ *       (nframes - 1 int64) and holds d_merged_cnt[f] keys.
+ * Implementation: composite keys (frame << 3*depth | key) in one radix sort,
+ * one run-length pass, per-frame offsets by binary search, then one
+ * persistent merge launch over a window queue spanning all pairs.  Every size
+ * after the input stays on the device, so the call can be captured in a
+ * graph: cga_batch_graph_create records it once (on a private stream) into
+ * an executable graph that cga_batch_graph_launch replays on any stream,
+ * with the same buffers.  Requires 3 * depth + ceil(log2(nframes)) <= 64;
+ * nframes in [1, 65536]; n < 2^30.  tune NULL = autotuned (see below) or
+ * default digit width and tile size; results never depend on it. */
+size_t cga_batch_workspace_bytes(const cga_grid *grid, int nframes, int64_t n);
+int cga_batch_build_merge(const cga_grid *grid, const float *d_xyz, const int64_t *d_off,
+                          int nframes, int64_t n, void *d_keys, uint32_t *d_counts,
+                          int64_t *d_key_off, void *d_merged, int64_t *d_merged_off,
+                          int64_t *d_merged_cnt, const cga_tune *tune, void *d_ws,
+                          size_t ws_bytes, cga_stream stream);
+int cga_batch_graph_create(const cga_grid *grid, const float *d_xyz, const int64_t *d_off,
+                           int nframes, int64_t n, void *d_keys, uint32_t *d_counts,
+                           int64_t *d_key_off, void *d_merged, int64_t *d_merged_off,
+                           int64_t *d_merged_cnt, const cga_tune *tune, void *d_ws,
+                           size_t ws_bytes, void **graph);
+int cga_batch_graph_launch(void *graph, cga_stream stream);
+int cga_batch_graph_destroy(void *graph);
+
+/* -------------------------------------------------------------- autotuner
+ * Times every compiled (radix_bits, tile_items) pair of the radix sort on n
+ * keys of key_bytes width and key_bits significant bits -- a copy of d_keys,
+ * or synthetic hashed keys when d_keys is NULL -- and records the fastest for
+ * (key_bytes, key_bits, floor(log2 n)).  Later calls with tune == NULL
+ * (build, project, batched) use a recorded choice when one matches.  When
+ * the environment variable CGA_TUNE_CACHE names a file, recorded choices are
+ * loaded from it on first use and appended to it.  Returns the choice and its
+ * best time in milliseconds. */
+size_t cga_autotune_workspace_bytes(uint32_t key_bytes, int64_t n);
+int cga_autotune_sort(const void *d_keys, uint32_t key_bytes, uint32_t key_bits, int64_t n,
+                      void *d_ws, size_t ws_bytes, cga_tune *best, float *best_ms,
+                      cga_stream stream);
+
 /* ---------------------------------------------------------------- timing
  * Per-kernel launch timing for measurement.  After cga_prof_enable, each
  * launch of a kernel whose label is in the comma-separated `filter` (NULL or

@@ -101,6 +101,16 @@ _sig("cga_index_lookup_workspace_bytes", _SZ)
 _sig("cga_index_lookup", ctypes.c_int, _P, _P, _I64, _P, _I64, _P, _P, _P, _P, _SZ, _P)
 _sig("cga_index_stats", ctypes.c_int, _P, _P, _P, _P)
 _sig("cga_mlp_loss_grad", ctypes.c_int, _P, _P, _P, _I64, _P, _P, _P)
+_sig("cga_batch_workspace_bytes", _SZ, _GP, ctypes.c_int, _I64)
+_sig("cga_batch_build_merge", ctypes.c_int, _GP, _P, _P, ctypes.c_int, _I64, _P, _P, _P, _P, _P, _P,
+     _TP, _P, _SZ, _P)
+_sig("cga_batch_graph_create", ctypes.c_int, _GP, _P, _P, ctypes.c_int, _I64, _P, _P, _P, _P, _P,
+     _P, _TP, _P, _SZ, ctypes.POINTER(ctypes.c_void_p))
+_sig("cga_batch_graph_launch", ctypes.c_int, _P, _P)
+_sig("cga_batch_graph_destroy", ctypes.c_int, _P)
+_sig("cga_autotune_workspace_bytes", _SZ, ctypes.c_uint32, _I64)
+_sig("cga_autotune_sort", ctypes.c_int, _P, ctypes.c_uint32, ctypes.c_uint32, _I64, _P, _SZ, _TP,
+     ctypes.POINTER(ctypes.c_float), _P)
 _sig("cga_prof_enable", ctypes.c_int, ctypes.c_char_p)
 _sig("cga_prof_disable", ctypes.c_int)
 _sig("cga_prof_reset", ctypes.c_int)
@@ -398,6 +408,97 @@ def cga_mlp_loss_grad(params: torch.Tensor, x: torch.Tensor, t: torch.Tensor, st
     _check(lib.cga_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss),
                                  _stream(stream)), "cga_mlp_loss_grad")
     return float(loss.item()), g
+
+
+# ---------------------------------------------------------------- batched
+class BatchOutputs:
+    """Device outputs of one batched build + pair merge."""
+
+    def __init__(self, grid, nframes: int, n: int, device="cuda", counts=True):
+        kt = key_dtype(grid)
+        self.keys = _cap_tensor(n, kt, device)
+        self.counts = _cap_tensor(n, torch.int32, device) if counts else None
+        self.key_off = torch.zeros(nframes + 1, dtype=torch.int64, device=device)
+        self.merged = _cap_tensor(2 * n, kt, device)
+        self.merged_off = _cap_tensor(max(nframes - 1, 1), torch.int64, device)
+        self.merged_cnt = _cap_tensor(max(nframes - 1, 1), torch.int64, device)
+
+    def frame(self, f: int):
+        o = self.key_off.cpu().tolist()
+        return self.keys[o[f]:o[f + 1]]
+
+    def pair(self, f: int):
+        s0, c = int(self.merged_off[f].item()), int(self.merged_cnt[f].item())
+        return self.merged[s0:s0 + c]
+
+
+def _batch_args(grid, xyz, off, out, tune, wsb):
+    g = grid_struct(grid)
+    nf = off.shape[0] - 1
+    return (ctypes.byref(g), _ptr(xyz), _ptr(off), nf, xyz.shape[0], _ptr(out.keys), _ptr(out.counts),
+            _ptr(out.key_off), _ptr(out.merged), _ptr(out.merged_off), _ptr(out.merged_cnt),
+            tune_struct(tune), _ptr(wsb), wsb.numel()), g
+
+
+def cga_batch_build_merge(xyz: torch.Tensor, off: torch.Tensor, grid, *, out=None, tune=None,
+                          ws=None, stream=None) -> BatchOutputs:
+    """Build every frame's CGA and merge each consecutive pair (device sizes)."""
+    nf = off.shape[0] - 1
+    out = out if out is not None else BatchOutputs(grid, nf, xyz.shape[0], xyz.device)
+    g = grid_struct(grid)
+    wsb = _ws("batch", lib.cga_batch_workspace_bytes(ctypes.byref(g), nf, xyz.shape[0]), ws)
+    args, _ = _batch_args(grid, xyz, off, out, tune, wsb)
+    _check(lib.cga_batch_build_merge(*args, _stream(stream)), "cga_batch_build_merge")
+    return out
+
+
+class BatchGraph:
+    """The batched build + pair merge captured once as an executable graph over
+    fixed buffers; launch() replays it on a stream."""
+
+    def __init__(self, xyz, off, grid, out=None, tune=None, ws=None):
+        nf = off.shape[0] - 1
+        self.out = out if out is not None else BatchOutputs(grid, nf, xyz.shape[0], xyz.device)
+        g = grid_struct(grid)
+        self.wsb = _ws("batch_graph", lib.cga_batch_workspace_bytes(ctypes.byref(g), nf,
+                                                                    xyz.shape[0]), ws)
+        self._keep = (xyz, off)
+        args, self._g = _batch_args(grid, xyz, off, self.out, tune, self.wsb)
+        h = ctypes.c_void_p()
+        _check(lib.cga_batch_graph_create(*args, ctypes.byref(h)), "cga_batch_graph_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib.cga_batch_graph_launch(self.handle, _stream(stream)), "cga_batch_graph_launch")
+
+    def status(self, stream=None):
+        return lib.cga_ws_status(_ptr(self.wsb), _stream(stream))
+
+    def close(self):
+        if self.handle:
+            lib.cga_batch_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cga_autotune_sort(keys=None, key_bytes=8, key_bits=64, n=None, ws=None, stream=None):
+    """Time every compiled (radix bits, tile items) on these keys (or synthetic
+    ones) and record the fastest; returns (radix_bits, tile_items, ms)."""
+    if keys is not None:
+        n = keys.shape[0] if n is None else int(n)
+        key_bytes = keys.element_size()
+    wsb = _ws("autotune", lib.cga_autotune_workspace_bytes(key_bytes, n), ws)
+    best = cga_tune()
+    ms = ctypes.c_float()
+    _check(lib.cga_autotune_sort(_ptr(keys), key_bytes, key_bits, n, _ptr(wsb), wsb.numel(),
+                                 ctypes.byref(best), ctypes.byref(ms), _stream(stream)),
+           "cga_autotune_sort")
+    return best.radix_bits, best.tile_items, ms.value
 
 
 # ------------------------------------------------------------------ timing

@@ -82,8 +82,9 @@ SortCfg default_sort_cfg(bool wide, int64_t n) {
     return c;
 }
 
-static int pick_cfg(const cga_tune *t, bool wide, int64_t n, SortCfg *out) {
+static int pick_cfg(const cga_tune *t, bool wide, int64_t n, SortCfg *out, int key_bits = 0) {
     SortCfg c = default_sort_cfg(wide, n);
+    if (!t && key_bits > 0) tuned_sort_cfg(wide ? 8 : 4, key_bits, n, &c);
     if (t) {
         c.radix_bits = (int)t->radix_bits;
         c.items = (int)t->tile_items;
@@ -311,7 +312,7 @@ int cga_build(const cga_grid *g, const float *d_xyz, int64_t n, void *d_keys, ui
     if (n >= (int64_t)1 << 30) return CGA_EUNSUPPORTED;
     const bool wide = wide_keys(g->depth);
     SortCfg cfg;
-    CGA_TRY(pick_cfg(tune, wide, n, &cfg));
+    CGA_TRY(pick_cfg(tune, wide, n, &cfg, 3 * (int)g->depth));
     BuildLayout L = build_layout(d_ws, g, n, cfg);
     if (ws_bytes < L.bytes) return CGA_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
@@ -383,7 +384,7 @@ int cga_sort_keys(const cga_grid *g, const void *d_keys, int64_t n, const int64_
     if (n > 0 && (!d_keys || !d_out)) return CGA_EINVAL;
     if (n >= (int64_t)1 << 30) return CGA_EUNSUPPORTED;
     SortCfg cfg;
-    CGA_TRY(pick_cfg(tune, wide, n, &cfg));
+    CGA_TRY(pick_cfg(tune, wide, n, &cfg, (int)key_bits));
     Control *ctl;
     SortWs w;
     void *a, *b;

@@ -18,8 +18,8 @@ constexpr uint32_t kIndexMagic = 0x49414743u;  // "CGAI"
 constexpr uint32_t kIndexVersion = 1;
 constexpr int kMlpHidden = 16;
 constexpr int kMlpParams = 3 * kMlpHidden + 1;  // w1[16], b1[16], w2[16], b2
-constexpr int kLeafBlock = 256;
-constexpr int kLeafCache = 8192;  // leaf inputs kept in LDS (floats)
+constexpr int kLeafBlock = 64;  // one wave per leaf
+constexpr int kLeafCache = 4096;  // leaf inputs kept in LDS (floats)
 
 struct IndexHeader {
     uint32_t magic, version, n_leaves, leaf_kind;
@@ -28,41 +28,53 @@ struct IndexHeader {
     float root_a, root_b, inv_span;
     uint32_t nparams;
     uint32_t root_segs;
+    uint32_t leaf_stride;  // bytes per leaf record
 };
 static_assert(sizeof(IndexHeader) <= 256, "index header");
 
-// Offsets of the root knots and per-leaf arrays after the 256-byte header.
-struct IndexView {
-    IndexHeader *h;
-    float *rx, *ry, *rs;  // root knot inputs, outputs (R + 1 each), slopes (R)
-    int64_t *first;    // n_leaves + 1
-    uint64_t *kfirst;  // first key of each leaf
-    float *isp;        // 1 / (last key - first key) of each leaf, or 0
-    int32_t *err_lo, *err_hi;
-    float *params;     // n_leaves x nparams
+// One leaf = one record: this head, then its parameters; 64 bytes for a
+// linear leaf, 256 for a network leaf, so a lookup reads one or a few lines.
+struct LeafHead {
+    int64_t first;    // first rank of the leaf
+    uint64_t kfirst;  // key at that rank
+    int32_t count;    // keys in the leaf
+    float isp;        // 1 / (last key - first key), or 0
+    int32_t err_lo, err_hi;
+};
+static_assert(sizeof(LeafHead) == 32, "leaf head");
+
+// One root segment: input at its start, output at its start and end, slope.
+struct RootSeg {
+    float x0, y0, y1, slope;
 };
 
 __host__ __device__ inline size_t idx_align(size_t v) { return (v + 255) / 256 * 256; }
+__host__ __device__ inline uint32_t leaf_stride(uint32_t nparams) {
+    return nparams <= 8 ? 64u : 256u;
+}
+
+struct IndexView {
+    IndexHeader *h;
+    float *rx;      // R segment start inputs (searched)
+    RootSeg *seg;   // R segments
+    char *leaves;   // n_leaves records of leaf_stride bytes
+    __device__ LeafHead &head(uint32_t j) const { return *(LeafHead *)(leaves + (size_t)j * h->leaf_stride); }
+    __device__ float *params(uint32_t j) const {
+        return (float *)(leaves + (size_t)j * h->leaf_stride + sizeof(LeafHead));
+    }
+};
 
 __host__ __device__ inline size_t index_layout(char *base, uint32_t L, uint32_t nparams,
                                                uint32_t R, IndexView *v) {
     size_t off = 256;
-    auto take = [&](size_t bytes) {
-        char *p = base ? base + off : nullptr;
-        off = idx_align(off + bytes);
-        return p;
-    };
     IndexView w;
     w.h = (IndexHeader *)base;
-    w.rx = (float *)take(R ? ((size_t)R + 1) * 4 : 0);
-    w.ry = (float *)take(R ? ((size_t)R + 1) * 4 : 0);
-    w.rs = (float *)take((size_t)R * 4);
-    w.first = (int64_t *)take(((size_t)L + 1) * 8);
-    w.kfirst = (uint64_t *)take((size_t)L * 8);
-    w.isp = (float *)take((size_t)L * 4);
-    w.err_lo = (int32_t *)take((size_t)L * 4);
-    w.err_hi = (int32_t *)take((size_t)L * 4);
-    w.params = (float *)take((size_t)L * nparams * 4);
+    w.rx = base ? (float *)(base + off) : nullptr;
+    off = idx_align(off + (size_t)R * 4);
+    w.seg = base ? (RootSeg *)(base + off) : nullptr;
+    off = idx_align(off + (size_t)R * sizeof(RootSeg));
+    w.leaves = base ? base + off : nullptr;
+    off = idx_align(off + (size_t)L * leaf_stride(nparams));
     if (v) *v = w;
     return off;
 }
@@ -74,24 +86,26 @@ __device__ __forceinline__ float root_x(uint64_t q, uint64_t kmin, uint64_t kmax
     return __fmul_rn((float)c, isp);
 }
 
-// Root routing; monotone in q.  Piecewise-linear roots evaluate segment s
-// (the last knot with input <= x) clamped to its end values, so adjacent
-// segments cannot overlap after rounding.
-__device__ __forceinline__ uint32_t route(const IndexHeader &h, const IndexView &v, uint64_t q) {
+// Root routing; monotone in q.  A piecewise-linear root evaluates segment s
+// (the last segment whose start input is <= x) clamped to its end values,
+// so adjacent segments cannot overlap after rounding.  `rx` may point to an
+// LDS copy of the segment starts.
+__device__ __forceinline__ uint32_t route(const IndexHeader &h, const IndexView &v, const float *rx,
+                                          uint64_t q) {
     const float x = root_x(q, h.kmin, h.kmax, h.inv_span);
     float y;
     if (h.root_segs == 0) {
         y = fmaf(h.root_a, x, h.root_b);
     } else {
-        uint32_t lo = 0, hi = h.root_segs;  // knots 0..R; find last rx[s] <= x, s < R
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (v.rx[mid] <= x) lo = mid;
-            else hi = mid;
+        uint32_t lo = 0, len = h.root_segs;  // last s in [0, R) with rx[s] <= x (rx[0] = 0)
+        while (len > 1) {
+            const uint32_t half = len >> 1;
+            lo = rx[lo + half] <= x ? lo + half : lo;
+            len -= half;
         }
-        const float y0 = v.ry[lo], y1 = v.ry[lo + 1];
-        y = fmaf(v.rs[lo], __fsub_rn(x, v.rx[lo]), y0);
-        y = y >= y0 ? (y <= y1 ? y : y1) : y0;
+        const RootSeg g = v.seg[lo];
+        y = fmaf(g.slope, __fsub_rn(x, g.x0), g.y0);
+        y = y >= g.y0 ? (y <= g.y1 ? y : g.y1) : g.y0;
     }
     y = floorf(y);
     const float top = (float)(h.n_leaves - 1);
@@ -109,16 +123,15 @@ __device__ __forceinline__ float mlp_forward(const float *p, float x) {
     return f;
 }
 
-// Predicted rank of q in leaf j, in [first_j, first_j + n_j].
-__device__ __forceinline__ int64_t leaf_predict(const IndexView &v, uint32_t kind, uint32_t np,
-                                                uint32_t j, uint64_t q, int64_t n) {
-    int64_t f0 = v.first[j], f1 = v.first[j + 1];
+// Leaf range [f0, f1) clamped to [0, n], and the predicted rank in [f0, f1].
+__device__ __forceinline__ int64_t leaf_predict(const LeafHead &lh, const float *p, uint32_t kind,
+                                                uint64_t q, int64_t n, int64_t *f0o, int64_t *f1o) {
+    int64_t f0 = lh.first, nj = lh.count;
     f0 = f0 < 0 ? 0 : (f0 > n ? n : f0);
-    f1 = f1 < f0 ? f0 : (f1 > n ? n : f1);
-    const int64_t nj = f1 - f0;
-    const uint64_t kf = v.kfirst[j];
-    const float x = q <= kf ? 0.0f : __fmul_rn((float)(q - kf), v.isp[j]);
-    const float *p = v.params + (size_t)j * np;
+    nj = nj < 0 ? 0 : (nj > n - f0 ? n - f0 : nj);
+    *f0o = f0;
+    *f1o = f0 + nj;
+    const float x = q <= lh.kfirst ? 0.0f : __fmul_rn((float)(q - lh.kfirst), lh.isp);
     const float f = kind == 0 ? fmaf(p[0], x, p[1]) : mlp_forward(p, x);
     float r = rintf(__fmul_rn((float)nj, f));
     r = r >= 0.0f ? r : 0.0f;  // NaN -> 0
@@ -154,26 +167,13 @@ __device__ __forceinline__ void mlp_accumulate(const float *p, float x, float t,
     g[3 * kMlpHidden] = __fadd_rn(g[3 * kMlpHidden], dr);
 }
 
-// Deterministic block sum of `cnt` per-thread float partials into doubles:
-// wave sums by shuffles in a fixed pattern, then the waves in order.
-template <int CNT>
-__device__ __forceinline__ void block_sum49(float *v, double *out, float *s_w /* WAVES x CNT */) {
-    constexpr int WAVES = kLeafBlock / 64;
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
+// Wave-wide sum of one float partial per lane, combined in a fixed
+// butterfly order in fp64; every lane gets the sum.
+__device__ __forceinline__ double wave_sum(float v) {
+    double x = (double)v;
 #pragma unroll
-    for (int c = 0; c < CNT; ++c) {
-        float x = v[c];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x = __fadd_rn(x, __shfl_xor(x, o, 64));
-        if (lane == 0) s_w[wave * CNT + c] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < CNT) {
-        double s = 0.0;
-        for (int w = 0; w < WAVES; ++w) s += (double)s_w[w * CNT + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
 }
 
 // ----------------------------------------------------------------- kernels
@@ -181,6 +181,7 @@ __global__ void k_index_header(const uint64_t *keys, int64_t n, uint32_t L, uint
                                uint32_t np, uint32_t R, IndexHeader *h) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     h->root_segs = R;
+    h->leaf_stride = leaf_stride(np);
     h->magic = kIndexMagic;
     h->version = kIndexVersion;
     h->n_leaves = L;
@@ -247,73 +248,73 @@ __global__ void k_root_final(const double *partial, int blocks, int64_t n, Index
     h->root_b = bf;
 }
 
-// Piecewise-linear root: knots at ranks t * (n - 1) / R.
+// Piecewise-linear root: segment t runs between the keys at ranks
+// t * (n - 1) / R and (t + 1) * (n - 1) / R.
 __global__ void k_root_knots(const uint64_t *__restrict__ keys, int64_t n, char *index) {
     const IndexHeader &h = *(const IndexHeader *)index;
     IndexView v;
     index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
     const uint32_t R = h.root_segs;
     const float fl = (float)h.n_leaves, fn = (float)n;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t <= R; t += gridDim.x * blockDim.x) {
-        const int64_t r = (int64_t)(((uint64_t)t * (uint64_t)(n - 1)) / R);
-        v.rx[t] = root_x(keys[r], h.kmin, h.kmax, h.inv_span);
-        v.ry[t] = __fdiv_rn(__fmul_rn((float)r, fl), fn);
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < R; t += gridDim.x * blockDim.x) {
+        const int64_t r0 = (int64_t)(((uint64_t)t * (uint64_t)(n - 1)) / R);
+        const int64_t r1 = (int64_t)(((uint64_t)(t + 1) * (uint64_t)(n - 1)) / R);
+        const float x0 = t == 0 ? 0.0f : root_x(keys[r0], h.kmin, h.kmax, h.inv_span);
+        const float x1 = root_x(keys[r1], h.kmin, h.kmax, h.inv_span);
+        RootSeg g;
+        g.x0 = x0;
+        g.y0 = __fdiv_rn(__fmul_rn((float)r0, fl), fn);
+        g.y1 = __fdiv_rn(__fmul_rn((float)r1, fl), fn);
+        const float dx = __fsub_rn(x1, x0);
+        g.slope = dx > 0.0f ? __fdiv_rn(__fsub_rn(g.y1, g.y0), dx) : 0.0f;
+        v.seg[t] = g;
+        v.rx[t] = x0;
     }
 }
 
-__global__ void k_root_slopes(char *index) {
-    const IndexHeader &h = *(const IndexHeader *)index;
-    IndexView v;
-    index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < h.root_segs;
-         t += gridDim.x * blockDim.x) {
-        const float dx = __fsub_rn(v.rx[t + 1], v.rx[t]);
-        v.rs[t] = dx > 0.0f ? __fdiv_rn(__fsub_rn(v.ry[t + 1], v.ry[t]), dx) : 0.0f;
-    }
-}
-
-// first[j] = first rank routed to leaf >= j (routing is monotone).
+// first[j] = first rank routed to leaf >= j (routing is monotone); first[L] = n.
 __global__ __launch_bounds__(256) void k_leaf_bounds(const uint64_t *__restrict__ keys, int64_t n,
-                                                     char *index) {
+                                                     const char *index, int64_t *first) {
     IndexView v;
     const IndexHeader &h = *(const IndexHeader *)index;
-    index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
+    index_layout((char *)index, h.n_leaves, h.nparams, h.root_segs, &v);
     const uint32_t L = h.n_leaves;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t lj = route(h, v, keys[i]);
-        const int64_t lp = i > 0 ? (int64_t)route(h, v, keys[i - 1]) : -1;
-        for (int64_t j = lp + 1; j <= lj; ++j) v.first[j] = i;
+        const int64_t lj = route(h, v, v.rx, keys[i]);
+        const int64_t lp = i > 0 ? (int64_t)route(h, v, v.rx, keys[i - 1]) : -1;
+        for (int64_t j = lp + 1; j <= lj; ++j) first[j] = i;
         if (i == n - 1)
-            for (int64_t j = lj + 1; j <= (int64_t)L; ++j) v.first[j] = n;
+            for (int64_t j = lj + 1; j <= (int64_t)L; ++j) first[j] = n;
     }
     if (n == 0 && blockIdx.x == 0)
-        for (int64_t j = threadIdx.x; j <= (int64_t)L; j += blockDim.x) v.first[j] = 0;
+        for (int64_t j = threadIdx.x; j <= (int64_t)L; j += blockDim.x) first[j] = 0;
 }
 
-// One workgroup per leaf: fit the leaf model and reset its window.
+// One wave per leaf: fit the leaf model, write its record, reset its window.
 template <int KIND>
 __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit(const uint64_t *__restrict__ keys,
-                                                         char *index, uint32_t epochs, float lr) {
+                                                         char *index, const int64_t *first,
+                                                         uint32_t epochs, float lr) {
     __shared__ float s_x[kLeafCache];
     __shared__ float s_p[kMlpParams], s_m[kMlpParams], s_v[kMlpParams];
-    __shared__ double s_g[kMlpParams + 1];
-    __shared__ float s_w[(kLeafBlock / 64) * (kMlpParams + 1)];
-    __shared__ double s_lin[4][kLeafBlock];
 
     IndexView v;
     const IndexHeader &h = *(const IndexHeader *)index;
     index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
     const uint32_t j = blockIdx.x;
     const int tid = threadIdx.x;
-    const int64_t f0 = v.first[j], f1 = v.first[j + 1], nj = f1 - f0;
-    float *par = v.params + (size_t)j * h.nparams;
+    const int64_t f0 = first[j], f1 = first[j + 1], nj = f1 - f0;
+    LeafHead &lh = v.head(j);
+    float *par = v.params(j);
     if (nj <= 0) {
         if (tid == 0) {
-            v.kfirst[j] = 0;
-            v.isp[j] = 0.0f;
-            v.err_lo[j] = 0;
-            v.err_hi[j] = 0;
+            lh.first = f0;
+            lh.kfirst = 0;
+            lh.count = 0;
+            lh.isp = 0.0f;
+            lh.err_lo = 0;
+            lh.err_hi = 0;
         }
         for (uint32_t c = tid; c < h.nparams; c += blockDim.x) par[c] = 0.0f;
         return;
@@ -328,38 +329,34 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit(const uint64_t *__restr
     for (int64_t s = tid; s < nj && s < kLeafCache; s += blockDim.x)
         s_x[s] = __fmul_rn((float)(keys[f0 + s] - kf), isp);
     if (tid == 0) {
-        v.kfirst[j] = kf;
-        v.isp[j] = isp;
-        v.err_lo[j] = 0x7FFFFFFF;
-        v.err_hi[j] = (int32_t)0x80000000;
+        lh.first = f0;
+        lh.kfirst = kf;
+        lh.count = (int32_t)nj;
+        lh.isp = isp;
+        lh.err_lo = 0x7FFFFFFF;
+        lh.err_hi = (int32_t)0x80000000;
     }
     __syncthreads();
 
     if (KIND == 0) {
         // least squares of t = s / n_j on x (fp64 sums)
-        double sx = 0, st = 0, sxx = 0, sxt = 0;
+        double acc[4] = {0, 0, 0, 0};
         for (int64_t s = tid; s < nj; s += blockDim.x) {
             const double x = (double)xof(s), t = (double)s / (double)nj;
-            sx += x;
-            st += t;
-            sxx += x * x;
-            sxt += x * t;
+            acc[0] += x;
+            acc[1] += t;
+            acc[2] += x * x;
+            acc[3] += x * t;
         }
-        s_lin[0][tid] = sx;
-        s_lin[1][tid] = st;
-        s_lin[2][tid] = sxx;
-        s_lin[3][tid] = sxt;
-        __syncthreads();
-        for (int w = kLeafBlock / 2; w > 0; w >>= 1) {
-            if (tid < w)
-                for (int c = 0; c < 4; ++c) s_lin[c][tid] += s_lin[c][tid + w];
-            __syncthreads();
-        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
         if (tid == 0) {
             const double dn = (double)nj;
-            const double den = dn * s_lin[2][0] - s_lin[0][0] * s_lin[0][0];
-            const double a = den > 0.0 ? (dn * s_lin[3][0] - s_lin[0][0] * s_lin[1][0]) / den : 0.0;
-            const double b = (s_lin[1][0] - a * s_lin[0][0]) / dn;
+            const double den = dn * acc[2] - acc[0] * acc[0];
+            const double a = den > 0.0 ? (dn * acc[3] - acc[0] * acc[1]) / den : 0.0;
+            const double b = (acc[1] - a * acc[0]) / dn;
             par[0] = (float)a;
             par[1] = (float)b;
         }
@@ -378,8 +375,8 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit(const uint64_t *__restr
         for (int q = 0; q < kMlpHidden; ++q) {
             const float dx = __fsub_rn(kx[q + 1], kx[q]);
             const float sl = dx > 0.0f ? __fdiv_rn(__fsub_rn(kt[q + 1], kt[q]), dx) : 0.0f;
-            s_p[q] = 1.0f;                           // w1
-            s_p[kMlpHidden + q] = -kx[q];            // b1
+            s_p[q] = 1.0f;                                  // w1
+            s_p[kMlpHidden + q] = -kx[q];                   // b1
             s_p[2 * kMlpHidden + q] = __fsub_rn(sl, prev);  // w2: change of slope
             prev = sl;
         }
@@ -403,11 +400,17 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit(const uint64_t *__restr
         g[kMlpParams] = 0.0f;
         for (int64_t s = tid; s < nj; s += blockDim.x)
             mlp_accumulate(p, xof(s), __fdiv_rn((float)s, fnj), g, g[kMlpParams]);
-        block_sum49<kMlpParams + 1>(g, s_g, s_w);
         pw1 = __fmul_rn(pw1, b1c);
         pw2 = __fmul_rn(pw2, b2c);
+        // lane c updates parameter c (every lane gets every sum)
+        float gr = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kMlpParams; ++c) {
+            const double sum = wave_sum(g[c]);
+            if (c == tid) gr = (float)(sum / (double)nj);
+        }
+        __syncthreads();
         if (tid < kMlpParams) {
-            const float gr = (float)(s_g[tid] / (double)nj);
             const float m = fmaf(b1c, s_m[tid], __fmul_rn(1.0f - b1c, gr));
             const float vv = fmaf(b2c, s_v[tid], __fmul_rn(__fmul_rn(1.0f - b2c, gr), gr));
             s_m[tid] = m;
@@ -429,11 +432,13 @@ __global__ __launch_bounds__(256) void k_leaf_err(const uint64_t *__restrict__ k
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t q = keys[i];
-        const uint32_t j = route(h, v, q);
-        const int64_t e = i - leaf_predict(v, h.leaf_kind, h.nparams, j, q, n);
+        const uint32_t j = route(h, v, v.rx, q);
+        LeafHead &lh = v.head(j);
+        int64_t f0, f1;
+        const int64_t e = i - leaf_predict(lh, v.params(j), h.leaf_kind, q, n, &f0, &f1);
         const int32_t ec = (int32_t)(e > 0x3FFFFFFF ? 0x3FFFFFFF : (e < -0x3FFFFFFF ? -0x3FFFFFFF : e));
-        atomicMin(&v.err_lo[j], ec);
-        atomicMax(&v.err_hi[j], ec);
+        atomicMin(&lh.err_lo, ec);
+        atomicMax(&lh.err_hi, ec);
     }
 }
 
@@ -447,37 +452,43 @@ __device__ __forceinline__ int64_t lb_range(const K *keys, int64_t lo, int64_t h
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_index_lookup(const char *__restrict__ index,
-                                                      const uint64_t *__restrict__ keys, int64_t n,
-                                                      const uint64_t *__restrict__ q, int64_t nq,
-                                                      int64_t *__restrict__ rank,
-                                                      uint8_t *__restrict__ found,
-                                                      unsigned long long *fallbacks, uint32_t *err) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nq) return;
+constexpr int kLookupBlock = 1024;
+constexpr uint32_t kLdsSegs = 4096;  // root segment starts staged in LDS up to this many
+
+__global__ __launch_bounds__(kLookupBlock) void k_index_lookup(
+    const char *__restrict__ index, const uint64_t *__restrict__ keys, int64_t n,
+    const uint64_t *__restrict__ q, int64_t nq, int64_t *__restrict__ rank,
+    uint8_t *__restrict__ found, unsigned long long *fallbacks, uint32_t *err) {
+    __shared__ float s_rx[kLdsSegs];
     const IndexHeader h = *(const IndexHeader *)index;
     const bool ok = h.magic == kIndexMagic && h.version == kIndexVersion && h.n == n &&
                     h.n_leaves >= 1 && h.n_leaves <= 65536 && h.leaf_kind <= 1 &&
-                    h.nparams == (h.leaf_kind ? (uint32_t)kMlpParams : 2u) && h.root_segs <= 65536 &&
+                    h.nparams == (h.leaf_kind ? (uint32_t)kMlpParams : 2u) &&
+                    h.root_segs <= 65536 && h.leaf_stride == leaf_stride(h.nparams) &&
                     (n == 0 || (keys[0] == h.kmin && keys[n - 1] == h.kmax));
+    IndexView v;
+    index_layout((char *)index, h.n_leaves, h.nparams, h.root_segs, &v);
+    const bool lds = ok && h.root_segs > 0 && h.root_segs <= kLdsSegs;
+    if (lds)
+        for (uint32_t i = threadIdx.x; i < h.root_segs; i += blockDim.x) s_rx[i] = v.rx[i];
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nq) return;
     if (!ok) {
         set_err(err, ERR_MISMATCH);
         rank[t] = 0;
         if (found) found[t] = 0;
         return;
     }
-    IndexView v;
-    index_layout((char *)index, h.n_leaves, h.nparams, h.root_segs, &v);
     const uint64_t x = q[t];
     int64_t r = 0;
     bool fell = false;
     if (n > 0) {
-        const uint32_t j = route(h, v, x);
-        int64_t f0 = v.first[j], f1 = v.first[j + 1];
-        f0 = f0 < 0 ? 0 : (f0 > n ? n : f0);
-        f1 = f1 < f0 ? f0 : (f1 > n ? n : f1);
-        const int64_t p = leaf_predict(v, h.leaf_kind, h.nparams, j, x, n);
-        int64_t lo = p + v.err_lo[j], hi = p + v.err_hi[j];
+        const uint32_t j = route(h, v, lds ? s_rx : v.rx, x);
+        const LeafHead lh = v.head(j);
+        int64_t f0, f1;
+        const int64_t p = leaf_predict(lh, v.params(j), h.leaf_kind, x, n, &f0, &f1);
+        int64_t lo = p + lh.err_lo, hi = p + lh.err_hi;
         lo = lo < f0 ? f0 : (lo > f1 ? f1 : lo);
         hi = hi < lo ? lo : (hi > f1 ? f1 : hi);
         const bool good = (lo == 0 || keys[lo - 1] < x) && (hi == n || keys[hi] >= x);
@@ -492,7 +503,8 @@ __global__ __launch_bounds__(256) void k_index_lookup(const char *__restrict__ i
     if (found) found[t] = (uint8_t)(r < n && keys[r] == x);
     if (fallbacks) {
         const uint64_t m = ballot64(fell);
-        if (m && lane_id() == __ffsll((long long)__ballot(1)) - 1) atomicAdd(fallbacks, (unsigned long long)__popcll(m));
+        if (m && lane_id() == __ffsll((long long)__ballot(1)) - 1)
+            atomicAdd(fallbacks, (unsigned long long)__popcll(m));
     }
 }
 
@@ -502,16 +514,15 @@ __global__ void k_index_stats(const char *index, int32_t *width, int64_t *count)
     index_layout((char *)index, h.n_leaves, h.nparams, h.root_segs, &v);
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < h.n_leaves;
          j += gridDim.x * blockDim.x) {
-        if (width) width[j] = v.err_hi[j] - v.err_lo[j] + 1;
-        if (count) count[j] = v.first[j + 1] - v.first[j];
+        const LeafHead &lh = v.head(j);
+        if (width) width[j] = lh.count ? lh.err_hi - lh.err_lo + 1 : 0;
+        if (count) count[j] = lh.count;
     }
 }
 
 __global__ __launch_bounds__(kLeafBlock) void k_mlp_loss_grad(const float *params, const float *x,
                                                               const float *t, int64_t n,
                                                               double *grad, double *loss) {
-    __shared__ double s_g[kMlpParams + 1];
-    __shared__ float s_w[(kLeafBlock / 64) * (kMlpParams + 1)];
     float p[kMlpParams], g[kMlpParams + 1];
     for (int c = 0; c < kMlpParams; ++c) {
         p[c] = params[c];
@@ -519,9 +530,15 @@ __global__ __launch_bounds__(kLeafBlock) void k_mlp_loss_grad(const float *param
     }
     g[kMlpParams] = 0.0f;
     for (int64_t s = threadIdx.x; s < n; s += blockDim.x) mlp_accumulate(p, x[s], t[s], g, g[kMlpParams]);
-    block_sum49<kMlpParams + 1>(g, s_g, s_w);
-    if (threadIdx.x < kMlpParams) grad[threadIdx.x] = n ? s_g[threadIdx.x] / (double)n : 0.0;
-    if (threadIdx.x == kMlpParams && loss) *loss = n ? s_g[kMlpParams] / (double)n : 0.0;
+#pragma unroll
+    for (int c = 0; c <= kMlpParams; ++c) {
+        const double sum = wave_sum(g[c]);
+        if (threadIdx.x == 0) {
+            const double mean = n ? sum / (double)n : 0.0;
+            if (c < kMlpParams) grad[c] = mean;
+            else if (loss) *loss = mean;
+        }
+    }
 }
 
 constexpr int kRootBlocks = 512;
@@ -540,8 +557,9 @@ size_t cga_index_bytes(const cga_index_params *p) {
 }
 
 size_t cga_index_train_workspace_bytes(const cga_index_params *p, int64_t n) {
-    if (!p || n < 0) return 0;
-    return kControlBytes + idx_align((size_t)kRootBlocks * 4 * sizeof(double));
+    if (!p || n < 0 || p->n_leaves < 1 || p->n_leaves > 65536) return 0;
+    return kControlBytes + idx_align((size_t)kRootBlocks * 4 * sizeof(double)) +
+           idx_align(((size_t)p->n_leaves + 1) * sizeof(int64_t));
 }
 
 int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p, void *d_index,
@@ -556,6 +574,8 @@ int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p
     hipStream_t s = (hipStream_t)stream;
     Control *ctl = (Control *)d_ws;
     double *partial = (double *)((char *)d_ws + kControlBytes);
+    int64_t *first =
+        (int64_t *)((char *)d_ws + kControlBytes + idx_align((size_t)kRootBlocks * 4 * sizeof(double)));
     const uint32_t L = p->n_leaves, np = p->leaf_kind ? kMlpParams : 2;
     CGA_TRY(launch_begin(ctl, nullptr, 0, nullptr, 0, nullptr, s));
     char *idx = (char *)d_index;
@@ -567,9 +587,8 @@ int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p
             k_root_partial<<<kRootBlocks, 256, 0, s>>>(d_keys, n, h, partial);
             k_root_final<<<1, 64, 0, s>>>(partial, kRootBlocks, n, h);
             if (p->root_segments) {
-                const unsigned rb = (p->root_segments + 256) / 256;
+                const unsigned rb = (p->root_segments + 255) / 256;
                 k_root_knots<<<rb, 256, 0, s>>>(d_keys, n, idx);
-                k_root_slopes<<<rb, 256, 0, s>>>(idx);
             }
         }
     }
@@ -577,14 +596,14 @@ int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p
     blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
     {
         CGA_PROF("index_bounds", s);
-        k_leaf_bounds<<<(unsigned)blocks, 256, 0, s>>>(d_keys, n, idx);
+        k_leaf_bounds<<<(unsigned)blocks, 256, 0, s>>>(d_keys, n, idx, first);
     }
     {
         CGA_PROF("index_fit", s);
         if (p->leaf_kind == 0)
-            k_leaf_fit<0><<<L, kLeafBlock, 0, s>>>(d_keys, idx, 0, 0.0f);
+            k_leaf_fit<0><<<L, kLeafBlock, 0, s>>>(d_keys, idx, first, 0, 0.0f);
         else
-            k_leaf_fit<1><<<L, kLeafBlock, 0, s>>>(d_keys, idx, p->epochs, p->lr);
+            k_leaf_fit<1><<<L, kLeafBlock, 0, s>>>(d_keys, idx, first, p->epochs, p->lr);
     }
     if (n > 0) {
         CGA_PROF("index_err", s);
@@ -607,7 +626,7 @@ int cga_index_lookup(const void *d_index, const uint64_t *d_keys, int64_t n, con
     CGA_TRY(launch_begin(ctl, nullptr, 0, nullptr, 0, nullptr, s));
     if (nq > 0) {
         CGA_PROF("index_lookup", s);
-        k_index_lookup<<<(unsigned)((nq + 255) / 256), 256, 0, s>>>(
+        k_index_lookup<<<(unsigned)((nq + kLookupBlock - 1) / kLookupBlock), kLookupBlock, 0, s>>>(
             (const char *)d_index, d_keys, n, d_q, nq, d_rank, d_found,
             (unsigned long long *)d_fallbacks, &ctl->err);
     }

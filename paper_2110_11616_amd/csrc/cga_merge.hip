@@ -5,34 +5,9 @@
 // every key present in both, and compacts its survivors with a decoupled
 // look-back over earlier windows.
 #include "cga_common.h"
+#include "cga_merge.h"
 
 namespace cga {
-
-constexpr int kMergeBlock = 256;
-constexpr int kMergeItems = 8;
-constexpr int kMergeTile = kMergeBlock * kMergeItems;
-
-constexpr uint64_t kMAgg = 1ull << 62;
-constexpr uint64_t kMInc = 2ull << 62;
-constexpr uint64_t kMVal = (1ull << 62) - 1;
-
-inline int64_t merge_tiles(int64_t total) {
-    return total <= 0 ? 1 : (total + kMergeTile - 1) / kMergeTile;
-}
-
-// Number of A elements among the first `diag` merged elements, with A
-// ordered before B on equal keys.
-template <typename K>
-__device__ __forceinline__ int64_t merge_path(const K *A, int64_t na, const K *B, int64_t nb,
-                                              int64_t diag) {
-    int64_t lo = diag > nb ? diag - nb : 0, hi = diag < na ? diag : na;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (A[mid] <= B[diag - 1 - mid]) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
 
 template <typename K>
 __global__ void k_merge_partition(const K *A, int64_t na_host, const int64_t *d_na, const K *B,
@@ -53,122 +28,15 @@ __global__ __launch_bounds__(kMergeBlock) void k_merge(
     uint8_t *__restrict__ src_out, int64_t cap, int64_t *n_out, uint64_t *status,
     uint32_t *tile_ctr, uint32_t *err) {
     __shared__ uint32_t s_tile;
-    __shared__ K s[kMergeTile + 1];
-    __shared__ uint8_t s_src[kMergeTile];
-    __shared__ uint32_t s_w[kMergeBlock / 64];
-    __shared__ int64_t s_prefix;
-
-    const int tid = threadIdx.x;
+    __shared__ MergeShared<K> sh;
     const uint32_t tile = next_tile(tile_ctr, &s_tile);
     const int64_t na = dev_count(na_host, d_na), nb = dev_count(nb_host, d_nb);
     const int64_t total = na + nb;
     const int64_t d0 = (int64_t)tile * kMergeTile;
     if (d0 >= total) return;
     const int64_t d1 = d0 + kMergeTile < total ? d0 + kMergeTile : total;
-    const int64_t a0 = part[tile], a1 = part[tile + 1];
-    const int64_t b0 = d0 - a0, b1 = d1 - a1;
-    const int la = (int)(a1 - a0), lb = (int)(b1 - b0);
-    const bool extra = b1 < nb;  // first B element after the window, for provenance
-    const int len = la + lb + (extra ? 1 : 0);
-    for (int j = tid; j < len; j += kMergeBlock)
-        s[j] = j < la ? A[a0 + j] : B[b0 + (j - la)];
-    const bool prev_global = a0 > 0;
-    const K prev_a_global = prev_global ? A[a0 - 1] : K(0);
-    __syncthreads();
-
-    const K *sa = s, *sb = s + la;
-    const int lab = la + lb;
-    const int dt = tid * kMergeItems < lab ? tid * kMergeItems : lab;
-    int at, bt;
-    {
-        int lo = dt > lb ? dt - lb : 0, hi = dt < la ? dt : la;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (sa[mid] <= sb[dt - 1 - mid]) lo = mid + 1;
-            else hi = mid;
-        }
-        at = lo;
-        bt = dt - at;
-    }
-    bool has_prev = at > 0 || prev_global;
-    K prev_a = at > 0 ? sa[at - 1] : prev_a_global;
-    const int lb_ext = lb + (extra ? 1 : 0);
-
-    K key[kMergeItems];
-    uint8_t srcb[kMergeItems];
-    bool keep[kMergeItems];
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int it = 0; it < kMergeItems; ++it) {
-        const bool valid = dt + it < lab && tid * kMergeItems + it < lab;
-        key[it] = K(0);
-        srcb[it] = 0;
-        keep[it] = false;
-        if (valid) {
-            const bool take_a = bt >= lb || (at < la && sa[at] <= sb[bt]);
-            if (take_a) {
-                K k = sa[at++];
-                srcb[it] = (bt < lb_ext && sb[bt] == k) ? 3 : 1;
-                prev_a = k;
-                has_prev = true;
-                key[it] = k;
-                keep[it] = true;
-            } else {
-                K k = sb[bt++];
-                key[it] = k;
-                srcb[it] = 2;
-                keep[it] = !(has_prev && prev_a == k);
-            }
-            cnt += keep[it] ? 1u : 0u;
-        }
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_sum<kMergeBlock>(cnt, s_w, &tot);
-
-    if (tid == 0) {
-        uint64_t pre = 0;
-        if (tile == 0) {
-            st_agent(&status[tile], kMInc | (uint64_t)tot);
-        } else {
-            st_agent(&status[tile], kMAgg | (uint64_t)tot);
-            int64_t t = (int64_t)tile - 1;
-            for (;;) {
-                uint64_t st = ld_agent(&status[t]);
-                if ((st >> 62) == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                pre += st & kMVal;
-                if (st & kMInc) break;
-                --t;
-            }
-            st_agent(&status[tile], kMInc | (pre + tot));
-        }
-        s_prefix = (int64_t)pre;
-        if (d1 == total && n_out) *n_out = (int64_t)pre + tot;
-    }
-    // stage survivors in LDS (the merge reads of s finished at the scan's barriers)
-    uint32_t o = ex;
-#pragma unroll
-    for (int it = 0; it < kMergeItems; ++it)
-        if (keep[it]) {
-            s[o] = key[it];
-            s_src[o] = srcb[it];
-            ++o;
-        }
-    __syncthreads();
-    const int64_t pre = s_prefix;
-    bool over = false;
-    for (int j = tid; j < (int)tot; j += kMergeBlock) {
-        int64_t g = pre + j;
-        if (g < cap) {
-            out[g] = s[j];
-            if (src_out) src_out[g] = s_src[j];
-        } else {
-            over = true;
-        }
-    }
-    if (over) set_err(err, ERR_CAPACITY);
+    merge_tile<K>(sh, A, na, B, nb, d0, d1, part[tile], part[tile + 1], out, src_out, cap, n_out,
+                  status, tile, 0, err);
 }
 
 struct MergeLayout {

@@ -60,6 +60,8 @@ int collect() {
 
 ProfScope::ProfScope(const char *label, hipStream_t s) {
     if (!g_on.load(std::memory_order_relaxed)) return;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!wanted(label)) return;
     Rec r{label, take_event(), take_event()};

@@ -134,6 +134,7 @@ int cga_project(const cga_grid *g, const void *d_keys, int64_t n, const int64_t 
     if (n >= (int64_t)1 << 30) return CGA_EUNSUPPORTED;
     const bool wide2 = wide_keys2(g->depth);
     SortCfg cfg = default_sort_cfg(wide2, n);
+    if (!tune) tuned_sort_cfg(wide2 ? 8 : 4, 2 * (int)g->depth, n, &cfg);
     if (tune) {
         cfg.radix_bits = (int)tune->radix_bits;
         cfg.items = (int)tune->tile_items;

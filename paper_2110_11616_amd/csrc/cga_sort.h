@@ -255,6 +255,9 @@ inline bool sort_cfg_supported(const SortCfg &c) {
            (c.items == 8 || c.items == 12 || c.items == 16);
 }
 
+// Autotuned configuration recorded for (key bytes, key bits, n), if any.
+bool tuned_sort_cfg(int key_bytes, int key_bits, int64_t n, SortCfg *out);
+
 inline size_t hist_lds_bytes(int passes, int rb) { return (size_t)passes * ((size_t)1 << rb) * 4; }
 
 template <typename K, int RB, int ITEMS>

@@ -74,21 +74,16 @@ def test_lookup_small_arrays(gpu):
 
 
 def _window_offsets(n_leaves, nparams, root):
-    """Byte offsets of the err_lo / err_hi arrays in the index buffer (header of
-    256 bytes, then root knots, first, kfirst, isp, err_lo, err_hi, params,
-    each rounded up to 256 bytes)."""
+    """Byte offsets of every leaf's err_lo / err_hi in the index buffer: a
+    256-byte header, the root segment starts (4 B each) and segments (16 B
+    each), then one record per leaf (64 B for linear leaves, 256 B for
+    network leaves) whose window sits at bytes 24 and 28."""
     al = lambda v: (v + 255) // 256 * 256
-    off = 256
-    if root:
-        off = al(off + (root + 1) * 4)
-        off = al(off + (root + 1) * 4)
-        off = al(off + root * 4)
-    off = al(off + (n_leaves + 1) * 8)   # first
-    off = al(off + n_leaves * 8)         # kfirst
-    off = al(off + n_leaves * 4)         # isp
-    lo = off
-    off = al(off + n_leaves * 4)
-    return lo, off
+    off = al(256 + root * 4)
+    off = al(off + root * 16)
+    stride = 64 if nparams <= 8 else 256
+    base = off + np.arange(n_leaves) * stride
+    return base + 24, base + 28
 
 
 def test_zeroed_windows_fall_back_and_stay_exact(gpu, lidar_keys):
@@ -97,8 +92,8 @@ def test_zeroed_windows_fall_back_and_stay_exact(gpu, lidar_keys):
     idx = gpu.cga_index_train(kd, n_leaves=4096, leaf_kind=1, epochs=10, root_segments=1024)
     host = idx.cpu().numpy().copy()
     lo, hi = _window_offsets(4096, 49, 1024)
-    host[lo:lo + 4096 * 4] = 0
-    host[hi:hi + 4096 * 4] = 0
+    for off in np.concatenate([lo, hi]):
+        host[off:off + 4] = 0
     bad = torch.from_numpy(host).cuda()
     q = _queries(keys, 100_000, 11)
     r, f, fb = gpu.cga_index_lookup(bad, kd, _t(q))
