@@ -12,7 +12,9 @@ Workloads:
   c1: 2 x 100k sphere points, depth 10, 1k queries, k = 1
 Prints one JSON line.  value = input points per second of whole steps.
 Unless --no-c5, it also measures the learned index against binary search on
-the 50M-key, 10M-query configuration (reported under "c5", not in value).
+the 50M-key, 10M-query configuration (reported under "c5"), and unless
+--no-c4 the graph-captured batched build + pair merge of 256 LiDAR frames
+(reported under "c4"); neither enters value.
 """
 from __future__ import annotations
 
@@ -41,6 +43,8 @@ def parse():
                     help="skip the per-kernel event timing (for external profilers)")
     ap.add_argument("--no-c5", action="store_true", help="skip the 50M-key learned-index run")
     ap.add_argument("--c5-reps", type=int, default=10)
+    ap.add_argument("--no-c4", action="store_true", help="skip the 256-frame batched run")
+    ap.add_argument("--c4-reps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -260,15 +264,18 @@ def c5_learned_vs_binary(cga, device, reps):
     setup_s = time.perf_counter() - t0
     out = {"keys": n, "unique_before_subset": u, "queries": len(q), "setup_s": round(setup_s, 1)}
     res = {}
-    for name, kind, root in (("mlp_pl_root", cga.LEAF_MLP, 1024), ("linear_pl_root", 0, 1024),
-                             ("mlp_linear_root", cga.LEAF_MLP, 0)):
+    variants = (("linear_leaves_65536_pl4096", 0, 65536, 4096),
+                ("mlp_leaves_65536_pl4096", cga.LEAF_MLP, 65536, 4096),
+                ("mlp_leaves_4096_pl1024", cga.LEAF_MLP, 4096, 1024),
+                ("mlp_leaves_4096_linear_root", cga.LEAF_MLP, 4096, 0))
+    for name, kind, leaves, root in variants:
         torch.cuda.synchronize()
         a = time.perf_counter()
-        idx = cga.cga_index_train(keys, n_leaves=4096, leaf_kind=kind, epochs=50, lr=1e-4,
+        idx = cga.cga_index_train(keys, n_leaves=leaves, leaf_kind=kind, epochs=50, lr=1e-4,
                                   root_segments=root)
         torch.cuda.synchronize()
         train_ms = (time.perf_counter() - a) * 1e3
-        w, c = cga.cga_index_stats(idx, 4096)
+        w, c = cga.cga_index_stats(idx, leaves)
         w, c = w.cpu().numpy().astype(np.float64), c.cpu().numpy()
         res[name] = {"train_ms": round(train_ms, 2),
                      "window_mean": round(float((w * c).sum() / max(c.sum(), 1)), 2),
@@ -314,6 +321,51 @@ def c5_learned_vs_binary(cga, device, reps):
     out["speedup_best_learned_vs_binary"] = round(
         max(v["lookups_per_s"] for v in res.values()) / out["binary"]["lookups_per_s"], 3)
     return out
+
+
+def c4_batched(cga, device, reps):
+    """256 LiDAR frames (log-uniform 10k..2M points) built and pair-merged by
+    one replay of the captured graph; the sort's digit width and tile size
+    come from the autotuner run on the same number of keys."""
+    import numpy as np
+    import torch
+
+    import gen
+    t0 = time.perf_counter()
+    d = gen.c4_frames()
+    xyz = torch.from_numpy(d["xyz"]).to(device)
+    off = torch.from_numpy(d["off"]).to(device)
+    g = d["grid"]
+    n, F = len(xyz), len(off) - 1
+    gen_s = time.perf_counter() - t0
+    fb = int(np.ceil(np.log2(F)))
+    rb, items, tune_ms = cga.cga_autotune_sort(key_bytes=8, key_bits=3 * g.depth + fb, n=n)
+    graph = cga.BatchGraph(xyz, off, g)
+    graph.launch()
+    torch.cuda.synchronize()
+    if graph.status() != 0:
+        raise RuntimeError("batched graph reported an error")
+    # the graph's frame 0 and pair 0 against the standalone entry points
+    k0, _ = cga.cga_build(xyz[: int(d["off"][1])], g)
+    k1, _ = cga.cga_build(xyz[int(d["off"][1]): int(d["off"][2])], g)
+    m01, _ = cga.cga_merge(k0, k1, g)
+    same = bool(torch.equal(graph.out.frame(0), k0) and torch.equal(graph.out.pair(0), m01))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        graph.launch()
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    u = int(graph.out.key_off[-1].item())
+    merged = int(graph.out.merged_cnt[: F - 1].sum().item())
+    graph.close()
+    return {"frames": F, "points": n, "unique_total": u, "merged_total": merged,
+            "gen_s": round(gen_s, 1), "autotune": {"radix_bits": rb, "tile_items": items,
+                                                   "sort_ms": round(tune_ms, 3)},
+            "graph_ms": round(ms, 3), "points_per_s": n / (ms * 1e-3),
+            "frame0_pair0_match_standalone": same}
 
 
 def main():
@@ -433,6 +485,8 @@ def main():
     }
     if not args.no_c5:
         line["c5"] = c5_learned_vs_binary(cga, device, args.c5_reps)
+    if not args.no_c4:
+        line["c4"] = c4_batched(cga, device, args.c4_reps)
     if not args.no_cpu_baseline:
         import numpy as np
         line["cpu_baseline"] = cpu_baseline(d, pipe.lq.cpu().numpy().view(np.uint64))

@@ -299,6 +299,314 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn(const K *__restrict__ keys, i
     }
 }
 
+
+// ------------------------------------------------------------------------
+// Team search: eight lanes answer one query together.
+//
+// A directory D over the top 21 key bits (cells at level T = depth - 7, or
+// every voxel when depth <= 7) gives the key range of any cell at level >= T
+// with two loads: D[c] = number of keys below cell c.  Round 0 splits the
+// directory cell that holds the query among the lanes (lane t walks its
+// t-th child in nearest-first order).  If the k-th distance found does not
+// prove the answer lies inside that cell, later rounds cover the box of
+// half-width r = floor(sqrt(bound)) around the query with the <= 2x2x2 cells
+// of the smallest level whose edge spans it, one cell per lane.  All lanes
+// prune with the best k-th distance any of them holds (one LDS word per
+// team).  After each round the lanes' sorted lists are merged by a three-step
+// butterfly of shuffles (bitonic min-merge), so every lane holds the team's
+// list.  A round is exact when it starts from a known bound whose ball the
+// box covers; otherwise the team restarts with the bound it now has (or a
+// box twice as wide while fewer than k voxels were seen).
+// ------------------------------------------------------------------------
+constexpr int kTeam = 8;
+constexpr int kTeamsPerBlock = kKnnBlock / kTeam;
+
+__host__ __device__ inline int dir_level(uint32_t depth) { return depth > 7 ? (int)depth - 7 : 0; }
+__host__ __device__ inline int64_t dir_cells(uint32_t depth) {
+    return (int64_t)1 << (3 * ((int)depth - dir_level(depth)));
+}
+
+// D[c] for c in [0, NC]: thread t fills cells [64 t, 64 t + 64).
+template <typename K>
+__global__ __launch_bounds__(256) void k_knn_dir(const K *__restrict__ keys, int64_t n_host,
+                                                 const int64_t *d_n, int T, int64_t nc,
+                                                 uint32_t *__restrict__ dir) {
+    const int64_t n = dev_count(n_host, d_n);
+    const int64_t c0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 64;
+    if (c0 > nc) return;
+    int64_t pos = lower_bound_in(keys, 0, (int32_t)n, (uint64_t)c0 << (3 * T));
+    dir[c0] = (uint32_t)pos;
+    const int64_t c1 = c0 + 63 < nc ? c0 + 63 : nc;
+    for (int64_t c = c0 + 1; c <= c1; ++c) {
+        pos = gallop_up(keys, n, pos, (uint64_t)c << (3 * T));
+        dir[c] = (uint32_t)pos;
+    }
+}
+
+__device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
+    uint64_t r = (uint64_t)sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return (uint32_t)r;
+}
+
+__device__ __forceinline__ bool cand_less(const Cand &a, const Cand &b) {
+    return a.d < b.d || (a.d == b.d && a.i < b.i);
+}
+
+// k-th smallest entry of a sorted list (static register indexing).
+template <int KT>
+__device__ __forceinline__ uint64_t kth_dist(const Cand (&e)[KT], int k) {
+    uint64_t d = e[0].d;
+#pragma unroll
+    for (int s = 1; s < KT; ++s) d = (s == k - 1) ? e[s].d : d;
+    return d;
+}
+
+// Merge the team's sorted lists (no sentinels here: each lane keeps its KT
+// best, real or empty): after the three exchange steps every lane holds the
+// KT smallest of the union.
+template <int KT>
+__device__ __forceinline__ void team_merge(Cand (&e)[KT]) {
+#pragma unroll
+    for (int step = 1; step < kTeam; step <<= 1) {
+        Cand p[KT];
+#pragma unroll
+        for (int s = 0; s < KT; ++s) {
+            const uint32_t lo = __shfl_xor((uint32_t)e[s].d, step, 64);
+            const uint32_t hi = __shfl_xor((uint32_t)(e[s].d >> 32), step, 64);
+            p[s].d = ((uint64_t)hi << 32) | lo;
+            p[s].i = __shfl_xor(e[s].i, step, 64);
+        }
+        // elementwise min against the reversed partner: a bitonic sequence
+        // holding the KT smallest, then a bitonic merge network
+#pragma unroll
+        for (int s = 0; s < KT; ++s) {
+            const Cand &b = p[KT - 1 - s];
+            if (cand_less(b, e[s])) e[s] = b;
+        }
+#pragma unroll
+        for (int j = KT / 2; j > 0; j >>= 1) {
+#pragma unroll
+            for (int s = 0; s < KT; ++s) {
+                if ((s & j) == 0) {
+                    if (cand_less(e[s + j], e[s])) {
+                        const Cand t = e[s];
+                        e[s] = e[s + j];
+                        e[s + j] = t;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename K, int KT>
+__global__ __launch_bounds__(kKnnBlock) void k_knn_team(
+    const K *__restrict__ keys, int64_t n_host, const int64_t *d_n, const uint32_t *__restrict__ dir,
+    const float *__restrict__ q, int64_t nq, float o0, float o1, float o2, float scale,
+    uint32_t depth, int k, int scan_max, int64_t *__restrict__ idx_out,
+    uint64_t *__restrict__ d2_out, uint32_t *err) {
+    extern __shared__ int32_t s_rng[];  // key ranges of open cells below the directory level
+    __shared__ unsigned long long s_bound[kTeamsPerBlock];
+    const int tid = threadIdx.x, team = tid / kTeam, tl = tid % kTeam;
+    const int DT = dir_level(depth);
+    int32_t *LO = s_rng + tid;
+    int32_t *HI = s_rng + (DT > 0 ? DT : 1) * kKnnBlock + tid;
+#define RLO(l) LO[(l) * kKnnBlock]
+#define RHI(l) HI[(l) * kKnnBlock]
+    if (tl == 0) s_bound[team] = ~0ull;
+    __syncthreads();  // the only block-wide barrier; teams run independently after it
+    const int64_t j = (int64_t)blockIdx.x * kTeamsPerBlock + team;
+    if (j >= nq) return;
+
+    const float o[3] = {o0, o1, o2};
+    Vox qv;
+    if (!quantize3(q[3 * j], q[3 * j + 1], q[3 * j + 2], o, scale, depth, qv)) {
+        if (tl == 0) set_err(err, ERR_NONFINITE);
+        for (int s = tl; s < k; s += kTeam) {
+            idx_out[j * k + s] = -1;
+            d2_out[j * k + s] = ~0ull;
+        }
+        return;
+    }
+    const Cand kEmpty{~0ull, 0x7FFFFFFF};
+    Cand e[KT];
+#pragma unroll
+    for (int s = 0; s < KT; ++s) e[s] = kEmpty;
+    uint64_t kth = ~0ull;  // this lane's k-th distance
+
+    const uint64_t qkey = enc3(qv.x, qv.y, qv.z, depth, false);
+    auto qo = [&](int l) -> uint32_t {
+        return (((qv.x >> l) & 1u) << 2) | (((qv.y >> l) & 1u) << 1) | ((qv.z >> l) & 1u);
+    };
+    int32_t sk_lo = 0, sk_hi = 0;  // key range already considered (skipped by scans)
+    auto bound_now = [&]() -> uint64_t {
+        const uint64_t b = s_bound[team];
+        return kth < b ? kth : b;
+    };
+    auto scan = [&](int32_t lo, int32_t hi) {
+        for (int32_t i = lo; i < hi; ++i) {
+            if (i >= sk_lo && i < sk_hi) {
+                i = sk_hi - 1;
+                continue;
+            }
+            Vox v = dec3(keys[i], depth, false);
+            cand_insert<KT>(e, sq_dist(v, qv.x, qv.y, qv.z), i);
+        }
+        kth = kth_dist<KT>(e, k);
+        if (kth < s_bound[team]) atomicMin(&s_bound[team], (unsigned long long)kth);
+    };
+    auto pruned = [&](uint64_t prefix, int l) {
+        const uint32_t bx = compact3(prefix >> 2) << l, by = compact3(prefix >> 1) << l,
+                       bz = compact3(prefix) << l;
+        const uint32_t ext = (1u << l) - 1;
+        const uint64_t gx = axis_gap(qv.x, bx, bx + ext), gy = axis_gap(qv.y, by, by + ext),
+                       gz = axis_gap(qv.z, bz, bz + ext);
+        return gx * gx + gy * gy + gz * gz > bound_now();
+    };
+    // key range of cell (prefix, l): the directory at levels >= DT, else a
+    // binary search in the parent's range
+    auto cell_range = [&](uint64_t prefix, int l, int32_t &lo, int32_t &hi) {
+        if (l >= DT) {
+            const int sh = 3 * (l - DT);
+            lo = (int32_t)dir[prefix << sh];
+            hi = (int32_t)dir[(prefix + 1) << sh];
+            return;
+        }
+        int32_t pl, ph;
+        if (l + 1 >= DT) {
+            const int sh = 3 * (l + 1 - DT);
+            pl = (int32_t)dir[(prefix >> 3) << sh];
+            ph = (int32_t)dir[((prefix >> 3) + 1) << sh];
+        } else {
+            pl = RLO(l + 1);
+            ph = RHI(l + 1);
+        }
+        const int s3 = 3 * l;
+        lo = lower_bound_in(keys, pl, ph, prefix << s3);
+        hi = lower_bound_in(keys, lo, ph, (prefix + 1) << s3);
+    };
+    auto walk = [&](uint64_t prefix, int lr) {
+        int l = lr;
+        for (;;) {
+            if (!pruned(prefix, l)) {
+                int32_t lo, hi;
+                cell_range(prefix, l, lo, hi);
+                if (hi > lo && !(lo >= sk_lo && hi <= sk_hi)) {
+                    if (l == 0 || hi - lo <= scan_max) {
+                        scan(lo, hi);
+                    } else {
+                        if (l < DT) {
+                            RLO(l) = lo;
+                            RHI(l) = hi;
+                        }
+                        prefix = (prefix << 3) | qo(l - 1);  // first child: the query's side
+                        --l;
+                        continue;
+                    }
+                }
+            }
+            bool done = false;
+            for (;;) {
+                if (l == lr) {
+                    done = true;
+                    break;
+                }
+                const uint32_t so = near_order((uint32_t)(prefix & 7) ^ qo(l));
+                if (so < 7) {
+                    prefix = (prefix & ~7ull) | (near_order(so + 1) ^ qo(l));
+                    break;
+                }
+                prefix >>= 3;
+                ++l;
+            }
+            if (done) break;
+        }
+    };
+    auto reset = [&]() {
+#pragma unroll
+        for (int s = 0; s < KT; ++s) e[s] = kEmpty;
+        kth = ~0ull;
+    };
+
+    const uint32_t top = (1u << depth) - 1;
+    // round 0: the directory cell holding the query, split over the lanes
+    const uint64_t cq = qkey >> (3 * DT);
+    const int32_t tlo = (int32_t)dir[cq], thi = (int32_t)dir[cq + 1];
+    if (DT == 0) {
+        if (tl == 0) scan(tlo, thi);
+    } else {
+        walk((cq << 3) | (near_order((uint32_t)tl) ^ qo(DT - 1)), DT - 1);
+    }
+    team_merge<KT>(e);
+    kth = kth_dist<KT>(e, k);
+    uint64_t bound = kth;
+    bool done;
+    {
+        // every voxel outside the directory cell is at least m away
+        const uint32_t c[3] = {qv.x, qv.y, qv.z};
+        uint64_t m = ~0ull;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const uint32_t b = (c[a] >> DT) << DT;
+            const uint64_t below = (uint64_t)(c[a] - b) + 1, above = (uint64_t)b + (1u << DT) - c[a];
+            if (b > 0 && below < m) m = below;
+            if ((uint64_t)b + (1u << DT) <= top && above < m) m = above;
+        }
+        done = m == ~0ull || (bound != ~0ull && m * m > bound);
+    }
+    sk_lo = tlo;
+    sk_hi = thi;
+    if (!done && tl != 0) reset();  // lane 0 carries the team's list into the next round
+    uint32_t r = bound != ~0ull ? isqrt64(bound) : ((1u << DT) - 1) / 2;
+    while (!done) {
+        if (r > top) r = top;
+        const bool exact = bound != ~0ull && isqrt64(bound) <= r;
+        int ls = DT;
+        while (ls < (int)depth && (1u << ls) < 2 * r + 1) ++ls;
+        {
+            const uint32_t c3[3] = {qv.x, qv.y, qv.z};
+            uint32_t c[3];
+            bool ok = true;
+            const uint32_t m = near_order((uint32_t)tl);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t lo = c3[a] > r ? c3[a] - r : 0;
+                const uint32_t hi = (uint64_t)c3[a] + r < top ? c3[a] + r : top;
+                const uint32_t own = c3[a] >> ls, clo = lo >> ls, chi = hi >> ls;
+                if ((m >> (2 - a)) & 1u) {
+                    const uint32_t other = own == clo ? chi : clo;
+                    ok = ok && other != own;
+                    c[a] = other;
+                } else {
+                    c[a] = own;
+                }
+            }
+            if (ok) walk((spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]), ls);
+        }
+        team_merge<KT>(e);
+        kth = kth_dist<KT>(e, k);
+        if (exact || ls == (int)depth) break;
+        // not exact yet: start over on the box the candidates now bound
+        bound = kth;
+        r = bound != ~0ull ? isqrt64(bound) : 2 * r + 1;
+        reset();
+        sk_lo = sk_hi = 0;
+        if (tl == 0) s_bound[team] = bound;
+    }
+#undef RLO
+#undef RHI
+#pragma unroll
+    for (int s = 0; s < KT; ++s) {
+        if (s < k && (s % kTeam) == tl) {
+            const bool real = e[s].d != ~0ull;
+            idx_out[j * k + s] = real ? (int64_t)e[s].i : -1;
+            d2_out[j * k + s] = real ? e[s].d : ~0ull;
+        }
+    }
+}
+
 // Query ordering key: query index above the top kOrderBits of its Morton key,
 // with the digit histogram of the 8-bit sort passes over those bits.
 __global__ __launch_bounds__(256) void k_knn_order(const float *__restrict__ q, int64_t nq, float o0,
@@ -335,6 +643,7 @@ __global__ __launch_bounds__(256) void k_knn_order(const float *__restrict__ q, 
 struct KnnKnobs {
     int scan = kScanDefault;
     bool order = false;
+    bool team = true;
 };
 static KnnKnobs knn_knobs() {
     KnnKnobs k;
@@ -343,20 +652,23 @@ static KnnKnobs knn_knobs() {
         if (v >= 1 && v <= 4096) k.scan = v;
     }
     if (const char *e = getenv("CGA_KNN_ORDER")) k.order = atoi(e) != 0;
+    if (const char *e = getenv("CGA_KNN_TEAM")) k.team = atoi(e) != 0;
     return k;
 }
 
 struct KnnLayout {
     Control *ctl;
+    uint32_t *dir;
     SortWs sort;
     uint64_t *a, *b;
     size_t bytes;
 };
 
-static KnnLayout knn_layout(void *ws, int64_t nq) {
+static KnnLayout knn_layout(void *ws, int64_t nq, uint32_t depth) {
     KnnLayout L;
     Carve c(ws);
     L.ctl = c.take<Control>(1);
+    L.dir = c.take<uint32_t>((size_t)dir_cells(depth) + 1);
     L.a = L.b = nullptr;
     if (nq >= kOrderMin && knn_knobs().order) {
         SortCfg cfg;
@@ -373,8 +685,16 @@ static KnnLayout knn_layout(void *ws, int64_t nq) {
 template <typename K, int KT>
 static void knn_launch(const cga_grid *g, const K *keys, int64_t n, const int64_t *d_n,
                        const float *q, int64_t nq, int k, const uint64_t *order, int64_t *idx,
-                       uint64_t *d2, uint32_t *err, hipStream_t s) {
+                       uint64_t *d2, uint32_t *err, const uint32_t *dir, hipStream_t s) {
     CGA_PROF("knn", s);
+    if (dir) {
+        const int dt = dir_level(g->depth);
+        const size_t lds = (size_t)(dt > 0 ? dt : 1) * kKnnBlock * 2 * sizeof(int32_t);
+        k_knn_team<K, KT><<<(unsigned)((nq + kTeamsPerBlock - 1) / kTeamsPerBlock), kKnnBlock, lds, s>>>(
+            keys, n, d_n, dir, q, nq, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth,
+            k, knn_knobs().scan, idx, d2, err);
+        return;
+    }
     const size_t lds = (size_t)(g->depth + 1) * kKnnBlock * 2 * sizeof(int32_t);
     k_knn<K, KT><<<(unsigned)((nq + kKnnBlock - 1) / kKnnBlock), kKnnBlock, lds, s>>>(
         keys, n, d_n, q, nq, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth, k,
@@ -384,13 +704,20 @@ static void knn_launch(const cga_grid *g, const K *keys, int64_t n, const int64_
 template <typename K>
 static void knn_dispatch(const cga_grid *g, const K *keys, int64_t n, const int64_t *d_n,
                          const float *q, int64_t nq, int k, const uint64_t *order, int64_t *idx,
-                         uint64_t *d2, uint32_t *err, hipStream_t s) {
-    if (k <= 1) knn_launch<K, 1>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
-    else if (k <= 2) knn_launch<K, 2>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
-    else if (k <= 4) knn_launch<K, 4>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
-    else if (k <= 8) knn_launch<K, 8>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
-    else if (k <= 16) knn_launch<K, 16>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
-    else knn_launch<K, 32>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, s);
+                         uint64_t *d2, uint32_t *err, uint32_t *dir, hipStream_t s) {
+    if (dir) {
+        const int dt = dir_level(g->depth);
+        const int64_t nc = dir_cells(g->depth);
+        const int64_t threads = nc / 64 + 1;
+        CGA_PROF("knn_dir", s);
+        k_knn_dir<K><<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(keys, n, d_n, dt, nc, dir);
+    }
+    if (k <= 1) knn_launch<K, 1>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
+    else if (k <= 2) knn_launch<K, 2>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
+    else if (k <= 4) knn_launch<K, 4>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
+    else if (k <= 8) knn_launch<K, 8>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
+    else if (k <= 16) knn_launch<K, 16>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
+    else knn_launch<K, 32>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
 }
 
 // ---------------------------------------------------------- binary lookup
@@ -416,7 +743,7 @@ extern "C" {
 
 size_t cga_knn_workspace_bytes(const cga_grid *g, int64_t n, int64_t nq) {
     if (!grid_valid(g) || n < 0 || nq < 0) return 0;
-    return knn_layout(nullptr, nq).bytes;
+    return knn_layout(nullptr, nq, g->depth).bytes;
 }
 
 int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n, const float *d_q,
@@ -428,7 +755,7 @@ int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n
     if (g->key_mode != CGA_KEY_MORTON) return CGA_EUNSUPPORTED;
     if (n >= ((int64_t)1 << 31) - 1) return CGA_EUNSUPPORTED;
     if (nq >= ((int64_t)1 << (64 - kOrderBits))) return CGA_EUNSUPPORTED;
-    KnnLayout L = knn_layout(d_ws, nq);
+    KnnLayout L = knn_layout(d_ws, nq, g->depth);
     if (ws_bytes < L.bytes) return CGA_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     Control *ctl = L.ctl;
@@ -450,12 +777,13 @@ int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n
             sort_launch<uint64_t>(L.sort, L.a, L.b, L.a, L.b, nq, nullptr, true, ctl->tile_ctr, s);
             order = L.b;
         }
+        uint32_t *dir = knn_knobs().team ? L.dir : nullptr;
         if (wide_keys(g->depth))
             knn_dispatch<uint64_t>(g, (const uint64_t *)d_keys, n, d_n, d_q, nq, k, order, d_idx,
-                                   d_d2, &ctl->err, s);
+                                   d_d2, &ctl->err, dir, s);
         else
             knn_dispatch<uint32_t>(g, (const uint32_t *)d_keys, n, d_n, d_q, nq, k, order, d_idx,
-                                   d_d2, &ctl->err, s);
+                                   d_d2, &ctl->err, dir, s);
         CGA_HIP(hipGetLastError());
     }
     return CGA_OK;
