@@ -45,7 +45,22 @@ def parse():
     ap.add_argument("--c5-reps", type=int, default=10)
     ap.add_argument("--no-c4", action="store_true", help="skip the 256-frame batched run")
     ap.add_argument("--c4-reps", type=int, default=5)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers 5 times (a plain copy "
+                         "kernel of known size, to scale hardware byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration(nbytes):
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                      "reps": 5}))
 
 
 def make_workload(name):
@@ -190,15 +205,16 @@ def kernel_source_sha():
 
 
 def load_traffic(label, workload):
-    """HBM bytes per step of a kernel from committed rocprofv3 counter runs,
-    or None when absent or taken on different kernel sources."""
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain
+    copy of known size), or None when absent or taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", f"{label}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
     if t.get("source_sha") != kernel_source_sha():
         return None
-    return t.get("bytes_per_step")
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(d, lookups=None):
@@ -374,6 +390,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the path is single-GPU; see the sharding design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import torch
 
     import paper_2110_11616_amd as cga
@@ -453,7 +472,7 @@ def main():
             roofline = {
                 "bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (round(traffic / per_step_launches) if traffic else None),
+                "traffic": round(traffic) if traffic else None,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": per_step_launches,
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
             }

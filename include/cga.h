@@ -160,7 +160,8 @@ int cga_project(const cga_grid *grid, const void *d_keys, int64_t n, const int64
  * CGA smallest in (squared voxel distance, key).  Outputs row-major nq x k:
  * d_idx (int64 position in the key array, -1 padding when fewer than k
  * voxels exist) and d_d2 (uint64 squared distance, UINT64_MAX padding).
- * k in [1, 32].  MORTON grids only in this build (LINEAR: CGA_EUNSUPPORTED).
+ * k in [1, 32]; n (the host bound) below 2^31 (else CGA_EINVAL).  MORTON
+ * grids only (LINEAR: CGA_EUNSUPPORTED).
  * Errors: CGA_ENONFINITE for a non-finite query (device). */
 size_t cga_knn_workspace_bytes(const cga_grid *grid, int64_t n, int64_t nq);
 int cga_knn(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,
@@ -171,7 +172,7 @@ int cga_knn(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *
  * Point location and range start over a sorted unique uint64 key array (the
  * lookup of Section V-A; Table III): rank = number of keys < q (lower bound),
  * found = (rank < n && keys[rank] == q).  Plain branch-free binary search;
- * the judge of the learned index below.  d_found nullable. */
+ * the exact baseline that the learned index below is checked against.  d_found nullable. */
 int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n,
                       const uint64_t *d_q, int64_t nq, int64_t *d_rank, uint8_t *d_found,
                       cga_stream stream);

@@ -29,7 +29,7 @@
 namespace cga {
 
 constexpr int kKnnBlock = 256;
-constexpr int kScanDefault = 32;  // scan a cell outright when it holds at most this many keys
+constexpr int kScanDefault = 16;  // scan a cell outright when it holds at most this many keys
 // Queries are answered in the order of the top kOrderBits of their own keys,
 // so that the lanes of a wave walk neighbouring cells (sorted by index with
 // the onesweep sort when there are at least kOrderMin queries).
@@ -326,21 +326,24 @@ __host__ __device__ inline int64_t dir_cells(uint32_t depth) {
     return (int64_t)1 << (3 * ((int)depth - dir_level(depth)));
 }
 
-// D[c] for c in [0, NC]: thread t fills cells [64 t, 64 t + 64).
+// D[c] for c in [0, NC]: one thread per cell.  Two lanes of each block first
+// find the key range of the block's 256 consecutive cells; every thread then
+// searches only inside it, so a thread needs a few probes, not log2(n).
 template <typename K>
 __global__ __launch_bounds__(256) void k_knn_dir(const K *__restrict__ keys, int64_t n_host,
                                                  const int64_t *d_n, int T, int64_t nc,
                                                  uint32_t *__restrict__ dir) {
-    const int64_t n = dev_count(n_host, d_n);
-    const int64_t c0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 64;
-    if (c0 > nc) return;
-    int64_t pos = lower_bound_in(keys, 0, (int32_t)n, (uint64_t)c0 << (3 * T));
-    dir[c0] = (uint32_t)pos;
-    const int64_t c1 = c0 + 63 < nc ? c0 + 63 : nc;
-    for (int64_t c = c0 + 1; c <= c1; ++c) {
-        pos = gallop_up(keys, n, pos, (uint64_t)c << (3 * T));
-        dir[c] = (uint32_t)pos;
+    __shared__ int32_t s_lim[2];
+    const int32_t n = (int32_t)dev_count(n_host, d_n);
+    const int64_t b0 = (int64_t)blockIdx.x * 256;
+    if (threadIdx.x < 2) {
+        const int64_t c = b0 + (threadIdx.x == 0 ? 0 : 256);
+        s_lim[threadIdx.x] = c > nc ? n : lower_bound_in(keys, 0, n, (uint64_t)c << (3 * T));
     }
+    __syncthreads();
+    const int64_t c = b0 + threadIdx.x;
+    if (c > nc) return;
+    dir[c] = (uint32_t)lower_bound_in(keys, s_lim[0], s_lim[1], (uint64_t)c << (3 * T));
 }
 
 __device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
@@ -350,16 +353,46 @@ __device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
     return (uint32_t)r;
 }
 
-__device__ __forceinline__ bool cand_less(const Cand &a, const Cand &b) {
-    return a.d < b.d || (a.d == b.d && a.i < b.i);
+// The team kernel keeps its candidate list as two register arrays (squared
+// distance, key index) rather than an array of structs: whole-struct swaps
+// would be lowered to memory copies and push the list out to scratch.
+__device__ __forceinline__ bool cand_less2(uint64_t ad, int32_t ai, uint64_t bd, int32_t bi) {
+    return ad < bd || (ad == bd && ai < bi);
 }
 
-// k-th smallest entry of a sorted list (static register indexing).
+// Insert into an ascending list of KT entries (the largest drops out).
 template <int KT>
-__device__ __forceinline__ uint64_t kth_dist(const Cand (&e)[KT], int k) {
-    uint64_t d = e[0].d;
+__device__ __forceinline__ void cand_insert2(uint64_t (&ed)[KT], int32_t (&ei)[KT], uint64_t d,
+                                             int32_t i) {
+    if (!cand_less2(d, i, ed[KT - 1], ei[KT - 1])) return;
+    bool placed = false;
 #pragma unroll
-    for (int s = 1; s < KT; ++s) d = (s == k - 1) ? e[s].d : d;
+    for (int s = KT - 1; s > 0; --s) {
+        const bool sh = !placed && cand_less2(d, i, ed[s - 1], ei[s - 1]);
+        const uint64_t nd = sh ? ed[s - 1] : (placed ? ed[s] : d);
+        const int32_t ni = sh ? ei[s - 1] : (placed ? ei[s] : i);
+        placed = placed || !sh;
+        ed[s] = nd;
+        ei[s] = ni;
+    }
+    if (!placed) {
+        ed[0] = d;
+        ei[0] = i;
+    }
+}
+
+// k-th smallest distance of a sorted list: the largest of its first k
+// entries.  Written as a predicated maximum because a select chain on
+// s == k - 1 is folded back into a variable index, which would put the list
+// in scratch memory.
+template <int KT>
+__device__ __forceinline__ uint64_t kth_dist(const uint64_t (&ed)[KT], int k) {
+    uint64_t d = ed[0];
+#pragma unroll
+    for (int s = 1; s < KT; ++s) {
+        const uint64_t v = s < k ? ed[s] : 0;
+        d = v > d ? v : d;
+    }
     return d;
 }
 
@@ -367,34 +400,40 @@ __device__ __forceinline__ uint64_t kth_dist(const Cand (&e)[KT], int k) {
 // best, real or empty): after the three exchange steps every lane holds the
 // KT smallest of the union.
 template <int KT>
-__device__ __forceinline__ void team_merge(Cand (&e)[KT]) {
+__device__ __forceinline__ void team_merge(uint64_t (&ed)[KT], int32_t (&ei)[KT]) {
 #pragma unroll
     for (int step = 1; step < kTeam; step <<= 1) {
-        Cand p[KT];
+        uint64_t pd[KT];
+        int32_t pi[KT];
 #pragma unroll
         for (int s = 0; s < KT; ++s) {
-            const uint32_t lo = __shfl_xor((uint32_t)e[s].d, step, 64);
-            const uint32_t hi = __shfl_xor((uint32_t)(e[s].d >> 32), step, 64);
-            p[s].d = ((uint64_t)hi << 32) | lo;
-            p[s].i = __shfl_xor(e[s].i, step, 64);
+            const uint32_t lo = __shfl_xor((uint32_t)ed[s], step, 64);
+            const uint32_t hi = __shfl_xor((uint32_t)(ed[s] >> 32), step, 64);
+            pd[s] = ((uint64_t)hi << 32) | lo;
+            pi[s] = __shfl_xor(ei[s], step, 64);
         }
         // elementwise min against the reversed partner: a bitonic sequence
         // holding the KT smallest, then a bitonic merge network
 #pragma unroll
         for (int s = 0; s < KT; ++s) {
-            const Cand &b = p[KT - 1 - s];
-            if (cand_less(b, e[s])) e[s] = b;
+            const uint64_t bd = pd[KT - 1 - s];
+            const int32_t bi = pi[KT - 1 - s];
+            const bool t = cand_less2(bd, bi, ed[s], ei[s]);
+            ed[s] = t ? bd : ed[s];
+            ei[s] = t ? bi : ei[s];
         }
 #pragma unroll
         for (int j = KT / 2; j > 0; j >>= 1) {
 #pragma unroll
             for (int s = 0; s < KT; ++s) {
                 if ((s & j) == 0) {
-                    if (cand_less(e[s + j], e[s])) {
-                        const Cand t = e[s];
-                        e[s] = e[s + j];
-                        e[s + j] = t;
-                    }
+                    const uint64_t ad = ed[s], bd = ed[s + j];
+                    const int32_t ai = ei[s], bi = ei[s + j];
+                    const bool t = cand_less2(bd, bi, ad, ai);
+                    ed[s] = t ? bd : ad;
+                    ei[s] = t ? bi : ai;
+                    ed[s + j] = t ? ad : bd;
+                    ei[s + j] = t ? ai : bi;
                 }
             }
         }
@@ -430,34 +469,37 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_team(
         }
         return;
     }
-    const Cand kEmpty{~0ull, 0x7FFFFFFF};
-    Cand e[KT];
+    uint64_t ed[KT];
+    int32_t ei[KT];
 #pragma unroll
-    for (int s = 0; s < KT; ++s) e[s] = kEmpty;
+    for (int s = 0; s < KT; ++s) {
+        ed[s] = ~0ull;
+        ei[s] = 0x7FFFFFFF;
+    }
     uint64_t kth = ~0ull;  // this lane's k-th distance
 
     const uint64_t qkey = enc3(qv.x, qv.y, qv.z, depth, false);
-    auto qo = [&](int l) -> uint32_t {
+    auto qo = [&](int l) __attribute__((always_inline)) -> uint32_t {
         return (((qv.x >> l) & 1u) << 2) | (((qv.y >> l) & 1u) << 1) | ((qv.z >> l) & 1u);
     };
     int32_t sk_lo = 0, sk_hi = 0;  // key range already considered (skipped by scans)
-    auto bound_now = [&]() -> uint64_t {
+    auto bound_now = [&]() __attribute__((always_inline)) -> uint64_t {
         const uint64_t b = s_bound[team];
         return kth < b ? kth : b;
     };
-    auto scan = [&](int32_t lo, int32_t hi) {
+    auto scan = [&](int32_t lo, int32_t hi) __attribute__((always_inline)) {
         for (int32_t i = lo; i < hi; ++i) {
             if (i >= sk_lo && i < sk_hi) {
                 i = sk_hi - 1;
                 continue;
             }
             Vox v = dec3(keys[i], depth, false);
-            cand_insert<KT>(e, sq_dist(v, qv.x, qv.y, qv.z), i);
+            cand_insert2<KT>(ed, ei, sq_dist(v, qv.x, qv.y, qv.z), i);
         }
-        kth = kth_dist<KT>(e, k);
+        kth = kth_dist<KT>(ed, k);
         if (kth < s_bound[team]) atomicMin(&s_bound[team], (unsigned long long)kth);
     };
-    auto pruned = [&](uint64_t prefix, int l) {
+    auto pruned = [&](uint64_t prefix, int l) __attribute__((always_inline)) {
         const uint32_t bx = compact3(prefix >> 2) << l, by = compact3(prefix >> 1) << l,
                        bz = compact3(prefix) << l;
         const uint32_t ext = (1u << l) - 1;
@@ -467,7 +509,7 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_team(
     };
     // key range of cell (prefix, l): the directory at levels >= DT, else a
     // binary search in the parent's range
-    auto cell_range = [&](uint64_t prefix, int l, int32_t &lo, int32_t &hi) {
+    auto cell_range = [&](uint64_t prefix, int l, int32_t &lo, int32_t &hi) __attribute__((always_inline)) {
         if (l >= DT) {
             const int sh = 3 * (l - DT);
             lo = (int32_t)dir[prefix << sh];
@@ -487,7 +529,7 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_team(
         lo = lower_bound_in(keys, pl, ph, prefix << s3);
         hi = lower_bound_in(keys, lo, ph, (prefix + 1) << s3);
     };
-    auto walk = [&](uint64_t prefix, int lr) {
+    auto walk = [&](uint64_t prefix, int lr) __attribute__((always_inline)) {
         int l = lr;
         for (;;) {
             if (!pruned(prefix, l)) {
@@ -524,9 +566,12 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_team(
             if (done) break;
         }
     };
-    auto reset = [&]() {
+    auto reset = [&]() __attribute__((always_inline)) {
 #pragma unroll
-        for (int s = 0; s < KT; ++s) e[s] = kEmpty;
+        for (int s = 0; s < KT; ++s) {
+            ed[s] = ~0ull;
+            ei[s] = 0x7FFFFFFF;
+        }
         kth = ~0ull;
     };
 
@@ -539,8 +584,8 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_team(
     } else {
         walk((cq << 3) | (near_order((uint32_t)tl) ^ qo(DT - 1)), DT - 1);
     }
-    team_merge<KT>(e);
-    kth = kth_dist<KT>(e, k);
+    team_merge<KT>(ed, ei);
+    kth = kth_dist<KT>(ed, k);
     uint64_t bound = kth;
     bool done;
     {
@@ -585,8 +630,8 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_team(
             }
             if (ok) walk((spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]), ls);
         }
-        team_merge<KT>(e);
-        kth = kth_dist<KT>(e, k);
+        team_merge<KT>(ed, ei);
+        kth = kth_dist<KT>(ed, k);
         if (exact || ls == (int)depth) break;
         // not exact yet: start over on the box the candidates now bound
         bound = kth;
@@ -600,9 +645,9 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_team(
 #pragma unroll
     for (int s = 0; s < KT; ++s) {
         if (s < k && (s % kTeam) == tl) {
-            const bool real = e[s].d != ~0ull;
-            idx_out[j * k + s] = real ? (int64_t)e[s].i : -1;
-            d2_out[j * k + s] = real ? e[s].d : ~0ull;
+            const bool real = ed[s] != ~0ull;
+            idx_out[j * k + s] = real ? (int64_t)ei[s] : -1;
+            d2_out[j * k + s] = real ? ed[s] : ~0ull;
         }
     }
 }
@@ -708,9 +753,8 @@ static void knn_dispatch(const cga_grid *g, const K *keys, int64_t n, const int6
     if (dir) {
         const int dt = dir_level(g->depth);
         const int64_t nc = dir_cells(g->depth);
-        const int64_t threads = nc / 64 + 1;
         CGA_PROF("knn_dir", s);
-        k_knn_dir<K><<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(keys, n, d_n, dt, nc, dir);
+        k_knn_dir<K><<<(unsigned)((nc + 1 + 255) / 256), 256, 0, s>>>(keys, n, d_n, dt, nc, dir);
     }
     if (k <= 1) knn_launch<K, 1>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
     else if (k <= 2) knn_launch<K, 2>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
@@ -749,7 +793,8 @@ size_t cga_knn_workspace_bytes(const cga_grid *g, int64_t n, int64_t nq) {
 int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n, const float *d_q,
             int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2, void *d_ws, size_t ws_bytes,
             cga_stream stream) {
-    if (!grid_valid(g) || n < 0 || nq < 0 || k < 1 || k > 32 || !d_ws) return CGA_EINVAL;
+    if (!grid_valid(g) || n < 0 || n > INT32_MAX || nq < 0 || k < 1 || k > 32 || !d_ws)
+        return CGA_EINVAL;
     if (nq > 0 && (!d_q || !d_idx || !d_d2)) return CGA_EINVAL;
     if (n > 0 && !d_keys) return CGA_EINVAL;
     if (g->key_mode != CGA_KEY_MORTON) return CGA_EUNSUPPORTED;

@@ -92,6 +92,8 @@ def test_host_validation_before_any_launch(lib):
                            None) == EINVAL
     assert lib.cga_knn(ctypes.byref(grid(10, 1)), fake, 10, None, fake, 5, 1, fake, fake, fake, 256,
                        None) == EUNSUPPORTED
+    assert lib.cga_knn(ctypes.byref(g), fake, 1 << 31, None, fake, 5, 1, fake, fake, fake, 256,
+                       None) == EINVAL
     lib.cga_project.argtypes = [P, P, I64, P, ctypes.c_int, P, P, I64, P, P, P, ctypes.c_size_t,
                                 P, P]
     for axis in (-1, 3):
