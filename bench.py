@@ -188,6 +188,9 @@ def algorithmic_bytes(label, pipe, counts):
         return kb * (ua + ub + um)
     if label == "rekey":
         return (kb + k2b) * um
+    if label == "knn_tree":
+        # read every key of the union once
+        return kb * um
     if label == "knn":
         # per query: read the query (12 B), write k (index, d2) pairs (16 B
         # each), read at least the k result keys
@@ -415,7 +418,7 @@ def main():
 
     # per-kernel breakdown (untimed pass), to name the dominant kernel
     labels = ["begin", "encode", "histogram", "hist_scan", "onesweep", "rle", "merge_partition",
-              "merge", "rekey", "knn", "index_root", "index_bounds", "index_fit", "index_err",
+              "merge", "rekey", "knn_tree", "knn", "index_root", "index_bounds", "index_fit", "index_err",
               "index_lookup", "binary_lookup"]
     kern_ms = {}
     dominant = None

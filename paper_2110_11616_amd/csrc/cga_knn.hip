@@ -1,65 +1,44 @@
 // k-nearest-neighbour search, Eq. (7)-(8) generalised to k, over a sorted
 // unique MORTON key array, and plain binary-search point lookup.
 //
-// Morton keys make every octree cell a contiguous key range: cell (prefix,
-// L) holds exactly the keys in [prefix << 3L, (prefix + 1) << 3L).  One thread
-// answers one query:
-//  1. Binary-search the query's own key, then gallop outward from that
-//     position to get the key range of every cell that contains the query,
-//     from the voxel (level 0) up to the root -- O(log n) probes in total, all
-//     near one place in the array.
-//  2. Scan the query's voxel, then for each containing cell from the bottom
-//     up visit its other seven children nearest-first (the child on the
-//     query's side first, then those across one, two, three faces).  Inside a
-//     visited child the same nearest-first order recurses without a stack:
-//     the order of a child among its siblings follows from its own index bits
-//     and the query's, and the key range of each open ancestor is kept per
-//     level in LDS.  A cell whose nearest point is farther than the current
-//     k-th distance is skipped (strictly farther, so ties survive); a cell
-//     with at most a threshold number of keys is scanned exactly.
-//  3. Stop climbing as soon as every point outside the finished cell is
-//     farther than the current k-th distance.
-// Candidates are kept in registers ordered by (squared distance, key); key
-// order is array order.
+// In Morton order every octree cell is a contiguous run of keys, so the array
+// already is a pointer-free octree; searching it directly costs a binary
+// search for every cell visited.  Each call therefore first derives the
+// explicit octree of the array, level by level from the voxels up, in four
+// passes over the keys:
+//   level-L node j (L = 1..depth) is the j-th distinct prefix key >> 3L;
+//   its 64-bit word is first << 8 | mask, where first indexes its first child
+//   at level L - 1 (a key index at L = 1) and bit o of mask says whether the
+//   child in octant o exists.  Child o is then node first + popcount(mask
+//   below bit o): one 8-byte load per visited node, and no load at all for
+//   the voxels under a level-1 node, whose coordinates follow from the path.
+// A dense table maps every level-DT cell (DT = depth - 7, 2^21 cells) to its
+// node, so a search enters the tree near the bottom instead of at the root.
+//
+// Queries: a team of 8 lanes answers one query.  Round 0 splits the query's
+// level-LA cell among the lanes (one child each), every lane walking its
+// subtree depth-first, nearest child first, pruning cells whose nearest point
+// is strictly farther than the team's current k-th distance (kept in LDS, so
+// ties survive).  The lanes' candidate lists, ordered by (squared distance,
+// key index), are then merged by a butterfly of bitonic merges.  If the
+// k-th distance ball is not inside the searched cell, the next round searches
+// the up to 8 cells of the smallest level that cover the ball's bounding cube
+// (one per lane), and repeats with the grown ball until a round that started
+// from a known bound covers it.
 #include <cstdlib>
 
 #include "cga_common.h"
-#include "cga_sort.h"
 
 namespace cga {
 
 constexpr int kKnnBlock = 256;
-constexpr int kScanDefault = 16;  // scan a cell outright when it holds at most this many keys
-// Queries are answered in the order of the top kOrderBits of their own keys,
-// so that the lanes of a wave walk neighbouring cells (sorted by index with
-// the onesweep sort when there are at least kOrderMin queries).
-constexpr int kOrderBits = 24;
-constexpr int64_t kOrderMin = 4096;
-
-struct Cand {
-    uint64_t d;
-    int32_t i;
-};
-
-__device__ __forceinline__ bool cand_lt(uint64_t d, int32_t i, const Cand &c) {
-    return d < c.d || (d == c.d && i < c.i);
-}
-
-// Ascending list of KT candidates, the last k of which are the answer; the
-// first KT - k slots hold (0, -1) sentinels that no real candidate precedes.
-template <int KT>
-__device__ __forceinline__ void cand_insert(Cand (&e)[KT], uint64_t d, int32_t i) {
-    if (!cand_lt(d, i, e[KT - 1])) return;
-    bool placed = false;
-#pragma unroll
-    for (int s = KT - 1; s > 0; --s) {
-        const bool sh = !placed && cand_lt(d, i, e[s - 1]);
-        Cand nv = sh ? e[s - 1] : (placed ? e[s] : Cand{d, i});
-        placed = placed || !sh;
-        e[s] = nv;
-    }
-    if (!placed) e[0] = Cand{d, i};
-}
+constexpr int kTeam = 8;
+constexpr int kTeamsPerBlock = kKnnBlock / kTeam;
+constexpr int kMaxDepth = 21;
+constexpr int kTreeRows = 4;                       // rows of 256 keys per build tile
+constexpr int kTreeTile = kTreeRows * 256;         // keys per build tile
+constexpr int kLaDefault = 4;                      // round-0 cell level
+constexpr uint32_t kPackedDepth = 15;              // deepest grid with 32-bit squared distances
 
 template <typename K>
 __device__ __forceinline__ int64_t lower_bound_dev(const K *keys, int64_t n, K q) {
@@ -73,277 +52,245 @@ __device__ __forceinline__ int64_t lower_bound_dev(const K *keys, int64_t n, K q
     return lo + (keys[lo] < q ? 1 : 0);
 }
 
-// First index in [lo, hi) whose key is >= t (hi if none).
-template <typename K>
-__device__ __forceinline__ int32_t lower_bound_in(const K *keys, int32_t lo, int32_t hi, uint64_t t) {
-    while (lo < hi) {
-        int32_t mid = (int32_t)(((uint32_t)lo + (uint32_t)hi) >> 1);
-        if ((uint64_t)keys[mid] < t) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
+// ------------------------------------------------------------ octree build
+__host__ __device__ inline int dense_level(uint32_t depth) { return depth > 7 ? (int)depth - 7 : 0; }
+__host__ __device__ inline int64_t dense_cells(uint32_t depth) {
+    return dense_level(depth) > 0 ? (int64_t)1 << 21 : 0;
 }
 
-// First index >= lo whose key is >= t, given every key before lo is < t.
+// Highest level at which key i starts a new cell: key 0 starts every cell up
+// to the root (level depth); key i > 0 starts the cells of every level below
+// the highest bit in which it differs from key i - 1.  -1 past the end (and
+// for a repeated key, which valid input never has).
 template <typename K>
-__device__ __forceinline__ int64_t gallop_up(const K *keys, int64_t n, int64_t lo, uint64_t t) {
-    if (lo >= n || (uint64_t)keys[lo] >= t) return lo;
-    int64_t bad = lo, step = 1, good = n;  // keys[bad] < t, keys[good] >= t (or good == n)
-    for (;;) {
-        int64_t nx = bad + step;
-        if (nx >= n) break;
-        if ((uint64_t)keys[nx] >= t) {
-            good = nx;
-            break;
+__device__ __forceinline__ int head_level(const K *keys, int64_t i, int64_t n, uint32_t depth) {
+    if (i >= n) return -1;
+    if (i == 0) return (int)depth;
+    const uint64_t x = (uint64_t)keys[i] ^ (uint64_t)keys[i - 1];
+    return x ? (63 - __clzll(x)) / 3 : -1;
+}
+
+// Number of keys: the device count when given, never above the host bound.
+__device__ __forceinline__ int64_t key_count(int64_t n_host, const int64_t *d_n) {
+    const int64_t n = dev_count(n_host, d_n);
+    return n < n_host ? n : n_host;
+}
+
+// Total node count of all levels, or -1 when it exceeds the arrays (a key
+// array that is not a CGA of the grid can have more cells than the bound).
+__device__ __forceinline__ int64_t tree_total(const int64_t *lvl, uint32_t depth, int64_t nodes_max) {
+    int64_t t = 0;
+    for (uint32_t L = 1; L <= depth; ++L) t += lvl[L];
+    return t <= nodes_max ? t : -1;
+}
+
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Pass 1: per tile of kTreeTile keys, the number of nodes each level starts
+// in it (cnt[(L - 1) * tiles + tile]); also clears the dense entry table.
+template <typename K>
+__global__ __launch_bounds__(256) void k_tree_count(const K *__restrict__ keys, int64_t n_host,
+                                                    const int64_t *d_n, uint32_t depth,
+                                                    int64_t tiles, uint32_t *__restrict__ cnt,
+                                                    uint32_t *__restrict__ dense, int64_t ncells,
+                                                    uint32_t *err) {
+    __shared__ uint32_t s_c[kMaxDepth + 1];
+    const int64_t n = key_count(n_host, d_n);
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * 256)
+        dense[c] = 0;
+    if (threadIdx.x <= kMaxDepth) s_c[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    for (int r = 0; r < kTreeRows; ++r) {
+        const int64_t i = (int64_t)blockIdx.x * kTreeTile + r * 256 + threadIdx.x;
+        const int h = head_level(keys, i, n, depth);
+        // not a CGA of this grid: unsorted, repeated, or wider than 3 * depth bits
+        if (i < n && ((i > 0 && keys[i] <= keys[i - 1]) || ((uint64_t)keys[i] >> (3 * depth)) != 0))
+            set_err(err, ERR_MISMATCH);
+        for (uint32_t L = 1; L <= depth; ++L) {
+            const uint64_t b = __ballot(h >= (int)L);
+            if (!b) break;
+            if (lane == 0) atomicAdd(&s_c[L], (uint32_t)__popcll(b));
         }
-        bad = nx;
-        step <<= 1;
     }
-    int64_t a = bad + 1, b = good;
-    while (a < b) {
-        int64_t mid = (a + b) >> 1;
-        if ((uint64_t)keys[mid] < t) a = mid + 1;
-        else b = mid;
-    }
-    return a;
+    __syncthreads();
+    if (threadIdx.x >= 1 && threadIdx.x <= depth)
+        cnt[(int64_t)(threadIdx.x - 1) * tiles + blockIdx.x] = s_c[threadIdx.x];
 }
 
-// First index whose key is >= t, given every key from hi on is >= t.
+// Pass 2: one block per level; exclusive scan of the tile counts in place,
+// level size into lvl[L] (lvl[0] = number of keys).
+__global__ __launch_bounds__(1024) void k_tree_scan(uint32_t *__restrict__ cnt, int64_t tiles,
+                                                    int64_t n_host, const int64_t *d_n,
+                                                    int64_t *__restrict__ lvl) {
+    __shared__ uint32_t s_w[16];
+    const int L = blockIdx.x + 1;
+    uint32_t *c = cnt + (int64_t)(L - 1) * tiles;
+    const int64_t per = (tiles + 1023) / 1024;
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    const int64_t b1 = b0 + per < tiles ? b0 + per : tiles;
+    uint32_t sum = 0;
+    for (int64_t t = b0; t < b1; ++t) sum += c[t];
+    // block exclusive scan of the per-thread sums
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < 16; ++w) {
+        before += w < wave ? s_w[w] : 0;
+        total += s_w[w];
+    }
+    uint32_t run = before + incl - sum;
+    for (int64_t t = b0; t < b1; ++t) {
+        const uint32_t v = c[t];
+        c[t] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) {
+        lvl[L] = total;
+        if (L == 1) lvl[0] = key_count(n_host, d_n);
+    }
+}
+
+// Pass 3: node index of every cell each key starts, at every level; writes
+// the first-child index and the octant of each node, and the dense entry of
+// each level-DT node.  Level offsets: node arrays of all levels are
+// concatenated, level L starting at base(L) = lvl[1] + ... + lvl[L - 1].
 template <typename K>
-__device__ __forceinline__ int64_t gallop_down(const K *keys, int64_t hi, uint64_t t) {
-    if (hi <= 0 || (uint64_t)keys[hi - 1] < t) return hi;
-    int64_t good = hi - 1, step = 1, bad = -1;  // keys[good] >= t, keys[bad] < t (or -1)
-    for (;;) {
-        int64_t nx = good - step;
-        if (nx < 0) break;
-        if ((uint64_t)keys[nx] < t) {
-            bad = nx;
-            break;
+__global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, int64_t n_host,
+                                                    const int64_t *d_n, uint32_t depth, int dt,
+                                                    int64_t tiles, const uint32_t *__restrict__ cnt,
+                                                    const int64_t *__restrict__ lvl,
+                                                    uint32_t *__restrict__ first,
+                                                    uint8_t *__restrict__ oct,
+                                                    uint32_t *__restrict__ dense, int64_t ncells,
+                                                    int64_t nodes_max) {
+    __shared__ uint32_t s_w[kTreeRows][4][kMaxDepth + 1];
+    __shared__ int64_t s_base[kMaxDepth + 2];
+    __shared__ uint32_t s_off[kMaxDepth + 1];
+    __shared__ int s_max[4];
+    if (tree_total(lvl, depth, nodes_max) < 0) return;  // block-uniform
+    const int64_t n = key_count(n_host, d_n);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        int64_t b = 0;
+        for (uint32_t L = 1; L <= depth + 1; ++L) {
+            s_base[L] = b;
+            if (L <= depth) b += lvl[L];
         }
-        good = nx;
-        step <<= 1;
     }
-    int64_t a = bad + 1, b = good;
-    while (a < b) {
-        int64_t mid = (a + b) >> 1;
-        if ((uint64_t)keys[mid] < t) a = mid + 1;
-        else b = mid;
+    if (threadIdx.x >= 1 && threadIdx.x <= depth)
+        s_off[threadIdx.x] = cnt[(int64_t)(threadIdx.x - 1) * tiles + blockIdx.x];
+    int h[kTreeRows];
+    int hmax = -1;
+#pragma unroll
+    for (int r = 0; r < kTreeRows; ++r) {
+        h[r] = head_level(keys, (int64_t)blockIdx.x * kTreeTile + r * 256 + threadIdx.x, n, depth);
+        hmax = h[r] > hmax ? h[r] : hmax;
     }
-    return a;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int v = __shfl_xor(hmax, o, 64);
+        hmax = v > hmax ? v : hmax;
+    }
+    if (lane == 0) s_max[wave] = hmax;
+    __syncthreads();
+    int bmax = s_max[0];
+    for (int w = 1; w < 4; ++w) bmax = s_max[w] > bmax ? s_max[w] : bmax;
+    // wave counts of the nodes each level starts, per row
+#pragma unroll
+    for (int r = 0; r < kTreeRows; ++r)
+        for (int L = 1; L <= bmax; ++L) {
+            const uint64_t b = __ballot(h[r] >= L);
+            if (lane == 0) s_w[r][wave][L] = (uint32_t)__popcll(b);
+        }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kTreeRows; ++r) {
+        const int64_t i = (int64_t)blockIdx.x * kTreeTile + r * 256 + threadIdx.x;
+        int64_t child = i;  // this key's node one level down (the key itself at level 0)
+        for (int L = 1; L <= bmax; ++L) {
+            const uint64_t b = __ballot(h[r] >= L);
+            if (!b) break;
+            uint32_t before = s_off[L];
+            for (int rr = 0; rr < r; ++rr)
+                for (int w = 0; w < 4; ++w) before += s_w[rr][w][L];
+            for (int w = 0; w < wave; ++w) before += s_w[r][w][L];
+            if (h[r] >= L) {
+                const int64_t j = (int64_t)before + mbcnt64(b);
+                const int64_t t = s_base[L] + j;
+                first[t] = (uint32_t)child;
+                oct[t] = (uint8_t)(((uint64_t)keys[i] >> (3 * L)) & 7);
+                const uint64_t dc = (uint64_t)keys[i] >> (3 * dt);
+                if (L == dt && dc < (uint64_t)ncells) dense[dc] = (uint32_t)j + 1;
+                child = j;
+            }
+        }
+    }
 }
 
-__device__ __forceinline__ uint64_t sq_dist(const Vox &a, uint32_t x, uint32_t y, uint32_t z) {
-    int64_t dx = (int64_t)a.x - x, dy = (int64_t)a.y - y, dz = (int64_t)a.z - z;
-    return (uint64_t)(dx * dx + dy * dy + dz * dz);
+// Pass 4: one thread per node: child mask from the children's octants, and
+// the packed node word.
+template <typename K>
+__global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, uint32_t depth,
+                                                   const int64_t *__restrict__ lvl,
+                                                   const uint32_t *__restrict__ first,
+                                                   const uint8_t *__restrict__ oct,
+                                                   uint64_t *__restrict__ node, int64_t nodes_max) {
+    __shared__ int64_t s_n[kMaxDepth + 2], s_base[kMaxDepth + 2];
+    if (threadIdx.x == 0) {
+        s_n[0] = lvl[0];
+        int64_t b = 0;
+        for (uint32_t L = 1; L <= depth; ++L) {
+            s_n[L] = lvl[L];
+            s_base[L] = b;
+            b += lvl[L];
+        }
+        s_base[depth + 1] = b <= nodes_max ? b : 0;  // nothing to do for an oversized tree
+    }
+    __syncthreads();
+    const int64_t total = s_base[depth + 1];
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+        uint32_t L = 1;
+        while (L < depth && t >= s_base[L + 1]) ++L;
+        const int64_t j = t - s_base[L];
+        const int64_t f0 = first[t];
+        int64_t f1 = j + 1 < s_n[L] ? (int64_t)first[t + 1] : s_n[L - 1];
+        if (f1 > f0 + 8) f1 = f0 + 8;  // eight children at most (unique keys)
+        uint32_t mask = 0;
+        for (int64_t c = f0; c < f1; ++c) {
+            const uint32_t o = L == 1 ? (uint32_t)((uint64_t)keys[c] & 7) : oct[s_base[L - 1] + c];
+            mask |= 1u << o;
+        }
+        node[t] = ((uint64_t)f0 << 8) | mask;
+    }
 }
 
-__device__ __forceinline__ uint64_t axis_gap(uint32_t q, uint32_t lo, uint32_t hi) {
-    return q < lo ? (uint64_t)(lo - q) : (q > hi ? (uint64_t)(q - hi) : 0ull);
-}
-
+// ----------------------------------------------------------------- search
 // Visiting order of the 8 children: by the number of axes on which the child
 // lies across from the query (0, 1, 1, 1, 2, 2, 2, 3).  Self-inverse.
 __device__ __forceinline__ uint32_t near_order(uint32_t s) { return s == 3 ? 4u : (s == 4 ? 3u : s); }
 
-template <typename K, int KT>
-__global__ __launch_bounds__(kKnnBlock) void k_knn(const K *__restrict__ keys, int64_t n_host,
-                                                   const int64_t *d_n, const float *__restrict__ q,
-                                                   int64_t nq, float o0, float o1, float o2,
-                                                   float scale, uint32_t depth, int k,
-                                                   int scan_max,
-                                                   const uint64_t *__restrict__ order,
-                                                   int64_t *__restrict__ idx_out,
-                                                   uint64_t *__restrict__ d2_out, uint32_t *err) {
-    // key range [lo, hi) of the open cell at each level, one column per thread
-    extern __shared__ int32_t s_rng[];
-    int32_t *LO = s_rng + threadIdx.x;
-    int32_t *HI = s_rng + (depth + 1) * kKnnBlock + threadIdx.x;
-#define RLO(l) LO[(l) * kKnnBlock]
-#define RHI(l) HI[(l) * kKnnBlock]
-
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nq) return;
-    const int64_t j = order ? (int64_t)(order[t] >> kOrderBits) : t;
-    const int64_t n = dev_count(n_host, d_n);
-    const float o[3] = {o0, o1, o2};
-    Vox qv;
-    if (!quantize3(q[3 * j], q[3 * j + 1], q[3 * j + 2], o, scale, depth, qv)) {
-        if (!order) set_err(err, ERR_NONFINITE);  // else reported by the ordering pass
-        for (int s = 0; s < k; ++s) {
-            idx_out[j * k + s] = -1;
-            d2_out[j * k + s] = ~0ull;
-        }
-        return;
-    }
-
-    Cand e[KT];
-#pragma unroll
-    for (int s = 0; s < KT; ++s) e[s] = s < KT - k ? Cand{0, -1} : Cand{~0ull, 0x7FFFFFFF};
-
-    const uint64_t qkey = enc3(qv.x, qv.y, qv.z, depth, false);
-    // query's octant bits below each level: child index of the cell holding q
-    auto qo = [&](int l) -> uint32_t {
-        return (((qv.x >> l) & 1u) << 2) | (((qv.y >> l) & 1u) << 1) | ((qv.z >> l) & 1u);
-    };
-
-    // 1. range of the query's own voxel; the ranges of larger cells that
-    // contain the query are galloped out from it as the climb needs them
-    int64_t glo, ghi;
-    {
-        const int64_t p = lower_bound_dev(keys, n, (K)qkey);
-        glo = gallop_down(keys, p, qkey);
-        ghi = gallop_up(keys, n, p, qkey + 1);
-        RLO(0) = (int32_t)glo;
-        RHI(0) = (int32_t)ghi;
-    }
-
-    auto scan = [&](int32_t lo, int32_t hi) {
-        for (int32_t i = lo; i < hi; ++i) {
-            Vox v = dec3(keys[i], depth, false);
-            cand_insert<KT>(e, sq_dist(v, qv.x, qv.y, qv.z), i);
-        }
-    };
-    auto pruned = [&](uint64_t prefix, int l) {
-        const uint32_t bx = compact3(prefix >> 2) << l, by = compact3(prefix >> 1) << l,
-                       bz = compact3(prefix) << l;
-        const uint32_t ext = (1u << l) - 1;
-        const uint64_t gx = axis_gap(qv.x, bx, bx + ext), gy = axis_gap(qv.y, by, by + ext),
-                       gz = axis_gap(qv.z, bz, bz + ext);
-        return gx * gx + gy * gy + gz * gz > e[KT - 1].d;
-    };
-
-    // 2. the query's voxel, then the other children of each containing cell
-    scan(RLO(0), RHI(0));
-    for (int lp = 1; lp <= (int)depth; ++lp) {
-        // 3. every point outside the finished cell (level lp - 1) is at least
-        // this far along some axis
-        {
-            const int lc = lp - 1;
-            const uint32_t c[3] = {qv.x, qv.y, qv.z};
-            uint64_t m = ~0ull;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const uint32_t b = (c[a] >> lc) << lc;
-                const uint64_t below = (uint64_t)(c[a] - b) + 1, above = (uint64_t)b + (1u << lc) - c[a];
-                const bool has_below = b > 0, has_above = (uint64_t)b + (1u << lc) <= ((1ull << depth) - 1);
-                if (has_below && below < m) m = below;
-                if (has_above && above < m) m = above;
-            }
-            if (m == ~0ull || (e[KT - 1].d != ~0ull && m * m > e[KT - 1].d)) break;
-        }
-        {
-            const uint64_t cs = (qkey >> (3 * lp)) << (3 * lp);
-            const uint64_t ce = cs + (1ull << (3 * lp));
-            glo = gallop_down(keys, glo, cs);
-            ghi = gallop_up(keys, n, ghi, ce);
-            RLO(lp) = (int32_t)glo;
-            RHI(lp) = (int32_t)ghi;
-        }
-        if (RHI(lp) - RLO(lp) == RHI(lp - 1) - RLO(lp - 1)) continue;  // no other keys here
-        const uint64_t parent = qkey >> (3 * lp);
-        const uint32_t qc = qo(lp - 1);
-        for (uint32_t sidx = 1; sidx < 8; ++sidx) {
-            // walk the subtree of sibling `sidx` (level lr = lp - 1) nearest-first
-            const int lr = lp - 1;
-            uint64_t prefix = (parent << 3) | (near_order(sidx) ^ qc);
-            int l = lr;
-            for (;;) {
-                if (!pruned(prefix, l)) {
-                    const int sh = 3 * l;
-                    const uint64_t cs = prefix << sh, ce = (prefix + 1) << sh;
-                    const int32_t lo = lower_bound_in(keys, RLO(l + 1), RHI(l + 1), cs);
-                    const int32_t hi = lower_bound_in(keys, lo, RHI(l + 1), ce);
-                    if (hi > lo) {
-                        if (l == 0 || hi - lo <= scan_max) {
-                            scan(lo, hi);
-                        } else {
-                            RLO(l) = lo;
-                            RHI(l) = hi;
-                            prefix = (prefix << 3) | qo(l - 1);  // first child: the query's side
-                            --l;
-                            continue;
-                        }
-                    }
-                }
-                // next cell: following sibling in nearest-first order, climbing
-                // out of finished parents, until the subtree root is done
-                bool done = false;
-                for (;;) {
-                    if (l == lr) {
-                        done = true;
-                        break;
-                    }
-                    const uint32_t so = near_order((uint32_t)(prefix & 7) ^ qo(l));
-                    if (so < 7) {
-                        prefix = (prefix & ~7ull) | (near_order(so + 1) ^ qo(l));
-                        break;
-                    }
-                    prefix >>= 3;
-                    ++l;
-                }
-                if (done) break;
-            }
-        }
-    }
-#undef RLO
-#undef RHI
-
-#pragma unroll
-    for (int s = 0; s < KT; ++s) {
-        if (s >= KT - k) {
-            const int o_ = s - (KT - k);
-            const bool real = e[s].d != ~0ull;
-            idx_out[j * k + o_] = real ? (int64_t)e[s].i : -1;
-            d2_out[j * k + o_] = real ? e[s].d : ~0ull;
-        }
-    }
+// The child mask reordered by visiting slot: bit s of the result is bit
+// near_order(s) ^ qo of m (XOR by qo swaps bit pairs, pair pairs, nibbles;
+// near_order swaps slots 3 and 4).
+__device__ __forceinline__ uint32_t slot_mask(uint32_t m, uint32_t qo) {
+    if (qo & 1u) m = ((m & 0x55u) << 1) | ((m & 0xAAu) >> 1);
+    if (qo & 2u) m = ((m & 0x33u) << 2) | ((m & 0xCCu) >> 2);
+    if (qo & 4u) m = ((m & 0x0Fu) << 4) | ((m & 0xF0u) >> 4);
+    return (m & 0xE7u) | ((m >> 1) & 0x08u) | ((m << 1) & 0x10u);
 }
 
-
-// ------------------------------------------------------------------------
-// Team search: eight lanes answer one query together.
-//
-// A directory D over the top 21 key bits (cells at level T = depth - 7, or
-// every voxel when depth <= 7) gives the key range of any cell at level >= T
-// with two loads: D[c] = number of keys below cell c.  Round 0 splits the
-// directory cell that holds the query among the lanes (lane t walks its
-// t-th child in nearest-first order).  If the k-th distance found does not
-// prove the answer lies inside that cell, later rounds cover the box of
-// half-width r = floor(sqrt(bound)) around the query with the <= 2x2x2 cells
-// of the smallest level whose edge spans it, one cell per lane.  All lanes
-// prune with the best k-th distance any of them holds (one LDS word per
-// team).  After each round the lanes' sorted lists are merged by a three-step
-// butterfly of shuffles (bitonic min-merge), so every lane holds the team's
-// list.  A round is exact when it starts from a known bound whose ball the
-// box covers; otherwise the team restarts with the bound it now has (or a
-// box twice as wide while fewer than k voxels were seen).
-// ------------------------------------------------------------------------
-constexpr int kTeam = 8;
-constexpr int kTeamsPerBlock = kKnnBlock / kTeam;
-
-__host__ __device__ inline int dir_level(uint32_t depth) { return depth > 7 ? (int)depth - 7 : 0; }
-__host__ __device__ inline int64_t dir_cells(uint32_t depth) {
-    return (int64_t)1 << (3 * ((int)depth - dir_level(depth)));
-}
-
-// D[c] for c in [0, NC]: one thread per cell.  Two lanes of each block first
-// find the key range of the block's 256 consecutive cells; every thread then
-// searches only inside it, so a thread needs a few probes, not log2(n).
-template <typename K>
-__global__ __launch_bounds__(256) void k_knn_dir(const K *__restrict__ keys, int64_t n_host,
-                                                 const int64_t *d_n, int T, int64_t nc,
-                                                 uint32_t *__restrict__ dir) {
-    __shared__ int32_t s_lim[2];
-    const int32_t n = (int32_t)dev_count(n_host, d_n);
-    const int64_t b0 = (int64_t)blockIdx.x * 256;
-    if (threadIdx.x < 2) {
-        const int64_t c = b0 + (threadIdx.x == 0 ? 0 : 256);
-        s_lim[threadIdx.x] = c > nc ? n : lower_bound_in(keys, 0, n, (uint64_t)c << (3 * T));
-    }
-    __syncthreads();
-    const int64_t c = b0 + threadIdx.x;
-    if (c > nc) return;
-    dir[c] = (uint32_t)lower_bound_in(keys, s_lim[0], s_lim[1], (uint64_t)c << (3 * T));
+__device__ __forceinline__ uint32_t axis_gap(uint32_t q, uint32_t lo, uint32_t hi) {
+    return q < lo ? lo - q : (q > hi ? q - hi : 0u);
 }
 
 __device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
@@ -353,415 +300,474 @@ __device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
     return (uint32_t)r;
 }
 
-// The team kernel keeps its candidate list as two register arrays (squared
-// distance, key index) rather than an array of structs: whole-struct swaps
-// would be lowered to memory copies and push the list out to scratch.
-__device__ __forceinline__ bool cand_less2(uint64_t ad, int32_t ai, uint64_t bd, int32_t bi) {
-    return ad < bd || (ad == bd && ai < bi);
-}
-
-// Insert into an ascending list of KT entries (the largest drops out).
+// Candidate lists, ascending in (squared distance, key index), kept in
+// registers: every array below is indexed only inside unrolled loops, and a
+// k-th entry is taken as a predicated maximum, never a variable index (which
+// would move the list to scratch memory).
+//
+// Up to depth 15 a squared voxel distance is below 2^32 - 1, so a candidate
+// packs into one word, distance above index, whose integer order is the
+// candidate order; distances are 32-bit throughout.
 template <int KT>
-__device__ __forceinline__ void cand_insert2(uint64_t (&ed)[KT], int32_t (&ei)[KT], uint64_t d,
-                                             int32_t i) {
-    if (!cand_less2(d, i, ed[KT - 1], ei[KT - 1])) return;
-    bool placed = false;
+struct PackedList {
+    using Dist = uint32_t;
+    static constexpr uint64_t kNone = ~0ull;  // bound meaning "no k-th candidate yet"
+    uint64_t e[KT];
+    __device__ __forceinline__ void clear() {
 #pragma unroll
-    for (int s = KT - 1; s > 0; --s) {
-        const bool sh = !placed && cand_less2(d, i, ed[s - 1], ei[s - 1]);
-        const uint64_t nd = sh ? ed[s - 1] : (placed ? ed[s] : d);
-        const int32_t ni = sh ? ei[s - 1] : (placed ? ei[s] : i);
-        placed = placed || !sh;
-        ed[s] = nd;
-        ei[s] = ni;
+        for (int s = 0; s < KT; ++s) e[s] = ~0ull;
     }
-    if (!placed) {
-        ed[0] = d;
-        ei[0] = i;
+    __device__ __forceinline__ void offer(uint32_t d, int32_t i) {
+        const uint64_t v = ((uint64_t)d << 32) | (uint32_t)i;
+        if (v >= e[KT - 1]) return;
+#pragma unroll
+        for (int s = KT - 1; s > 0; --s) {
+            const uint64_t lo = e[s - 1], cur = e[s];
+            e[s] = v < lo ? lo : (v < cur ? v : cur);
+        }
+        e[0] = v < e[0] ? v : e[0];
     }
-}
+    // k-th distance, or kNone while fewer than k candidates are held
+    __device__ __forceinline__ uint64_t kth(int k) const {
+        uint64_t m = e[0];
+#pragma unroll
+        for (int s = 1; s < KT; ++s) {
+            const uint64_t v = s < k ? e[s] : 0;
+            m = v > m ? v : m;
+        }
+        return m == ~0ull ? kNone : (m >> 32);
+    }
+    __device__ __forceinline__ void merge_step(int step) {
+        uint64_t p[KT];
+#pragma unroll
+        for (int s = 0; s < KT; ++s) {
+            const uint32_t lo = __shfl_xor((uint32_t)e[s], step, 64);
+            const uint32_t hi = __shfl_xor((uint32_t)(e[s] >> 32), step, 64);
+            p[s] = ((uint64_t)hi << 32) | lo;
+        }
+#pragma unroll
+        for (int s = 0; s < KT; ++s) e[s] = p[KT - 1 - s] < e[s] ? p[KT - 1 - s] : e[s];
+#pragma unroll
+        for (int j = KT / 2; j > 0; j >>= 1) {
+#pragma unroll
+            for (int s = 0; s < KT; ++s) {
+                if ((s & j) == 0) {
+                    const uint64_t a = e[s], b = e[s + j];
+                    e[s] = a < b ? a : b;
+                    e[s + j] = a < b ? b : a;
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void out(int s, int64_t &idx, uint64_t &d2) const {
+        uint64_t v = e[0];
+#pragma unroll
+        for (int t = 1; t < KT; ++t) v = t == s ? e[t] : v;
+        idx = v == ~0ull ? -1 : (int64_t)(uint32_t)v;
+        d2 = v == ~0ull ? ~0ull : (v >> 32);
+    }
+};
 
-// k-th smallest distance of a sorted list: the largest of its first k
-// entries.  Written as a predicated maximum because a select chain on
-// s == k - 1 is folded back into a variable index, which would put the list
-// in scratch memory.
+// Deeper grids: 64-bit distances beside the indexes, in two arrays (whole
+// struct swaps would be lowered to memory copies).
 template <int KT>
-__device__ __forceinline__ uint64_t kth_dist(const uint64_t (&ed)[KT], int k) {
-    uint64_t d = ed[0];
-#pragma unroll
-    for (int s = 1; s < KT; ++s) {
-        const uint64_t v = s < k ? ed[s] : 0;
-        d = v > d ? v : d;
+struct WideList {
+    using Dist = uint64_t;
+    static constexpr uint64_t kNone = ~0ull;
+    uint64_t d[KT];
+    int32_t i[KT];
+    __device__ static __forceinline__ bool less(uint64_t ad, int32_t ai, uint64_t bd, int32_t bi) {
+        return ad < bd || (ad == bd && ai < bi);
     }
-    return d;
-}
-
-// Merge the team's sorted lists (no sentinels here: each lane keeps its KT
-// best, real or empty): after the three exchange steps every lane holds the
-// KT smallest of the union.
-template <int KT>
-__device__ __forceinline__ void team_merge(uint64_t (&ed)[KT], int32_t (&ei)[KT]) {
+    __device__ __forceinline__ void clear() {
 #pragma unroll
-    for (int step = 1; step < kTeam; step <<= 1) {
+        for (int s = 0; s < KT; ++s) {
+            d[s] = ~0ull;
+            i[s] = 0x7FFFFFFF;
+        }
+    }
+    __device__ __forceinline__ void offer(uint64_t vd, int32_t vi) {
+        if (!less(vd, vi, d[KT - 1], i[KT - 1])) return;
+#pragma unroll
+        for (int s = KT - 1; s > 0; --s) {
+            const bool sh = less(vd, vi, d[s - 1], i[s - 1]);
+            const bool here = less(vd, vi, d[s], i[s]);
+            const uint64_t nd = sh ? d[s - 1] : (here ? vd : d[s]);
+            const int32_t ni = sh ? i[s - 1] : (here ? vi : i[s]);
+            d[s] = nd;
+            i[s] = ni;
+        }
+        const bool f = less(vd, vi, d[0], i[0]);
+        d[0] = f ? vd : d[0];
+        i[0] = f ? vi : i[0];
+    }
+    __device__ __forceinline__ uint64_t kth(int k) const {
+        uint64_t m = d[0];
+#pragma unroll
+        for (int s = 1; s < KT; ++s) {
+            const uint64_t v = s < k ? d[s] : 0;
+            m = v > m ? v : m;
+        }
+        return m;
+    }
+    __device__ __forceinline__ void merge_step(int step) {
         uint64_t pd[KT];
         int32_t pi[KT];
 #pragma unroll
         for (int s = 0; s < KT; ++s) {
-            const uint32_t lo = __shfl_xor((uint32_t)ed[s], step, 64);
-            const uint32_t hi = __shfl_xor((uint32_t)(ed[s] >> 32), step, 64);
+            const uint32_t lo = __shfl_xor((uint32_t)d[s], step, 64);
+            const uint32_t hi = __shfl_xor((uint32_t)(d[s] >> 32), step, 64);
             pd[s] = ((uint64_t)hi << 32) | lo;
-            pi[s] = __shfl_xor(ei[s], step, 64);
+            pi[s] = __shfl_xor(i[s], step, 64);
         }
-        // elementwise min against the reversed partner: a bitonic sequence
-        // holding the KT smallest, then a bitonic merge network
 #pragma unroll
         for (int s = 0; s < KT; ++s) {
-            const uint64_t bd = pd[KT - 1 - s];
-            const int32_t bi = pi[KT - 1 - s];
-            const bool t = cand_less2(bd, bi, ed[s], ei[s]);
-            ed[s] = t ? bd : ed[s];
-            ei[s] = t ? bi : ei[s];
+            const bool t = less(pd[KT - 1 - s], pi[KT - 1 - s], d[s], i[s]);
+            d[s] = t ? pd[KT - 1 - s] : d[s];
+            i[s] = t ? pi[KT - 1 - s] : i[s];
         }
 #pragma unroll
         for (int j = KT / 2; j > 0; j >>= 1) {
 #pragma unroll
             for (int s = 0; s < KT; ++s) {
                 if ((s & j) == 0) {
-                    const uint64_t ad = ed[s], bd = ed[s + j];
-                    const int32_t ai = ei[s], bi = ei[s + j];
-                    const bool t = cand_less2(bd, bi, ad, ai);
-                    ed[s] = t ? bd : ad;
-                    ei[s] = t ? bi : ai;
-                    ed[s + j] = t ? ad : bd;
-                    ei[s + j] = t ? ai : bi;
+                    const uint64_t ad = d[s], bd = d[s + j];
+                    const int32_t ai = i[s], bi = i[s + j];
+                    const bool t = less(bd, bi, ad, ai);
+                    d[s] = t ? bd : ad;
+                    i[s] = t ? bi : ai;
+                    d[s + j] = t ? ad : bd;
+                    i[s + j] = t ? ai : bi;
                 }
             }
         }
     }
-}
+    __device__ __forceinline__ void out(int s, int64_t &idx, uint64_t &d2) const {
+        uint64_t vd = d[0];
+        int32_t vi = i[0];
+#pragma unroll
+        for (int t = 1; t < KT; ++t) {
+            vd = t == s ? d[t] : vd;
+            vi = t == s ? i[t] : vi;
+        }
+        idx = vd == ~0ull ? -1 : (int64_t)vi;
+        d2 = vd;
+    }
+};
 
-template <typename K, int KT>
-__global__ __launch_bounds__(kKnnBlock) void k_knn_team(
-    const K *__restrict__ keys, int64_t n_host, const int64_t *d_n, const uint32_t *__restrict__ dir,
-    const float *__restrict__ q, int64_t nq, float o0, float o1, float o2, float scale,
-    uint32_t depth, int k, int scan_max, int64_t *__restrict__ idx_out,
-    uint64_t *__restrict__ d2_out, uint32_t *err) {
-    extern __shared__ int32_t s_rng[];  // key ranges of open cells below the directory level
+// One query per team of kTeam lanes.  LIST is PackedList (depth <= 15) or
+// WideList.
+template <int KT, class LIST>
+__global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
+    const uint64_t *__restrict__ node, const uint32_t *__restrict__ dense,
+    const int64_t *__restrict__ lvl, int64_t nodes_max, const float *__restrict__ q, int64_t nq,
+    float o0, float o1, float o2, float scale, uint32_t depth, int k, int la,
+    int64_t *__restrict__ idx_out, uint64_t *__restrict__ d2_out, uint32_t *err) {
+    using Dist = typename LIST::Dist;
+    extern __shared__ uint64_t s_word[];  // open node word per level, one column per thread
     __shared__ unsigned long long s_bound[kTeamsPerBlock];
+    __shared__ int64_t s_base[kMaxDepth + 1];
     const int tid = threadIdx.x, team = tid / kTeam, tl = tid % kTeam;
-    const int DT = dir_level(depth);
-    int32_t *LO = s_rng + tid;
-    int32_t *HI = s_rng + (DT > 0 ? DT : 1) * kKnnBlock + tid;
-#define RLO(l) LO[(l) * kKnnBlock]
-#define RHI(l) HI[(l) * kKnnBlock]
-    if (tl == 0) s_bound[team] = ~0ull;
+    if (tid == 0) {
+        int64_t b = 0;
+        for (uint32_t L = 1; L <= depth; ++L) {
+            s_base[L] = b;
+            b += lvl[L];
+        }
+    }
+    if (tl == 0) s_bound[team] = LIST::kNone;
     __syncthreads();  // the only block-wide barrier; teams run independently after it
     const int64_t j = (int64_t)blockIdx.x * kTeamsPerBlock + team;
     if (j >= nq) return;
+    // an oversized tree (keys that are not a CGA of the grid) searches nothing
+    const int64_t n = tree_total(lvl, depth, nodes_max) < 0 ? 0 : lvl[0];
+    const int dt = dense_level(depth);
 
     const float o[3] = {o0, o1, o2};
     Vox qv;
-    if (!quantize3(q[3 * j], q[3 * j + 1], q[3 * j + 2], o, scale, depth, qv)) {
-        if (tl == 0) set_err(err, ERR_NONFINITE);
+    const bool finite = quantize3(q[3 * j], q[3 * j + 1], q[3 * j + 2], o, scale, depth, qv);
+    if (!finite && tl == 0) set_err(err, ERR_NONFINITE);
+    if (!finite || n == 0) {
         for (int s = tl; s < k; s += kTeam) {
             idx_out[j * k + s] = -1;
             d2_out[j * k + s] = ~0ull;
         }
         return;
     }
-    uint64_t ed[KT];
-    int32_t ei[KT];
-#pragma unroll
-    for (int s = 0; s < KT; ++s) {
-        ed[s] = ~0ull;
-        ei[s] = 0x7FFFFFFF;
-    }
-    uint64_t kth = ~0ull;  // this lane's k-th distance
+    LIST list;
+    list.clear();
+    uint64_t kth = LIST::kNone;  // this lane's k-th distance
 
-    const uint64_t qkey = enc3(qv.x, qv.y, qv.z, depth, false);
     auto qo = [&](int l) __attribute__((always_inline)) -> uint32_t {
         return (((qv.x >> l) & 1u) << 2) | (((qv.y >> l) & 1u) << 1) | ((qv.z >> l) & 1u);
     };
-    int32_t sk_lo = 0, sk_hi = 0;  // key range already considered (skipped by scans)
-    auto bound_now = [&]() __attribute__((always_inline)) -> uint64_t {
-        const uint64_t b = s_bound[team];
-        return kth < b ? kth : b;
+    auto box_dist = [&](uint32_t x, uint32_t y, uint32_t z, int l) __attribute__((always_inline)) -> Dist {
+        const uint32_t e = (1u << l) - 1;
+        const Dist gx = axis_gap(qv.x, x, x + e), gy = axis_gap(qv.y, y, y + e),
+                   gz = axis_gap(qv.z, z, z + e);
+        return gx * gx + gy * gy + gz * gz;
     };
-    auto scan = [&](int32_t lo, int32_t hi) __attribute__((always_inline)) {
-        for (int32_t i = lo; i < hi; ++i) {
-            if (i >= sk_lo && i < sk_hi) {
-                i = sk_hi - 1;
-                continue;
-            }
-            Vox v = dec3(keys[i], depth, false);
-            cand_insert2<KT>(ed, ei, sq_dist(v, qv.x, qv.y, qv.z), i);
-        }
-        kth = kth_dist<KT>(ed, k);
+    auto offer = [&](Dist d, int32_t i) __attribute__((always_inline)) {
+        list.offer(d, i);
+        kth = list.kth(k);
         if (kth < s_bound[team]) atomicMin(&s_bound[team], (unsigned long long)kth);
     };
-    auto pruned = [&](uint64_t prefix, int l) __attribute__((always_inline)) {
-        const uint32_t bx = compact3(prefix >> 2) << l, by = compact3(prefix >> 1) << l,
-                       bz = compact3(prefix) << l;
-        const uint32_t ext = (1u << l) - 1;
-        const uint64_t gx = axis_gap(qv.x, bx, bx + ext), gy = axis_gap(qv.y, by, by + ext),
-                       gz = axis_gap(qv.z, bz, bz + ext);
-        return gx * gx + gy * gy + gz * gz > bound_now();
+    // the level-la cell holding the query, searched in round 0, is skipped
+    // by the round that follows it
+    bool skip = false;
+    auto skipped = [&](uint32_t x, uint32_t y, uint32_t z, int l) __attribute__((always_inline)) {
+        return skip && l <= la && (x >> la) == (qv.x >> la) && (y >> la) == (qv.y >> la) &&
+               (z >> la) == (qv.z >> la);
     };
-    // key range of cell (prefix, l): the directory at levels >= DT, else a
-    // binary search in the parent's range
-    auto cell_range = [&](uint64_t prefix, int l, int32_t &lo, int32_t &hi) __attribute__((always_inline)) {
-        if (l >= DT) {
-            const int sh = 3 * (l - DT);
-            lo = (int32_t)dir[prefix << sh];
-            hi = (int32_t)dir[(prefix + 1) << sh];
-            return;
-        }
-        int32_t pl, ph;
-        if (l + 1 >= DT) {
-            const int sh = 3 * (l + 1 - DT);
-            pl = (int32_t)dir[(prefix >> 3) << sh];
-            ph = (int32_t)dir[((prefix >> 3) + 1) << sh];
+    // Node (index within its level) of the level-l cell with corner (x, y, z),
+    // or -1 if empty; at l = 0 the key index of the voxel.
+    auto find_node = [&](uint32_t x, uint32_t y, uint32_t z, int l) __attribute__((always_inline)) -> int64_t {
+        int L;
+        int64_t nj;
+        if (dt > 0 && l <= dt) {
+            const uint32_t v = dense[enc3(x >> dt, y >> dt, z >> dt, 7, false)];
+            if (!v) return -1;
+            nj = (int64_t)v - 1;
+            L = dt;
         } else {
-            pl = RLO(l + 1);
-            ph = RHI(l + 1);
+            nj = 0;  // the root
+            L = (int)depth;
         }
-        const int s3 = 3 * l;
-        lo = lower_bound_in(keys, pl, ph, prefix << s3);
-        hi = lower_bound_in(keys, lo, ph, (prefix + 1) << s3);
-    };
-    auto walk = [&](uint64_t prefix, int lr) __attribute__((always_inline)) {
-        int l = lr;
-        for (;;) {
-            if (!pruned(prefix, l)) {
-                int32_t lo, hi;
-                cell_range(prefix, l, lo, hi);
-                if (hi > lo && !(lo >= sk_lo && hi <= sk_hi)) {
-                    if (l == 0 || hi - lo <= scan_max) {
-                        scan(lo, hi);
-                    } else {
-                        if (l < DT) {
-                            RLO(l) = lo;
-                            RHI(l) = hi;
-                        }
-                        prefix = (prefix << 3) | qo(l - 1);  // first child: the query's side
-                        --l;
-                        continue;
-                    }
-                }
-            }
-            bool done = false;
-            for (;;) {
-                if (l == lr) {
-                    done = true;
-                    break;
-                }
-                const uint32_t so = near_order((uint32_t)(prefix & 7) ^ qo(l));
-                if (so < 7) {
-                    prefix = (prefix & ~7ull) | (near_order(so + 1) ^ qo(l));
-                    break;
-                }
-                prefix >>= 3;
-                ++l;
-            }
-            if (done) break;
+        while (L > l) {
+            const uint64_t w = node[s_base[L] + nj];
+            --L;
+            const uint32_t oc = (((x >> L) & 1u) << 2) | (((y >> L) & 1u) << 1) | ((z >> L) & 1u);
+            if (!((w >> oc) & 1u)) return -1;
+            nj = (int64_t)(w >> 8) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
         }
-    };
-    auto reset = [&]() __attribute__((always_inline)) {
-#pragma unroll
-        for (int s = 0; s < KT; ++s) {
-            ed[s] = ~0ull;
-            ei[s] = 0x7FFFFFFF;
-        }
-        kth = ~0ull;
+        return nj;
     };
 
     const uint32_t top = (1u << depth) - 1;
-    // round 0: the directory cell holding the query, split over the lanes
-    const uint64_t cq = qkey >> (3 * DT);
-    const int32_t tlo = (int32_t)dir[cq], thi = (int32_t)dir[cq + 1];
-    if (DT == 0) {
-        if (tl == 0) scan(tlo, thi);
-    } else {
-        walk((cq << 3) | (near_order((uint32_t)tl) ^ qo(DT - 1)), DT - 1);
-    }
-    team_merge<KT>(ed, ei);
-    kth = kth_dist<KT>(ed, k);
-    uint64_t bound = kth;
-    bool done;
-    {
-        // every voxel outside the directory cell is at least m away
-        const uint32_t c[3] = {qv.x, qv.y, qv.z};
-        uint64_t m = ~0ull;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const uint32_t b = (c[a] >> DT) << DT;
-            const uint64_t below = (uint64_t)(c[a] - b) + 1, above = (uint64_t)b + (1u << DT) - c[a];
-            if (b > 0 && below < m) m = below;
-            if ((uint64_t)b + (1u << DT) <= top && above < m) m = above;
-        }
-        done = m == ~0ull || (bound != ~0ull && m * m > bound);
-    }
-    sk_lo = tlo;
-    sk_hi = thi;
-    if (!done && tl != 0) reset();  // lane 0 carries the team's list into the next round
-    uint32_t r = bound != ~0ull ? isqrt64(bound) : ((1u << DT) - 1) / 2;
-    while (!done) {
-        if (r > top) r = top;
-        const bool exact = bound != ~0ull && isqrt64(bound) <= r;
-        int ls = DT;
-        while (ls < (int)depth && (1u << ls) < 2 * r + 1) ++ls;
+    bool round0 = true, exact = false;
+    uint32_t r = 0;
+    uint64_t bound = LIST::kNone;  // k-th distance the current round started from
+    int ls = la - 1;
+    for (;;) {
+        // this lane's start cell: round 0 = one child of the query's level-la
+        // cell; later rounds = one of the level-ls cells covering the cube
+        // [q - r, q + r] (the query's own cell and, per axis where the cube
+        // crosses a cell border, the neighbour)
+        uint32_t c[3];
+        bool ok = true;
         {
             const uint32_t c3[3] = {qv.x, qv.y, qv.z};
-            uint32_t c[3];
-            bool ok = true;
-            const uint32_t m = near_order((uint32_t)tl);
+            if (round0) {
+                const uint32_t oc = near_order((uint32_t)tl) ^ qo(la - 1);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const uint32_t lo = c3[a] > r ? c3[a] - r : 0;
-                const uint32_t hi = (uint64_t)c3[a] + r < top ? c3[a] + r : top;
-                const uint32_t own = c3[a] >> ls, clo = lo >> ls, chi = hi >> ls;
-                if ((m >> (2 - a)) & 1u) {
-                    const uint32_t other = own == clo ? chi : clo;
-                    ok = ok && other != own;
-                    c[a] = other;
-                } else {
-                    c[a] = own;
+                for (int a = 0; a < 3; ++a)
+                    c[a] = ((c3[a] >> la) << la) | (((oc >> (2 - a)) & 1u) << (la - 1));
+            } else {
+                const uint32_t m = near_order((uint32_t)tl);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const uint32_t lo = c3[a] > r ? c3[a] - r : 0;
+                    const uint32_t hi = (uint64_t)c3[a] + r < top ? c3[a] + r : top;
+                    const uint32_t own = c3[a] >> ls, clo = lo >> ls, chi = hi >> ls;
+                    if ((m >> (2 - a)) & 1u) {
+                        const uint32_t other = own == clo ? chi : clo;
+                        ok = ok && other != own;
+                        c[a] = other << ls;
+                    } else {
+                        c[a] = own << ls;
+                    }
                 }
             }
-            if (ok) walk((spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]), ls);
         }
-        team_merge<KT>(ed, ei);
-        kth = kth_dist<KT>(ed, k);
-        if (exact || ls == (int)depth) break;
-        // not exact yet: start over on the box the candidates now bound
-        bound = kth;
-        r = bound != ~0ull ? isqrt64(bound) : 2 * r + 1;
-        reset();
-        sk_lo = sk_hi = 0;
+        const int64_t cn = ok && !skipped(c[0], c[1], c[2], ls) ? find_node(c[0], c[1], c[2], ls) : -1;
+        // depth-first walk of the start cell, nearest child first
+        if (cn >= 0) {
+            uint32_t x0 = c[0], y0 = c[1], z0 = c[2];
+            const int l0 = ls;
+            auto bound_now = [&]() __attribute__((always_inline)) -> uint64_t {
+                const uint64_t b = s_bound[team];
+                return kth < b ? kth : b;
+            };
+            if (l0 == 0) {
+                const Dist d = box_dist(x0, y0, z0, 0);
+                if (d <= bound_now()) offer(d, (int32_t)cn);
+            } else if (box_dist(x0, y0, z0, l0) <= bound_now()) {
+                int l = l0;
+                uint64_t w = node[s_base[l] + cn];
+                s_word[l * kKnnBlock + tid] = w;
+                uint32_t pm = slot_mask((uint32_t)w & 0xFFu, qo(l - 1));
+                for (;;) {
+                    if (pm == 0) {
+                        if (l == l0) break;
+                        // back to the parent, after this cell's slot
+                        const uint32_t oc = (((x0 >> l) & 1u) << 2) | (((y0 >> l) & 1u) << 1) | ((z0 >> l) & 1u);
+                        ++l;
+                        const uint32_t clr = ~((1u << l) - 1u);
+                        x0 &= clr;
+                        y0 &= clr;
+                        z0 &= clr;
+                        w = s_word[l * kKnnBlock + tid];
+                        const uint32_t done_slots = (2u << near_order(oc ^ qo(l - 1))) - 1u;
+                        pm = slot_mask((uint32_t)w & 0xFFu, qo(l - 1)) & ~done_slots;
+                        continue;
+                    }
+                    const uint32_t sl = __builtin_ctz(pm);
+                    pm &= pm - 1;
+                    const uint32_t oc = near_order(sl) ^ qo(l - 1);
+                    const int cl = l - 1;
+                    const uint32_t cx = x0 | (((oc >> 2) & 1u) << cl), cy = y0 | (((oc >> 1) & 1u) << cl),
+                                   cz = z0 | ((oc & 1u) << cl);
+                    const Dist bd = box_dist(cx, cy, cz, cl);
+                    if (bd > bound_now() || skipped(cx, cy, cz, cl)) continue;
+                    const int32_t ci = (int32_t)(w >> 8) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
+                    if (cl == 0) {
+                        offer(bd, ci);
+                        continue;
+                    }
+                    w = node[s_base[cl] + ci];
+                    s_word[cl * kKnnBlock + tid] = w;
+                    l = cl;
+                    x0 = cx;
+                    y0 = cy;
+                    z0 = cz;
+                    pm = slot_mask((uint32_t)w & 0xFFu, qo(l - 1));
+                }
+            }
+        }
+#pragma unroll
+        for (int step = 1; step < kTeam; step <<= 1) list.merge_step(step);
+        kth = list.kth(k);
+        if (round0) {
+            // done if every voxel outside the level-la cell is farther than
+            // the k-th candidate
+            const uint32_t c3[3] = {qv.x, qv.y, qv.z};
+            uint64_t m = ~0ull;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t b = (c3[a] >> la) << la;
+                const uint64_t below = (uint64_t)(c3[a] - b) + 1, above = (uint64_t)b + (1u << la) - c3[a];
+                if (b > 0 && below < m) m = below;
+                if ((uint64_t)b + (1u << la) <= top && above < m) m = above;
+            }
+            if (m == ~0ull || (kth != LIST::kNone && m * m > kth)) break;
+            round0 = false;
+            skip = true;
+            bound = kth;
+            if (tl != 0) {  // lane 0 carries the team's list into the next round
+                list.clear();
+                kth = LIST::kNone;
+            }
+            r = bound != LIST::kNone ? isqrt64(bound) : ((1u << la) - 1) / 2;
+        } else {
+            if (exact || ls == (int)depth) break;
+            // not exact yet: start over on the cube the candidates now bound
+            bound = kth;
+            r = bound != LIST::kNone ? isqrt64(bound) : 2 * r + 1;
+            list.clear();
+            kth = LIST::kNone;
+            skip = false;
+        }
         if (tl == 0) s_bound[team] = bound;
+        // a round is exact when it starts from a known k-th distance whose
+        // ball its cube contains
+        if (r > top) r = top;
+        exact = bound != LIST::kNone && isqrt64(bound) <= r;
+        ls = 0;
+        while (ls < (int)depth && (1u << ls) < 2 * r + 1) ++ls;
     }
-#undef RLO
-#undef RHI
 #pragma unroll
     for (int s = 0; s < KT; ++s) {
         if (s < k && (s % kTeam) == tl) {
-            const bool real = ed[s] != ~0ull;
-            idx_out[j * k + s] = real ? (int64_t)ei[s] : -1;
-            d2_out[j * k + s] = real ? ed[s] : ~0ull;
+            int64_t idx;
+            uint64_t d2;
+            list.out(s, idx, d2);
+            idx_out[j * k + s] = idx;
+            d2_out[j * k + s] = d2;
         }
     }
 }
 
-// Query ordering key: query index above the top kOrderBits of its Morton key,
-// with the digit histogram of the 8-bit sort passes over those bits.
-__global__ __launch_bounds__(256) void k_knn_order(const float *__restrict__ q, int64_t nq, float o0,
-                                                   float o1, float o2, float scale,
-                                                   uint32_t depth, uint64_t *__restrict__ out,
-                                                   uint32_t *hist, uint32_t *err) {
-    constexpr int RB = 8, PASSES = kOrderBits / RB;
-    __shared__ uint32_t s_h[PASSES << RB];
-    __shared__ int s_bad;
-    for (int i = threadIdx.x; i < (PASSES << RB); i += blockDim.x) s_h[i] = 0;
-    if (threadIdx.x == 0) s_bad = 0;
-    __syncthreads();
-    const float o[3] = {o0, o1, o2};
-    const int drop = 3 * (int)depth > kOrderBits ? 3 * (int)depth - kOrderBits : 0;
-    bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        Vox v;
-        bad |= !quantize3(q[3 * i], q[3 * i + 1], q[3 * i + 2], o, scale, depth, v);
-        const uint64_t top = enc3(v.x, v.y, v.z, depth, false) >> drop;
-        const uint64_t packed = ((uint64_t)i << kOrderBits) | top;
-        out[i] = packed;
-        hist_add<RB>(s_h, packed, PASSES);
+// Launch knob (never changes results): CGA_KNN_LA = level of the round-0 cell.
+static int knn_la(uint32_t depth) {
+    int la = kLaDefault;
+    if (const char *e = getenv("CGA_KNN_LA")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= kMaxDepth) la = v;
     }
-    if (bad) s_bad = 1;
-    __syncthreads();
-    hist_flush<RB>(s_h, hist, PASSES);
-    if (threadIdx.x == 0 && s_bad) set_err(err, ERR_NONFINITE);
+    return la < (int)depth ? la : (int)depth;
 }
 
-// Launch knobs (never change results): CGA_KNN_SCAN = scan threshold,
-// CGA_KNN_ORDER = 1 to answer queries in the order of their Morton keys
-// (measured slower here: it gathers the costliest queries into the same waves).
-struct KnnKnobs {
-    int scan = kScanDefault;
-    bool order = false;
-    bool team = true;
-};
-static KnnKnobs knn_knobs() {
-    KnnKnobs k;
-    if (const char *e = getenv("CGA_KNN_SCAN")) {
-        int v = atoi(e);
-        if (v >= 1 && v <= 4096) k.scan = v;
+// Upper bound on the number of octree nodes of n unique keys: level L has at
+// most min(n, 8^(depth - L)) nodes.
+static int64_t tree_nodes_max(int64_t n, uint32_t depth) {
+    int64_t t = 0;
+    for (uint32_t L = 1; L <= depth; ++L) {
+        const uint32_t e = 3 * (depth - L);
+        const int64_t cap = e >= 62 ? INT64_MAX : (int64_t)1 << e;
+        t += n < cap ? n : cap;
     }
-    if (const char *e = getenv("CGA_KNN_ORDER")) k.order = atoi(e) != 0;
-    if (const char *e = getenv("CGA_KNN_TEAM")) k.team = atoi(e) != 0;
-    return k;
+    return t > 0 ? t : 1;
 }
 
 struct KnnLayout {
     Control *ctl;
-    uint32_t *dir;
-    SortWs sort;
-    uint64_t *a, *b;
+    uint32_t *cnt;
+    int64_t *lvl;
+    uint32_t *first;
+    uint8_t *oct;
+    uint64_t *node;
+    uint32_t *dense;
+    int64_t tiles, nodes;
     size_t bytes;
 };
 
-static KnnLayout knn_layout(void *ws, int64_t nq, uint32_t depth) {
+static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth) {
     KnnLayout L;
     Carve c(ws);
+    L.tiles = n > 0 ? (n + kTreeTile - 1) / kTreeTile : 1;
+    L.nodes = tree_nodes_max(n, depth);
     L.ctl = c.take<Control>(1);
-    L.dir = c.take<uint32_t>((size_t)dir_cells(depth) + 1);
-    L.a = L.b = nullptr;
-    if (nq >= kOrderMin && knn_knobs().order) {
-        SortCfg cfg;
-        cfg.radix_bits = 8;
-        cfg.items = 16;
-        sort_carve(c, L.sort, nq, kOrderBits, cfg);
-        L.a = c.take<uint64_t>((size_t)nq);
-        L.b = c.take<uint64_t>((size_t)nq);
-    }
+    L.lvl = c.take<int64_t>(kMaxDepth + 2);
+    L.cnt = c.take<uint32_t>((size_t)L.tiles * depth);
+    L.first = c.take<uint32_t>((size_t)L.nodes);
+    L.oct = c.take<uint8_t>((size_t)L.nodes);
+    L.node = c.take<uint64_t>((size_t)L.nodes);
+    L.dense = c.take<uint32_t>((size_t)dense_cells(depth) + 1);
     L.bytes = c.size();
     return L;
 }
 
-template <typename K, int KT>
-static void knn_launch(const cga_grid *g, const K *keys, int64_t n, const int64_t *d_n,
-                       const float *q, int64_t nq, int k, const uint64_t *order, int64_t *idx,
-                       uint64_t *d2, uint32_t *err, const uint32_t *dir, hipStream_t s) {
-    CGA_PROF("knn", s);
-    if (dir) {
-        const int dt = dir_level(g->depth);
-        const size_t lds = (size_t)(dt > 0 ? dt : 1) * kKnnBlock * 2 * sizeof(int32_t);
-        k_knn_team<K, KT><<<(unsigned)((nq + kTeamsPerBlock - 1) / kTeamsPerBlock), kKnnBlock, lds, s>>>(
-            keys, n, d_n, dir, q, nq, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth,
-            k, knn_knobs().scan, idx, d2, err);
-        return;
-    }
-    const size_t lds = (size_t)(g->depth + 1) * kKnnBlock * 2 * sizeof(int32_t);
-    k_knn<K, KT><<<(unsigned)((nq + kKnnBlock - 1) / kKnnBlock), kKnnBlock, lds, s>>>(
-        keys, n, d_n, q, nq, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth, k,
-        knn_knobs().scan, order, idx, d2, err);
+template <typename K>
+static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64_t *d_n,
+                       uint32_t depth, hipStream_t s) {
+    CGA_PROF("knn_tree", s);
+    const int dt = dense_level(depth);
+    k_tree_count<K><<<(unsigned)L.tiles, 256, 0, s>>>(keys, n, d_n, depth, L.tiles, L.cnt, L.dense,
+                                                      dense_cells(depth), &L.ctl->err);
+    k_tree_scan<<<depth, 1024, 0, s>>>(L.cnt, L.tiles, n, d_n, L.lvl);
+    k_tree_build<K><<<(unsigned)L.tiles, 256, 0, s>>>(keys, n, d_n, depth, dt, L.tiles, L.cnt, L.lvl,
+                                                      L.first, L.oct, L.dense, dense_cells(depth),
+                                                      L.nodes);
+    int64_t blocks = (L.nodes + 255) / 256;
+    blocks = blocks < 4096 ? blocks : 4096;
+    k_tree_mask<K><<<(unsigned)blocks, 256, 0, s>>>(keys, depth, L.lvl, L.first, L.oct, L.node,
+                                                    L.nodes);
 }
 
-template <typename K>
-static void knn_dispatch(const cga_grid *g, const K *keys, int64_t n, const int64_t *d_n,
-                         const float *q, int64_t nq, int k, const uint64_t *order, int64_t *idx,
-                         uint64_t *d2, uint32_t *err, uint32_t *dir, hipStream_t s) {
-    if (dir) {
-        const int dt = dir_level(g->depth);
-        const int64_t nc = dir_cells(g->depth);
-        CGA_PROF("knn_dir", s);
-        k_knn_dir<K><<<(unsigned)((nc + 1 + 255) / 256), 256, 0, s>>>(keys, n, d_n, dt, nc, dir);
-    }
-    if (k <= 1) knn_launch<K, 1>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
-    else if (k <= 2) knn_launch<K, 2>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
-    else if (k <= 4) knn_launch<K, 4>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
-    else if (k <= 8) knn_launch<K, 8>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
-    else if (k <= 16) knn_launch<K, 16>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
-    else knn_launch<K, 32>(g, keys, n, d_n, q, nq, k, order, idx, d2, err, dir, s);
+template <int KT>
+static void knn_launch(const cga_grid *g, const KnnLayout &L, const float *q, int64_t nq, int k,
+                       int64_t *idx, uint64_t *d2, hipStream_t s) {
+    CGA_PROF("knn", s);
+    const size_t lds = (size_t)(g->depth + 1) * kKnnBlock * sizeof(uint64_t);
+    const unsigned blocks = (unsigned)((nq + kTeamsPerBlock - 1) / kTeamsPerBlock);
+    if (g->depth <= kPackedDepth)
+        k_knn_tree<KT, PackedList<KT>><<<blocks, kKnnBlock, lds, s>>>(
+            L.node, L.dense, L.lvl, L.nodes, q, nq, g->origin[0], g->origin[1], g->origin[2],
+            g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err);
+    else
+        k_knn_tree<KT, WideList<KT>><<<blocks, kKnnBlock, lds, s>>>(
+            L.node, L.dense, L.lvl, L.nodes, q, nq, g->origin[0], g->origin[1], g->origin[2],
+            g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err);
 }
 
 // ---------------------------------------------------------- binary lookup
@@ -787,7 +793,7 @@ extern "C" {
 
 size_t cga_knn_workspace_bytes(const cga_grid *g, int64_t n, int64_t nq) {
     if (!grid_valid(g) || n < 0 || nq < 0) return 0;
-    return knn_layout(nullptr, nq, g->depth).bytes;
+    return knn_layout(nullptr, n, g->depth).bytes;
 }
 
 int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n, const float *d_q,
@@ -798,37 +804,21 @@ int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n
     if (nq > 0 && (!d_q || !d_idx || !d_d2)) return CGA_EINVAL;
     if (n > 0 && !d_keys) return CGA_EINVAL;
     if (g->key_mode != CGA_KEY_MORTON) return CGA_EUNSUPPORTED;
-    if (n >= ((int64_t)1 << 31) - 1) return CGA_EUNSUPPORTED;
-    if (nq >= ((int64_t)1 << (64 - kOrderBits))) return CGA_EUNSUPPORTED;
-    KnnLayout L = knn_layout(d_ws, nq, g->depth);
+    KnnLayout L = knn_layout(d_ws, n, g->depth);
     if (ws_bytes < L.bytes) return CGA_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    Control *ctl = L.ctl;
-    const bool ordered = L.a != nullptr;
-    CGA_TRY(launch_begin(ctl, ordered ? L.sort.hist : nullptr, ordered ? sort_zero_bytes(L.sort) : 0,
-                         nullptr, 0, nullptr, s));
+    CGA_TRY(launch_begin(L.ctl, nullptr, 0, nullptr, 0, nullptr, s));
     if (nq > 0) {
-        const uint64_t *order = nullptr;
-        if (ordered) {
-            int64_t blocks = (nq + 256 * 8 - 1) / (256 * 8);
-            blocks = blocks > 1024 ? 1024 : blocks;
-            {
-                CGA_PROF("knn_order", s);
-                k_knn_order<<<(unsigned)blocks, 256, 0, s>>>(d_q, nq, g->origin[0], g->origin[1],
-                                                              g->origin[2], g->scale, g->depth, L.a,
-                                                              L.sort.hist, &ctl->err);
-            }
-            // 3 passes: a -> b -> a -> b
-            sort_launch<uint64_t>(L.sort, L.a, L.b, L.a, L.b, nq, nullptr, true, ctl->tile_ctr, s);
-            order = L.b;
-        }
-        uint32_t *dir = knn_knobs().team ? L.dir : nullptr;
         if (wide_keys(g->depth))
-            knn_dispatch<uint64_t>(g, (const uint64_t *)d_keys, n, d_n, d_q, nq, k, order, d_idx,
-                                   d_d2, &ctl->err, dir, s);
+            tree_build<uint64_t>(L, (const uint64_t *)d_keys, n, d_n, g->depth, s);
         else
-            knn_dispatch<uint32_t>(g, (const uint32_t *)d_keys, n, d_n, d_q, nq, k, order, d_idx,
-                                   d_d2, &ctl->err, dir, s);
+            tree_build<uint32_t>(L, (const uint32_t *)d_keys, n, d_n, g->depth, s);
+        if (k <= 1) knn_launch<1>(g, L, d_q, nq, k, d_idx, d_d2, s);
+        else if (k <= 2) knn_launch<2>(g, L, d_q, nq, k, d_idx, d_d2, s);
+        else if (k <= 4) knn_launch<4>(g, L, d_q, nq, k, d_idx, d_d2, s);
+        else if (k <= 8) knn_launch<8>(g, L, d_q, nq, k, d_idx, d_d2, s);
+        else if (k <= 16) knn_launch<16>(g, L, d_q, nq, k, d_idx, d_d2, s);
+        else knn_launch<32>(g, L, d_q, nq, k, d_idx, d_d2, s);
         CGA_HIP(hipGetLastError());
     }
     return CGA_OK;
