@@ -512,12 +512,18 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
         kth = list.kth(k);
         if (kth < s_bound[team]) atomicMin(&s_bound[team], (unsigned long long)kth);
     };
-    // the level-la cell holding the query, searched in round 0, is skipped
-    // by the round that follows it
+    // Region already searched (a box of level-sk_l cells, every earlier
+    // round's region inside it), skipped by later rounds so that lane 0 can
+    // carry the team's list forward without repeats.
     bool skip = false;
+    int sk_l = 0;
+    uint32_t sk_x0 = 0, sk_x1 = 0, sk_y0 = 0, sk_y1 = 0, sk_z0 = 0, sk_z1 = 0;
     auto skipped = [&](uint32_t x, uint32_t y, uint32_t z, int l) __attribute__((always_inline)) {
-        return skip && l <= la && (x >> la) == (qv.x >> la) && (y >> la) == (qv.y >> la) &&
-               (z >> la) == (qv.z >> la);
+        if (!skip || l > sk_l) return false;
+        x >>= sk_l;
+        y >>= sk_l;
+        z >>= sk_l;
+        return x >= sk_x0 && x <= sk_x1 && y >= sk_y0 && y <= sk_y1 && z >= sk_z0 && z <= sk_z1;
     };
     // Node (index within its level) of the level-l cell with corner (x, y, z),
     // or -1 if empty; at l = 0 the key index of the voxel.
@@ -544,9 +550,8 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
     };
 
     const uint32_t top = (1u << depth) - 1;
-    bool round0 = true, exact = false;
+    bool round0 = true;
     uint32_t r = 0;
-    uint64_t bound = LIST::kNone;  // k-th distance the current round started from
     int ls = la - 1;
     for (;;) {
         // this lane's start cell: round 0 = one child of the query's level-la
@@ -637,9 +642,12 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
 #pragma unroll
         for (int step = 1; step < kTeam; step <<= 1) list.merge_step(step);
         kth = list.kth(k);
+        // Exact once every voxel within the k-th distance lies in the region
+        // searched so far: the pruning only ever used k-th distances of real
+        // candidates, so no voxel of that ball inside the region was missed.
+        bool done;
         if (round0) {
-            // done if every voxel outside the level-la cell is farther than
-            // the k-th candidate
+            // every voxel outside the level-la cell is at least m away
             const uint32_t c3[3] = {qv.x, qv.y, qv.z};
             uint64_t m = ~0ull;
 #pragma unroll
@@ -649,31 +657,44 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
                 if (b > 0 && below < m) m = below;
                 if ((uint64_t)b + (1u << la) <= top && above < m) m = above;
             }
-            if (m == ~0ull || (kth != LIST::kNone && m * m > kth)) break;
-            round0 = false;
-            skip = true;
-            bound = kth;
-            if (tl != 0) {  // lane 0 carries the team's list into the next round
-                list.clear();
-                kth = LIST::kNone;
-            }
-            r = bound != LIST::kNone ? isqrt64(bound) : ((1u << la) - 1) / 2;
+            done = m == ~0ull || (kth != LIST::kNone && m * m > kth);
         } else {
-            if (exact || ls == (int)depth) break;
-            // not exact yet: start over on the cube the candidates now bound
-            bound = kth;
-            r = bound != LIST::kNone ? isqrt64(bound) : 2 * r + 1;
+            done = (kth != LIST::kNone && isqrt64(kth) <= r) || ls == (int)depth;
+        }
+        if (done) break;
+        // the region just searched is skipped from now on
+        skip = true;
+        if (round0) {
+            sk_l = la;
+            sk_x0 = sk_x1 = qv.x >> la;
+            sk_y0 = sk_y1 = qv.y >> la;
+            sk_z0 = sk_z1 = qv.z >> la;
+        } else {
+            sk_l = ls;
+            sk_x0 = (qv.x > r ? qv.x - r : 0) >> ls;
+            sk_y0 = (qv.y > r ? qv.y - r : 0) >> ls;
+            sk_z0 = (qv.z > r ? qv.z - r : 0) >> ls;
+            sk_x1 = ((uint64_t)qv.x + r < top ? qv.x + r : top) >> ls;
+            sk_y1 = ((uint64_t)qv.y + r < top ? qv.y + r : top) >> ls;
+            sk_z1 = ((uint64_t)qv.z + r < top ? qv.z + r : top) >> ls;
+        }
+        const uint64_t bound = kth;
+        if (tl != 0) {  // lane 0 carries the team's list into the next round
             list.clear();
             kth = LIST::kNone;
-            skip = false;
+        } else {
+            s_bound[team] = bound;
         }
-        if (tl == 0) s_bound[team] = bound;
-        // a round is exact when it starts from a known k-th distance whose
-        // ball its cube contains
+        // next cube: the k-th distance ball, or a grown cube while fewer than
+        // k candidates are known (from round 0 at least one level-la cell
+        // wide, so that the next region contains the la cell)
+        if (bound != LIST::kNone) r = isqrt64(bound);
+        else if (round0) r = ((1u << la) - 1) / 2 > 1 ? ((1u << la) - 1) / 2 : 1;
+        else r = 2 * r + 1;
         if (r > top) r = top;
-        exact = bound != LIST::kNone && isqrt64(bound) <= r;
         ls = 0;
         while (ls < (int)depth && (1u << ls) < 2 * r + 1) ++ls;
+        round0 = false;
     }
 #pragma unroll
     for (int s = 0; s < KT; ++s) {
