@@ -198,7 +198,8 @@ int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n,
  *         f(x) = sum_h w2_h relu(w1_h x + b1_h) + b2 (49 float32 parameters),
  *         initialised to the piecewise-linear interpolant of the leaf's
  *         rank function at its 16 rank quantiles and then trained by
- *         full-batch Adam on mean squared error for `epochs` epochs.
+ *         full-batch Adam on mean squared error for `epochs` epochs (a leaf
+ *         of more than 512 keys trains on 512 of them evenly spaced by rank).
  *  window: err_lo_j / err_hi_j = min / max of (rank - p) over the leaf's keys.
  * Lookup: route, predict, take [lo, hi] = p + [err_lo, err_hi] clamped to
  * the leaf, verify (lo == 0 || keys[lo-1] < q) && (hi == n || keys[hi] >= q),

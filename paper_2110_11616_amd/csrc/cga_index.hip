@@ -20,6 +20,8 @@ constexpr int kMlpHidden = 16;
 constexpr int kMlpParams = 3 * kMlpHidden + 1;  // w1[16], b1[16], w2[16], b2
 constexpr int kLeafBlock = 64;  // one wave per leaf
 constexpr int kLeafCache = 4096;  // leaf inputs kept in LDS (floats)
+constexpr int kMlpBatch = 512;    // training samples per network leaf and epoch
+constexpr int kMlpPad = 64;       // gradient vector length for the halving reduction
 
 struct IndexHeader {
     uint32_t magic, version, n_leaves, leaf_kind;
@@ -291,13 +293,11 @@ __global__ __launch_bounds__(256) void k_leaf_bounds(const uint64_t *__restrict_
         for (int64_t j = threadIdx.x; j <= (int64_t)L; j += blockDim.x) first[j] = 0;
 }
 
-// One wave per leaf: fit the leaf model, write its record, reset its window.
-template <int KIND>
-__global__ __launch_bounds__(kLeafBlock) void k_leaf_fit(const uint64_t *__restrict__ keys,
-                                                         char *index, const int64_t *first,
-                                                         uint32_t epochs, float lr) {
+// Linear leaves, one wave per leaf: least-squares fit, leaf record, window
+// reset.
+__global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_linear(const uint64_t *__restrict__ keys,
+                                                                char *index, const int64_t *first) {
     __shared__ float s_x[kLeafCache];
-    __shared__ float s_p[kMlpParams], s_m[kMlpParams], s_v[kMlpParams];
 
     IndexView v;
     const IndexHeader &h = *(const IndexHeader *)index;
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit(const uint64_t *__restr
     }
     __syncthreads();
 
-    if (KIND == 0) {
+    {
         // least squares of t = s / n_j on x (fp64 sums)
         double acc[4] = {0, 0, 0, 0};
         for (int64_t s = tid; s < nj; s += blockDim.x) {
@@ -360,67 +360,120 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit(const uint64_t *__restr
             par[0] = (float)a;
             par[1] = (float)b;
         }
+    }
+}
+
+// Network leaves, one wave per leaf: initialise the 1-16-1 network as the
+// piecewise-linear interpolant of the leaf's key -> rank map at 17 rank
+// quantiles, then train it with full-batch Adam on the mean squared error.
+// A leaf of more than kMlpBatch keys trains on kMlpBatch of them spaced
+// evenly by rank (its window is still measured over every key).  Per epoch
+// each lane accumulates the gradient of its samples; a recursive-halving
+// exchange (fixed order, so deterministic) leaves lane c with the sum for
+// parameter c, which it updates with its own Adam moments and publishes
+// through LDS.
+__global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_mlp(const uint64_t *__restrict__ keys,
+                                                             char *index, const int64_t *first,
+                                                             uint32_t epochs, float lr) {
+    __shared__ float s_x[kMlpBatch], s_t[kMlpBatch];
+    __shared__ float s_p[kMlpPad];
+    __shared__ float s_kx[kMlpHidden + 1], s_kt[kMlpHidden + 1];
+    IndexView v;
+    const IndexHeader &h = *(const IndexHeader *)index;
+    index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
+    const uint32_t j = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t f0 = first[j], f1 = first[j + 1], nj = f1 - f0;
+    LeafHead &lh = v.head(j);
+    float *par = v.params(j);
+    if (nj <= 0) {  // block-uniform
+        if (tid == 0) {
+            lh.first = f0;
+            lh.kfirst = 0;
+            lh.count = 0;
+            lh.isp = 0.0f;
+            lh.err_lo = 0;
+            lh.err_hi = 0;
+        }
+        for (uint32_t c = tid; c < h.nparams; c += blockDim.x) par[c] = 0.0f;
         return;
     }
-
-    // network leaf: piecewise-linear interpolant at 17 rank quantiles
+    const uint64_t kf = keys[f0];
+    const uint64_t span = keys[f1 - 1] - kf;
+    const float isp = span ? __fdiv_rn(1.0f, (float)span) : 0.0f;
+    const float fnj = (float)nj;
+    const int m = nj < kMlpBatch ? (int)nj : kMlpBatch;  // samples per epoch
+    for (int i = tid; i < m; i += kLeafBlock) {
+        const int64_t r = m == nj ? i : ((int64_t)i * nj) / m;  // < 2^41
+        s_x[i] = __fmul_rn((float)(keys[f0 + r] - kf), isp);
+        s_t[i] = __fdiv_rn((float)r, fnj);
+    }
+    if (tid <= kMlpHidden) {
+        const int64_t r = ((int64_t)tid * (nj - 1)) / kMlpHidden;  // < 2^35
+        s_kx[tid] = __fmul_rn((float)(keys[f0 + r] - kf), isp);
+        s_kt[tid] = __fdiv_rn((float)r, fnj);
+    }
     if (tid == 0) {
-        float kx[kMlpHidden + 1], kt[kMlpHidden + 1];
-        for (int q = 0; q <= kMlpHidden; ++q) {
-            const int64_t r = ((int64_t)q * (nj - 1)) / kMlpHidden;  // < 2^35
-            kx[q] = xof(r);
-            kt[q] = __fdiv_rn((float)r, fnj);
-        }
+        lh.first = f0;
+        lh.kfirst = kf;
+        lh.count = (int32_t)nj;
+        lh.isp = isp;
+        lh.err_lo = 0x7FFFFFFF;
+        lh.err_hi = (int32_t)0x80000000;
+    }
+    __syncthreads();
+    if (tid == 0) {
         float prev = 0.0f;
         for (int q = 0; q < kMlpHidden; ++q) {
-            const float dx = __fsub_rn(kx[q + 1], kx[q]);
-            const float sl = dx > 0.0f ? __fdiv_rn(__fsub_rn(kt[q + 1], kt[q]), dx) : 0.0f;
+            const float dx = __fsub_rn(s_kx[q + 1], s_kx[q]);
+            const float sl = dx > 0.0f ? __fdiv_rn(__fsub_rn(s_kt[q + 1], s_kt[q]), dx) : 0.0f;
             s_p[q] = 1.0f;                                  // w1
-            s_p[kMlpHidden + q] = -kx[q];                   // b1
+            s_p[kMlpHidden + q] = -s_kx[q];                 // b1
             s_p[2 * kMlpHidden + q] = __fsub_rn(sl, prev);  // w2: change of slope
             prev = sl;
         }
-        s_p[3 * kMlpHidden] = kt[0];  // b2
-    }
-    if (tid < kMlpParams) {
-        s_m[tid] = 0.0f;
-        s_v[tid] = 0.0f;
+        s_p[3 * kMlpHidden] = s_kt[0];  // b2
+        for (int c = kMlpParams; c < kMlpPad; ++c) s_p[c] = 0.0f;
     }
     __syncthreads();
 
-    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f;
+    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f, fm = (float)m;
     float pw1 = 1.0f, pw2 = 1.0f;  // b1c^t, b2c^t
+    float own = s_p[tid], am = 0.0f, av = 0.0f;
     for (uint32_t ep = 0; ep < epochs; ++ep) {
-        float p[kMlpParams], g[kMlpParams + 1];
+        float p[kMlpParams], gv[kMlpPad];
 #pragma unroll
-        for (int c = 0; c < kMlpParams; ++c) {
-            p[c] = s_p[c];
-            g[c] = 0.0f;
+        for (int c = 0; c < kMlpParams; ++c) p[c] = s_p[c];
+#pragma unroll
+        for (int c = 0; c < kMlpPad; ++c) gv[c] = 0.0f;
+        float loss = 0.0f;
+        for (int i = tid; i < m; i += kLeafBlock) mlp_accumulate(p, s_x[i], s_t[i], gv, loss);
+        // recursive halving: the partner lane tid ^ w keeps the other half;
+        // afterwards gv[0] is the sum for parameter tid
+#pragma unroll
+        for (int w = kLeafBlock / 2, half = kMlpPad / 2; w > 0; w >>= 1, half >>= 1) {
+            const bool hi = (tid & w) != 0;
+#pragma unroll
+            for (int i = 0; i < half; ++i) {
+                const float send = hi ? gv[i] : gv[i + half];
+                const float keep = hi ? gv[i + half] : gv[i];
+                gv[i] = __fadd_rn(keep, __shfl_xor(send, w, kLeafBlock));
+            }
         }
-        g[kMlpParams] = 0.0f;
-        for (int64_t s = tid; s < nj; s += blockDim.x)
-            mlp_accumulate(p, xof(s), __fdiv_rn((float)s, fnj), g, g[kMlpParams]);
         pw1 = __fmul_rn(pw1, b1c);
         pw2 = __fmul_rn(pw2, b2c);
-        // lane c updates parameter c (every lane gets every sum)
-        float gr = 0.0f;
-#pragma unroll
-        for (int c = 0; c < kMlpParams; ++c) {
-            const double sum = wave_sum(g[c]);
-            if (c == tid) gr = (float)(sum / (double)nj);
-        }
-        __syncthreads();
+        __syncthreads();  // every lane has read this epoch's parameters
         if (tid < kMlpParams) {
-            const float m = fmaf(b1c, s_m[tid], __fmul_rn(1.0f - b1c, gr));
-            const float vv = fmaf(b2c, s_v[tid], __fmul_rn(__fmul_rn(1.0f - b2c, gr), gr));
-            s_m[tid] = m;
-            s_v[tid] = vv;
-            const float mh = __fdiv_rn(m, 1.0f - pw1), vh = __fdiv_rn(vv, 1.0f - pw2);
-            s_p[tid] = __fsub_rn(s_p[tid], __fdiv_rn(__fmul_rn(lr, mh), __fadd_rn(sqrtf(vh), eps)));
+            const float gr = __fdiv_rn(gv[0], fm);
+            am = fmaf(b1c, am, __fmul_rn(1.0f - b1c, gr));
+            av = fmaf(b2c, av, __fmul_rn(__fmul_rn(1.0f - b2c, gr), gr));
+            const float mh = __fdiv_rn(am, 1.0f - pw1), vh = __fdiv_rn(av, 1.0f - pw2);
+            own = __fsub_rn(own, __fdiv_rn(__fmul_rn(lr, mh), __fadd_rn(sqrtf(vh), eps)));
+            s_p[tid] = own;
         }
         __syncthreads();
     }
-    if (tid < kMlpParams) par[tid] = s_p[tid];
+    for (uint32_t c = tid; c < h.nparams; c += blockDim.x) par[c] = c < (uint32_t)kMlpParams ? s_p[c] : 0.0f;
 }
 
 // Window of every leaf: min / max of (rank - predicted rank) over its keys.
@@ -601,9 +654,9 @@ int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p
     {
         CGA_PROF("index_fit", s);
         if (p->leaf_kind == 0)
-            k_leaf_fit<0><<<L, kLeafBlock, 0, s>>>(d_keys, idx, first, 0, 0.0f);
+            k_leaf_fit_linear<<<L, kLeafBlock, 0, s>>>(d_keys, idx, first);
         else
-            k_leaf_fit<1><<<L, kLeafBlock, 0, s>>>(d_keys, idx, first, p->epochs, p->lr);
+            k_leaf_fit_mlp<<<L, kLeafBlock, 0, s>>>(d_keys, idx, first, p->epochs, p->lr);
     }
     if (n > 0) {
         CGA_PROF("index_err", s);
