@@ -228,15 +228,23 @@ __global__ __launch_bounds__(256) void k_root_partial(const uint64_t *__restrict
     if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = s[threadIdx.x][0];
 }
 
-__global__ void k_root_final(const double *partial, int blocks, int64_t n, IndexHeader *h) {
-    if (threadIdx.x != 0) return;
-    double sx = 0, sy = 0, sxx = 0, sxy = 0;
-    for (int b = 0; b < blocks; ++b) {
-        sx += partial[4 * b];
-        sy += partial[4 * b + 1];
-        sxx += partial[4 * b + 2];
-        sxy += partial[4 * b + 3];
+// Least-squares line from the block partials, summed in a fixed order (each
+// thread a strided subset, then a tree), so the fit is deterministic.
+__global__ __launch_bounds__(256) void k_root_final(const double *partial, int blocks, int64_t n,
+                                                    IndexHeader *h) {
+    __shared__ double s[4][256];
+    double acc[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < blocks; b += 256)
+        for (int c = 0; c < 4; ++c) acc[c] += partial[4 * b + c];
+    for (int c = 0; c < 4; ++c) s[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x != 0) return;
+    const double sx = s[0][0], sy = s[1][0], sxx = s[2][0], sxy = s[3][0];
     const double dn = (double)n;
     const double den = dn * sxx - sx * sx;
     double a = den != 0.0 ? (dn * sxy - sx * sy) / den : 0.0;
@@ -477,21 +485,46 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_mlp(const uint64_t *__r
 }
 
 // Window of every leaf: min / max of (rank - predicted rank) over its keys.
+// Keys are sorted and routing is monotone, so a wave's 64 keys usually fall
+// in one leaf; such a wave reduces first and updates the leaf once.
 __global__ __launch_bounds__(256) void k_leaf_err(const uint64_t *__restrict__ keys, int64_t n,
                                                   char *index) {
     IndexView v;
     const IndexHeader &h = *(const IndexHeader *)index;
     index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t q = keys[i];
-        const uint32_t j = route(h, v, v.rx, q);
-        LeafHead &lh = v.head(j);
-        int64_t f0, f1;
-        const int64_t e = i - leaf_predict(lh, v.params(j), h.leaf_kind, q, n, &f0, &f1);
-        const int32_t ec = (int32_t)(e > 0x3FFFFFFF ? 0x3FFFFFFF : (e < -0x3FFFFFFF ? -0x3FFFFFFF : e));
-        atomicMin(&lh.err_lo, ec);
-        atomicMax(&lh.err_hi, ec);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < n; i0 += stride) {
+        const int64_t i = i0 + lane;  // i0 is wave-uniform, so lane 0 is always in range
+        const bool valid = i < n;
+        uint32_t j = 0xFFFFFFFFu;
+        int32_t ec = 0;
+        if (valid) {
+            const uint64_t q = keys[i];
+            j = route(h, v, v.rx, q);
+            int64_t f0, f1;
+            const int64_t e = i - leaf_predict(v.head(j), v.params(j), h.leaf_kind, q, n, &f0, &f1);
+            ec = (int32_t)(e > 0x3FFFFFFF ? 0x3FFFFFFF : (e < -0x3FFFFFFF ? -0x3FFFFFFF : e));
+        }
+        const uint32_t j0 = __shfl(j, 0, 64);
+        if (__ballot(valid && j == j0) == __ballot(valid)) {
+            int32_t lo = valid ? ec : 0x7FFFFFFF, hi = valid ? ec : (int32_t)0x80000000;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const int32_t a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
+                lo = a < lo ? a : lo;
+                hi = b > hi ? b : hi;
+            }
+            if (lane == 0) {
+                LeafHead &lh = v.head(j0);
+                atomicMin(&lh.err_lo, lo);
+                atomicMax(&lh.err_hi, hi);
+            }
+        } else if (valid) {
+            LeafHead &lh = v.head(j);
+            atomicMin(&lh.err_lo, ec);
+            atomicMax(&lh.err_hi, ec);
+        }
     }
 }
 
@@ -638,7 +671,7 @@ int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p
         k_index_header<<<1, 64, 0, s>>>(d_keys, n, L, p->leaf_kind, np, p->root_segments, h);
         if (n > 0) {
             k_root_partial<<<kRootBlocks, 256, 0, s>>>(d_keys, n, h, partial);
-            k_root_final<<<1, 64, 0, s>>>(partial, kRootBlocks, n, h);
+            k_root_final<<<1, 256, 0, s>>>(partial, kRootBlocks, n, h);
             if (p->root_segments) {
                 const unsigned rb = (p->root_segments + 255) / 256;
                 k_root_knots<<<rb, 256, 0, s>>>(d_keys, n, idx);
