@@ -498,8 +498,10 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
     list.clear();
     uint64_t kth = LIST::kNone;  // this lane's k-th distance
 
+    // the query's octant at level l is digit l of its Morton key
+    const uint64_t qkey = enc3(qv.x, qv.y, qv.z, depth, false);
     auto qo = [&](int l) __attribute__((always_inline)) -> uint32_t {
-        return (((qv.x >> l) & 1u) << 2) | (((qv.y >> l) & 1u) << 1) | ((qv.z >> l) & 1u);
+        return (uint32_t)(qkey >> (3 * l)) & 7u;
     };
     auto box_dist = [&](uint32_t x, uint32_t y, uint32_t z, int l) __attribute__((always_inline)) -> Dist {
         const uint32_t e = (1u << l) - 1;
@@ -600,42 +602,80 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
                 int l = l0;
                 uint64_t w = node[s_base[l] + cn];
                 s_word[l * kKnnBlock + tid] = w;
-                uint32_t pm = slot_mask((uint32_t)w & 0xFFu, qo(l - 1));
+                // Per open node: the query's octant one level down, the squared
+                // gap to the low and the high child half on each axis (a
+                // child's box distance is then three selects and two adds),
+                // whether its children are cells of the skipped level, and the
+                // bound, refreshed from the team's at every node.
+                uint32_t qol = 0;
+                Dist gxl = 0, gxh = 0, gyl = 0, gyh = 0, gzl = 0, gzh = 0;
+                bool touch = false;
+                uint64_t bnd = 0;
+                auto enter = [&]() __attribute__((always_inline)) {
+                    const int cl = l - 1;
+                    qol = qo(cl);
+                    const uint32_t h = 1u << cl, e = h - 1u;
+                    const Dist ax = axis_gap(qv.x, x0, x0 + e), bx = axis_gap(qv.x, x0 + h, x0 + h + e);
+                    const Dist ay = axis_gap(qv.y, y0, y0 + e), by = axis_gap(qv.y, y0 + h, y0 + h + e);
+                    const Dist az = axis_gap(qv.z, z0, z0 + e), bz = axis_gap(qv.z, z0 + h, z0 + h + e);
+                    gxl = ax * ax;
+                    gxh = bx * bx;
+                    gyl = ay * ay;
+                    gyh = by * by;
+                    gzl = az * az;
+                    gzh = bz * bz;
+                    touch = skip && cl == sk_l;
+                    bnd = bound_now();
+                };
+                enter();
+                uint32_t pm = slot_mask((uint32_t)w & 0xFFu, qol);
+                // One iteration: either climb back to the parent (its slots
+                // up to the one just finished are done), or take the next
+                // child -- prune it, offer it (a voxel), or descend into it.
+                // Climbing and descending share one node-entry tail, so a
+                // wave whose lanes take different paths runs it once.
                 for (;;) {
-                    if (pm == 0) {
-                        if (l == l0) break;
-                        // back to the parent, after this cell's slot
-                        const uint32_t oc = (((x0 >> l) & 1u) << 2) | (((y0 >> l) & 1u) << 1) | ((z0 >> l) & 1u);
+                    const bool up = pm == 0;
+                    if (up && l == l0) break;
+                    bool moved = up;
+                    uint32_t done_oc = 0;
+                    if (up) {
+                        done_oc = (((x0 >> l) & 1u) << 2) | (((y0 >> l) & 1u) << 1) | ((z0 >> l) & 1u);
                         ++l;
                         const uint32_t clr = ~((1u << l) - 1u);
                         x0 &= clr;
                         y0 &= clr;
                         z0 &= clr;
                         w = s_word[l * kKnnBlock + tid];
-                        const uint32_t done_slots = (2u << near_order(oc ^ qo(l - 1))) - 1u;
-                        pm = slot_mask((uint32_t)w & 0xFFu, qo(l - 1)) & ~done_slots;
-                        continue;
+                    } else {
+                        const uint32_t sl = __builtin_ctz(pm);
+                        pm &= pm - 1;
+                        const uint32_t oc = near_order(sl) ^ qol;
+                        const Dist bd = ((oc & 4u) ? gxh : gxl) + ((oc & 2u) ? gyh : gyl) + ((oc & 1u) ? gzh : gzl);
+                        const int cl = l - 1;
+                        const uint32_t cx = x0 | (((oc >> 2) & 1u) << cl), cy = y0 | (((oc >> 1) & 1u) << cl),
+                                       cz = z0 | ((oc & 1u) << cl);
+                        if (bd <= bnd && !(touch && skipped(cx, cy, cz, cl))) {
+                            const int32_t ci = (int32_t)(w >> 8) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
+                            if (cl == 0) {
+                                offer(bd, ci);
+                                bnd = kth < bnd ? kth : bnd;
+                            } else {
+                                w = node[s_base[cl] + ci];
+                                s_word[cl * kKnnBlock + tid] = w;
+                                l = cl;
+                                x0 = cx;
+                                y0 = cy;
+                                z0 = cz;
+                                moved = true;
+                            }
+                        }
                     }
-                    const uint32_t sl = __builtin_ctz(pm);
-                    pm &= pm - 1;
-                    const uint32_t oc = near_order(sl) ^ qo(l - 1);
-                    const int cl = l - 1;
-                    const uint32_t cx = x0 | (((oc >> 2) & 1u) << cl), cy = y0 | (((oc >> 1) & 1u) << cl),
-                                   cz = z0 | ((oc & 1u) << cl);
-                    const Dist bd = box_dist(cx, cy, cz, cl);
-                    if (bd > bound_now() || skipped(cx, cy, cz, cl)) continue;
-                    const int32_t ci = (int32_t)(w >> 8) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
-                    if (cl == 0) {
-                        offer(bd, ci);
-                        continue;
+                    if (moved) {
+                        enter();
+                        const uint32_t done_slots = up ? (2u << near_order(done_oc ^ qol)) - 1u : 0u;
+                        pm = slot_mask((uint32_t)w & 0xFFu, qol) & ~done_slots;
                     }
-                    w = node[s_base[cl] + ci];
-                    s_word[cl * kKnnBlock + tid] = w;
-                    l = cl;
-                    x0 = cx;
-                    y0 = cy;
-                    z0 = cz;
-                    pm = slot_mask((uint32_t)w & 0xFFu, qo(l - 1));
                 }
             }
         }
