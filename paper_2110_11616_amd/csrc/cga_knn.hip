@@ -329,11 +329,14 @@ struct PackedList {
     }
     // k-th distance, or kNone while fewer than k candidates are held
     __device__ __forceinline__ uint64_t kth(int k) const {
-        uint64_t m = e[0];
+        uint64_t m = e[KT - 1];
+        if (k != KT) {  // grid-uniform
+            m = e[0];
 #pragma unroll
-        for (int s = 1; s < KT; ++s) {
-            const uint64_t v = s < k ? e[s] : 0;
-            m = v > m ? v : m;
+            for (int s = 1; s < KT; ++s) {
+                const uint64_t v = s < k ? e[s] : 0;
+                m = v > m ? v : m;
+            }
         }
         return m == ~0ull ? kNone : (m >> 32);
     }
@@ -402,11 +405,14 @@ struct WideList {
         i[0] = f ? vi : i[0];
     }
     __device__ __forceinline__ uint64_t kth(int k) const {
-        uint64_t m = d[0];
+        uint64_t m = d[KT - 1];
+        if (k != KT) {  // grid-uniform
+            m = d[0];
 #pragma unroll
-        for (int s = 1; s < KT; ++s) {
-            const uint64_t v = s < k ? d[s] : 0;
-            m = v > m ? v : m;
+            for (int s = 1; s < KT; ++s) {
+                const uint64_t v = s < k ? d[s] : 0;
+                m = v > m ? v : m;
+            }
         }
         return m;
     }
