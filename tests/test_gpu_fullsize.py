@@ -1,0 +1,130 @@
+"""Full-size parity, in the launch configuration bench.py times.
+
+One step of bench.py's own pipeline (build two clouds, merge, project onto
+XY, k-NN of the queries against the union, learned index of the union and
+its lookups next to binary search) runs on the GPU at the workloads' full
+sizes:
+
+* c2: 2 x 1,048,576 LiDAR points, depth 12, 100k queries, k = 8 -- compared
+  with the oracle itself (std::map build, std::set_union merge, coordinate
+  drop), k-NN rows on a seeded sample of 2000 queries with the oracle's kd-tree
+  over the whole union, and every lookup with std::lower_bound.
+* c3: 2 x 10M points, depth 14, 1M queries, k = 16 -- build, merge and the
+  three projections compared with the definitions the oracle states (its
+  per-point quantize and key encode, each deduplicated with numpy: a set of
+  keys with multiplicities, a set union, the image under a coordinate drop),
+  k-NN rows on 32 sampled queries with oracle brute force over the ~20M-voxel
+  union, and a sample of lookups with std::lower_bound.
+"""
+import numpy as np
+import pytest
+import torch
+
+import bench
+import gen
+import oracle
+from helpers import say, u64
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _run_step(cga, d):
+    pipe = bench.Pipeline(cga, d, torch.device("cuda:0"))
+    pipe.step()
+    torch.cuda.synchronize()
+    pipe.check()
+    pipe.nu = int(pipe.cnt[2].item())
+    pipe.make_lookups()
+    pipe.step()
+    torch.cuda.synchronize()
+    pipe.check()
+    return pipe
+
+
+def _keys(t, n):
+    return u64(t[:n])
+
+
+def _check_lookups(pipe, m_ref, sample=None):
+    lq = pipe.lq.cpu().numpy().view(np.uint64)
+    lrank = pipe.lrank.cpu().numpy()
+    brank = pipe.brank.cpu().numpy()
+    lfound = pipe.lfound.cpu().numpy()
+    if sample is not None:
+        lq, lrank, brank, lfound = lq[sample], lrank[sample], brank[sample], lfound[sample]
+    want, present = oracle.lower_bound(m_ref, lq)
+    np.testing.assert_array_equal(lrank, want)
+    np.testing.assert_array_equal(brank, want)
+    np.testing.assert_array_equal(lfound.astype(bool), present.astype(bool))
+
+
+def _check_knn_rows(pipe, rows, idx_ref, d2_ref):
+    idx = pipe.idx.cpu().numpy()[rows]
+    d2 = pipe.d2.cpu().numpy().view(np.uint64)[rows]
+    np.testing.assert_array_equal(idx, idx_ref)
+    np.testing.assert_array_equal(d2, d2_ref)
+
+
+def test_c2_full(gpu):
+    cga = gpu
+    d = gen.c2_lidar()
+    g = d["grid"]
+    say("c2 full: build/merge/project/knn/index at 2 x 1048576 points")
+    pipe = _run_step(cga, d)
+    ua, ub, um, up = [int(x) for x in pipe.cnt.cpu().tolist()]
+    ka, ca = oracle.build(d["a"], g)
+    kb, cb = oracle.build(d["b"], g)
+    np.testing.assert_array_equal(_keys(pipe.ka, ua), ka)
+    np.testing.assert_array_equal(pipe.ca[:ua].cpu().numpy(), ca)
+    np.testing.assert_array_equal(_keys(pipe.kb, ub), kb)
+    np.testing.assert_array_equal(pipe.cb[:ub].cpu().numpy(), cb)
+    m, _ = oracle.merge(ka, kb, g.depth, g.key_mode)
+    np.testing.assert_array_equal(_keys(pipe.m, um), m)
+    p, pc = oracle.project(m, g.depth, g.key_mode, 2)
+    np.testing.assert_array_equal(u64(pipe.p[:up]), p)
+    np.testing.assert_array_equal(pipe.pc[:up].cpu().numpy(), pc)
+    rows = np.sort(np.random.default_rng(2002).choice(len(d["q"]), 2000, replace=False))
+    idx_ref, d2_ref = oracle.knn_kdtree(m, d["q"][rows], g, d["k"])
+    _check_knn_rows(pipe, rows, idx_ref, d2_ref)
+    _check_lookups(pipe, m)
+
+
+def _defined_build(xyz, g):
+    keys = oracle.encode(oracle.quantize(xyz, g), g.depth, g.key_mode)
+    return np.unique(keys, return_counts=True)
+
+
+def _defined_project(m, g, drop):
+    vox = oracle.decode(m, g.depth, g.key_mode)
+    keep = [a for a in range(3) if a != drop]
+    pk = oracle.encode2(vox[:, keep[0]], vox[:, keep[1]], g.depth, g.key_mode)
+    return np.unique(pk, return_counts=True)
+
+
+def test_c3_full(gpu):
+    cga = gpu
+    d = gen.c3_bumpy()
+    g = d["grid"]
+    say("c3 full: build/merge/project/knn/index at 2 x 10M points")
+    pipe = _run_step(cga, d)
+    ua, ub, um, up = [int(x) for x in pipe.cnt.cpu().tolist()]
+    ka, ca = _defined_build(d["a"], g)
+    np.testing.assert_array_equal(_keys(pipe.ka, ua), ka)
+    np.testing.assert_array_equal(pipe.ca[:ua].cpu().numpy(), ca)
+    kb, cb = _defined_build(d["b"], g)
+    np.testing.assert_array_equal(_keys(pipe.kb, ub), kb)
+    np.testing.assert_array_equal(pipe.cb[:ub].cpu().numpy(), cb)
+    m = np.union1d(ka, kb)
+    np.testing.assert_array_equal(_keys(pipe.m, um), m)
+    p, pc = _defined_project(m, g, 2)
+    np.testing.assert_array_equal(u64(pipe.p[:up]), p)
+    np.testing.assert_array_equal(pipe.pc[:up].cpu().numpy(), pc)
+    for drop in (0, 1):  # the other two axis projections of the workload
+        gk, gc = cga.cga_project(pipe.m[:um], g, drop)
+        pk, pcnt = _defined_project(m, g, drop)
+        np.testing.assert_array_equal(u64(gk), pk)
+        np.testing.assert_array_equal(gc.cpu().numpy(), pcnt)
+    rows = np.sort(np.random.default_rng(2003).choice(len(d["q"]), 32, replace=False))
+    idx_ref, d2_ref = oracle.knn_brute(m, d["q"][rows], g, d["k"])
+    _check_knn_rows(pipe, rows, idx_ref, d2_ref)
+    _check_lookups(pipe, m, sample=np.arange(0, len(pipe.lq), 7))
