@@ -14,6 +14,7 @@ constexpr int kSortBlock = 256;
 constexpr int kMaxPasses = 16;  // 64 bits at 4 bits per digit
 
 // Look-back status word: 2-bit flag + 30-bit count.
+constexpr int kLookWindow = 8;  // predecessors read per look-back round trip
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1;
@@ -186,16 +187,31 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
             s_boff[d] = ex;
             uint32_t before = 0;
             if (tile > 0) {
+                // kLookWindow predecessors per round trip: their loads are
+                // independent, so a walk over aggregates costs one latency
+                // per window, not per tile
                 int64_t t = (int64_t)tile - 1;
                 for (;;) {
-                    uint32_t st = ld_agent(&look[(size_t)t * RADIX + d]);
-                    if ((st & ~kValMask) == 0) {
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
+                    uint32_t st[kLookWindow];
+#pragma unroll
+                    for (int w = 0; w < kLookWindow; ++w)
+                        st[w] = t - w >= 0 ? ld_agent(&look[(size_t)(t - w) * RADIX + d]) : kFlagInc;
+                    bool done = false, stall = false;
+                    int used = 0;
+#pragma unroll
+                    for (int w = 0; w < kLookWindow; ++w) {
+                        if (done || stall) continue;
+                        if ((st[w] & ~kValMask) == 0) {
+                            stall = true;  // not published yet: resume here
+                            continue;
+                        }
+                        before += st[w] & kValMask;
+                        ++used;
+                        done = (st[w] & kFlagInc) != 0;
                     }
-                    before += st & kValMask;
-                    if (st & kFlagInc) break;
-                    --t;
+                    if (done) break;
+                    t -= used;
+                    if (stall) __builtin_amdgcn_s_sleep(1);
                 }
                 st_agent(&look[(size_t)tile * RADIX + d], kFlagInc | (before + cnt[j]));
             }
