@@ -59,6 +59,8 @@ def _load():
         lib.or_nn_cga.argtypes = [P, i64, P, P, P, P, u32, i32, P, i64, P, P]
         lib.or_lower_bound.argtypes = [P, i64, P, i64, P, P]
         lib.or_mlp_loss_grad.argtypes = [P, P, P, i64, P, P]
+        lib.or_occupancy.argtypes = [P, i64, u32, P, P]
+        lib.or_occupancy.restype = i64
         lib.or_mlp_loss_grad.restype = ctypes.c_double
         _lib = lib
     return _lib
@@ -209,6 +211,17 @@ def lower_bound(keys, q):
     found = np.empty(len(q), np.uint8)
     _load().or_lower_bound(_p(keys), len(keys), _p(q), len(q), _p(rank), _p(found))
     return rank, found
+
+
+def occupancy(keys, depth: int):
+    """Octree occupancy codes (Section II-E, constructing the octree / coding of
+    the occupancy codes) of a sorted unique MORTON key set: (codes root first,
+    level by level, cells in key order; occupied cells per level, index L)."""
+    keys = _u64(keys)
+    occ = np.empty(max(1, len(keys) * depth), np.uint8)
+    counts = np.empty(depth + 1, np.int64)
+    t = _load().or_occupancy(_p(keys), len(keys), depth, _p(occ), _p(counts))
+    return occ[:t].copy(), counts
 
 
 def mlp_loss_grad(params, x, t):

@@ -462,6 +462,31 @@ void or_lower_bound(const uint64_t *keys, int64_t n, const uint64_t *q, int64_t 
     }
 }
 
+/* Octree occupancy codes (Section II-E, point cloud compression: constructing
+ * the octree, coding of the occupancy codes).  The octree of a MORTON key set
+ * has, at level L, one occupied cell per distinct key >> 3L; a cell's 8-bit
+ * code has bit o set when its child in octant o (child prefix = prefix * 8 +
+ * o, o = x_bit << 2 | y_bit << 1 | z_bit) is occupied.  The codes are written
+ * from the root (L = depth) down to L = 1, level by level, cells of a level in
+ * key order.  counts[L] = occupied cells at level L (counts[0] = voxels).
+ * Returns the number of codes. */
+int64_t or_occupancy(const uint64_t *keys, int64_t n, uint32_t depth, uint8_t *occ,
+                     int64_t *counts) {
+    std::vector<std::set<uint64_t>> cells(depth + 1);
+    for (int64_t i = 0; i < n; ++i)
+        for (uint32_t L = 0; L <= depth; ++L) cells[L].insert(keys[i] >> (3 * L));
+    for (uint32_t L = 0; L <= depth; ++L) counts[L] = (int64_t)cells[L].size();
+    int64_t t = 0;
+    for (int L = (int)depth; L >= 1; --L)
+        for (uint64_t c : cells[L]) {
+            uint8_t m = 0;
+            for (uint32_t o = 0; o < 8; ++o)
+                if (cells[L - 1].count(c * 8 + o)) m |= (uint8_t)(1u << o);
+            occ[t++] = m;
+        }
+    return t;
+}
+
 /* 1-16-1 ReLU network f(x) = sum_h w2[h] relu(w1[h] x + b1[h]) + b2 and its
  * mean-squared-error loss L = (1/n) sum_i (f(x_i) - t_i)^2, with the analytic
  * gradient in fp64.  Parameter order: w1[16], b1[16], w2[16], b2.  Returns L.

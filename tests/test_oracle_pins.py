@@ -390,3 +390,54 @@ def test_mlp_gradient_matches_finite_differences():
         e[j] = h
         num = (oracle.mlp_loss_grad(p + e, x, t)[0] - oracle.mlp_loss_grad(p - e, x, t)[0]) / (2 * h)
         assert abs(num - g[j]) <= 1e-6 * max(1.0, abs(g[j])), j
+
+
+# ------------------------------------------------------------ occupancy codes
+def _decode_occupancy(codes, depth):
+    """Rebuild the key set from occupancy codes, root first, level by level:
+    the decoder the paper describes (only the codes are needed)."""
+    prefixes, t = [0], 0
+    for _ in range(depth):
+        nxt = []
+        for p in prefixes:
+            c = int(codes[t])
+            t += 1
+            nxt.extend(p * 8 + o for o in range(8) if (c >> o) & 1)
+        prefixes = nxt
+    assert t == len(codes)
+    return np.array(prefixes, dtype=np.uint64)
+
+
+def test_occupancy_hand_examples():
+    # depth 1: voxels in octants 0 and 7 of the root
+    codes, counts = oracle.occupancy(np.array([0, 7], np.uint64), 1)
+    assert codes.tolist() == [0x81] and counts.tolist() == [2, 1]
+    # depth 2: voxel 0 (cell 0, octant 0) and voxel 63 (cell 7, octant 7)
+    codes, counts = oracle.occupancy(np.array([0, 63], np.uint64), 2)
+    assert codes.tolist() == [0x81, 0x01, 0x80] and counts.tolist() == [2, 2, 1]
+    # one voxel at the far corner of a depth-3 grid: one path of octant 7
+    codes, counts = oracle.occupancy(np.array([511], np.uint64), 3)
+    assert codes.tolist() == [0x80, 0x80, 0x80] and counts.tolist() == [1, 1, 1, 1]
+
+
+@pytest.mark.parametrize("depth,n", [(1, 5), (2, 30), (4, 300), (7, 5000), (10, 20000)])
+def test_occupancy_decodes_to_the_keys(depth, n):
+    rng = np.random.default_rng(depth * 1000 + n)
+    keys = np.unique(rng.integers(0, 8 ** depth, n, dtype=np.uint64))
+    codes, counts = oracle.occupancy(keys, depth)
+    np.testing.assert_array_equal(_decode_occupancy(codes, depth), keys)
+    # one code per occupied cell of levels depth .. 1, whose set bits are the
+    # occupied cells one level down
+    assert len(codes) == counts[1:].sum() and counts[0] == len(keys) and counts[depth] == 1
+    pc = np.unpackbits(codes[:, None], axis=1).sum(1)
+    off = 0
+    for L in range(depth, 0, -1):
+        assert pc[off:off + counts[L]].sum() == counts[L - 1]
+        off += counts[L]
+
+
+def test_occupancy_of_the_c1_cloud_decodes():
+    d = gen.c1_spheres(n=20000)
+    keys, _ = oracle.build(d["a"], d["grid"])
+    codes, _ = oracle.occupancy(keys, d["grid"].depth)
+    np.testing.assert_array_equal(_decode_occupancy(codes, d["grid"].depth), keys)
