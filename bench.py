@@ -342,6 +342,29 @@ def c5_learned_vs_binary(cga, device, reps):
     return out
 
 
+def occupancy_codes(cga, pipe, reps=20):
+    """Octree occupancy codes of the step's union (not part of the step):
+    average time of one cga_occupancy call, device sizes, events around reps."""
+    import torch
+    n = pipe.nu
+    occ = torch.empty(cga.occupancy_bound(n, pipe.g.depth), dtype=torch.uint8, device=pipe.m.device)
+    counts = torch.empty(pipe.g.depth + 1, dtype=torch.int64, device=pipe.m.device)
+    ws = cga.Workspaces(pipe.m.device)
+    run = lambda: cga.cga_occupancy(pipe.m, pipe.g, n=n, occ_out=occ, counts_out=counts, sync=False,
+                                    ws=ws)
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    codes = int(counts[1:].sum().item())
+    return {"keys": n, "codes": codes, "ms": round(ms, 4), "codes_per_s": codes / (ms * 1e-3)}
+
+
 def c4_batched(cga, device, reps):
     """256 LiDAR frames (log-uniform 10k..2M points) built and pair-merged by
     one replay of the captured graph; the sort's digit width and tile size
@@ -505,6 +528,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    line["occupancy"] = occupancy_codes(cga, pipe)
     if not args.no_c5:
         line["c5"] = c5_learned_vs_binary(cga, device, args.c5_reps)
     if not args.no_c4:

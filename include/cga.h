@@ -162,11 +162,31 @@ int cga_project(const cga_grid *grid, const void *d_keys, int64_t n, const int64
  * voxels exist) and d_d2 (uint64 squared distance, UINT64_MAX padding).
  * k in [1, 32]; n (the host bound) below 2^31 (else CGA_EINVAL).  MORTON
  * grids only (LINEAR: CGA_EUNSUPPORTED).
- * Errors: CGA_ENONFINITE for a non-finite query (device). */
+ * Errors: CGA_ENONFINITE for a non-finite query (device); CGA_EMISMATCH
+ * (device) when the keys are not sorted, unique and within the grid (the
+ * results are then unspecified, but every access stays in bounds). */
 size_t cga_knn_workspace_bytes(const cga_grid *grid, int64_t n, int64_t nq);
 int cga_knn(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,
             const float *d_q, int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2, void *d_ws,
             size_t ws_bytes, cga_stream stream);
+
+/* -------------------------------------------------------------- occupancy
+ * Octree occupancy codes (Section II-E: constructing the octree, coding of
+ * the occupancy codes) of a sorted unique MORTON key array.  The octree's
+ * level-L cells are the distinct key >> 3L; a cell's code has bit o set when
+ * its child in octant o (o = x_bit << 2 | y_bit << 1 | z_bit) is occupied.
+ * d_occ (nullable) receives the codes of levels depth .. 1, root first, one
+ * level after another, cells of a level in key order: sum_{L>=1} count[L]
+ * bytes.  d_counts (nullable, depth + 1 int64) receives count[L], the
+ * occupied cells per level (count[0] = n, count[depth] = 1 when n > 0).
+ * n below 2^31.  Errors: CGA_ECAPACITY (device) when the codes exceed occ_cap
+ * bytes (codes past occ_cap are not written); CGA_EMISMATCH (device) when the
+ * keys are not sorted, unique and within the grid; CGA_EUNSUPPORTED for a
+ * LINEAR grid. */
+size_t cga_occupancy_workspace_bytes(const cga_grid *grid, int64_t n);
+int cga_occupancy(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,
+                  uint8_t *d_occ, int64_t occ_cap, int64_t *d_counts, void *d_ws,
+                  size_t ws_bytes, cga_stream stream);
 
 /* ----------------------------------------------------------------- lookup
  * Point location and range start over a sorted unique uint64 key array (the

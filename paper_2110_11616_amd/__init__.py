@@ -111,6 +111,8 @@ _sig("cga_batch_graph_destroy", ctypes.c_int, _P)
 _sig("cga_autotune_workspace_bytes", _SZ, ctypes.c_uint32, _I64)
 _sig("cga_autotune_sort", ctypes.c_int, _P, ctypes.c_uint32, ctypes.c_uint32, _I64, _P, _SZ, _TP,
      ctypes.POINTER(ctypes.c_float), _P)
+_sig("cga_occupancy_workspace_bytes", _SZ, _GP, _I64)
+_sig("cga_occupancy", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _P, _SZ, _P)
 _sig("cga_prof_enable", ctypes.c_int, ctypes.c_char_p)
 _sig("cga_prof_disable", ctypes.c_int)
 _sig("cga_prof_reset", ctypes.c_int)
@@ -328,6 +330,32 @@ def cga_knn(keys: torch.Tensor, queries: torch.Tensor, grid, k: int, *, n=None, 
     if sync:
         _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_knn")
     return idx, d2
+
+
+def occupancy_bound(n: int, depth: int) -> int:
+    """Most occupancy codes n voxels can have: min(n, 8^(depth - L)) per level."""
+    return max(1, sum(min(n, 8 ** (depth - L)) for L in range(1, depth + 1)))
+
+
+def cga_occupancy(keys: torch.Tensor, grid, *, n=None, d_n=None, occ_out=None, counts_out=None,
+                  sync: bool = True, ws=None, stream=None):
+    """Octree occupancy codes (Section II-E), root first, level by level:
+    (uint8 codes, int64 cells per level).  Trimmed to the code count when sync."""
+    n = keys.shape[0] if n is None else int(n)
+    g = grid_struct(grid)
+    dev = keys.device
+    occ = occ_out if occ_out is not None else torch.empty(occupancy_bound(n, grid.depth),
+                                                          dtype=torch.uint8, device=dev)
+    counts = counts_out if counts_out is not None else torch.empty(grid.depth + 1,
+                                                                   dtype=torch.int64, device=dev)
+    wsb = _ws("occupancy", lib.cga_occupancy_workspace_bytes(ctypes.byref(g), n), ws)
+    _check(lib.cga_occupancy(ctypes.byref(g), _ptr(keys), n, _ptr(d_n), _ptr(occ), occ.numel(),
+                             _ptr(counts), _ptr(wsb), wsb.numel(), _stream(stream)), "cga_occupancy")
+    if sync:
+        _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_occupancy")
+        total = int(counts[1:].sum().item())
+        return occ[:total], counts
+    return occ, counts
 
 
 def cga_binary_lookup(keys: torch.Tensor, q: torch.Tensor, *, n=None, d_n=None, rank_out=None,

@@ -238,13 +238,19 @@ __global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, 
 }
 
 // Pass 4: one thread per node: child mask from the children's octants, and
-// the packed node word.
+// the packed node word.  With emit set, the masks are also the octree's
+// occupancy codes, written to occ (nullable) root first, level by level,
+// cells in key order (level L starts after the codes of levels depth .. L + 1),
+// and counts (nullable) gets the cells per level.
 template <typename K>
 __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, uint32_t depth,
                                                    const int64_t *__restrict__ lvl,
                                                    const uint32_t *__restrict__ first,
                                                    const uint8_t *__restrict__ oct,
-                                                   uint64_t *__restrict__ node, int64_t nodes_max) {
+                                                   uint64_t *__restrict__ node, int64_t nodes_max,
+                                                   bool emit, uint8_t *__restrict__ occ,
+                                                   int64_t occ_cap, int64_t *__restrict__ counts,
+                                                   uint32_t *err) {
     __shared__ int64_t s_n[kMaxDepth + 2], s_base[kMaxDepth + 2];
     if (threadIdx.x == 0) {
         s_n[0] = lvl[0];
@@ -258,6 +264,10 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
     }
     __syncthreads();
     const int64_t total = s_base[depth + 1];
+    if (emit && blockIdx.x == 0) {
+        if (counts && threadIdx.x <= depth) counts[threadIdx.x] = s_n[threadIdx.x];
+        if (threadIdx.x == 0 && occ && total > occ_cap) set_err(err, ERR_CAPACITY);
+    }
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
         uint32_t L = 1;
         while (L < depth && t >= s_base[L + 1]) ++L;
@@ -271,6 +281,10 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
             mask |= 1u << o;
         }
         node[t] = ((uint64_t)f0 << 8) | mask;
+        if (emit && occ) {
+            const int64_t o = total - s_base[L + 1] + j;  // codes of levels above L come first
+            if (o < occ_cap) occ[o] = (uint8_t)mask;
+        }
     }
 }
 
@@ -806,8 +820,10 @@ static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth) {
 
 template <typename K>
 static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64_t *d_n,
-                       uint32_t depth, hipStream_t s) {
-    CGA_PROF("knn_tree", s);
+                       uint32_t depth, hipStream_t s, const char *label = "knn_tree",
+                       bool emit = false, uint8_t *occ = nullptr, int64_t occ_cap = 0,
+                       int64_t *counts = nullptr) {
+    CGA_PROF(label, s);
     const int dt = dense_level(depth);
     k_tree_count<K><<<(unsigned)L.tiles, 256, 0, s>>>(keys, n, d_n, depth, L.tiles, L.cnt, L.dense,
                                                       dense_cells(depth), &L.ctl->err);
@@ -818,7 +834,7 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
     int64_t blocks = (L.nodes + 255) / 256;
     blocks = blocks < 4096 ? blocks : 4096;
     k_tree_mask<K><<<(unsigned)blocks, 256, 0, s>>>(keys, depth, L.lvl, L.first, L.oct, L.node,
-                                                    L.nodes);
+                                                    L.nodes, emit, occ, occ_cap, counts, &L.ctl->err);
 }
 
 template <int KT>
@@ -888,6 +904,31 @@ int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n
         else knn_launch<32>(g, L, d_q, nq, k, d_idx, d_d2, s);
         CGA_HIP(hipGetLastError());
     }
+    return CGA_OK;
+}
+
+size_t cga_occupancy_workspace_bytes(const cga_grid *g, int64_t n) {
+    if (!grid_valid(g) || n < 0) return 0;
+    return knn_layout(nullptr, n, g->depth).bytes;
+}
+
+int cga_occupancy(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n,
+                  uint8_t *d_occ, int64_t occ_cap, int64_t *d_counts, void *d_ws, size_t ws_bytes,
+                  cga_stream stream) {
+    if (!grid_valid(g) || n < 0 || n > INT32_MAX || occ_cap < 0 || !d_ws) return CGA_EINVAL;
+    if ((n > 0 && !d_keys) || (occ_cap > 0 && !d_occ)) return CGA_EINVAL;
+    if (g->key_mode != CGA_KEY_MORTON) return CGA_EUNSUPPORTED;
+    KnnLayout L = knn_layout(d_ws, n, g->depth);
+    if (ws_bytes < L.bytes) return CGA_EWORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    CGA_TRY(launch_begin(L.ctl, nullptr, 0, nullptr, 0, nullptr, s));
+    if (wide_keys(g->depth))
+        tree_build<uint64_t>(L, (const uint64_t *)d_keys, n, d_n, g->depth, s, "occupancy", true,
+                             d_occ, occ_cap, d_counts);
+    else
+        tree_build<uint32_t>(L, (const uint32_t *)d_keys, n, d_n, g->depth, s, "occupancy", true,
+                             d_occ, occ_cap, d_counts);
+    CGA_HIP(hipGetLastError());
     return CGA_OK;
 }
 

@@ -291,6 +291,64 @@ def test_knn_edges(gpu):
     _check_knn(gpu, k21, rng.uniform(0, 1, (500, 3)).astype(np.float32), g21, 4)
 
 
+# --------------------------------------------------------------- occupancy
+def _check_occupancy(gpu, keys_gpu, g):
+    codes, counts = gpu.cga_occupancy(keys_gpu, g)
+    wcodes, wcounts = oracle.occupancy(u64(keys_gpu), g.depth)
+    np.testing.assert_array_equal(counts.cpu().numpy(), wcounts)
+    np.testing.assert_array_equal(codes.cpu().numpy(), wcodes)
+
+
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s", "w_c3s"])
+def test_occupancy(gpu, wl, request):
+    d = _wl(wl, request)
+    g = d["grid"]
+    k, _ = gpu.cga_build(dev(d["a"]), g)
+    say("occupancy", wl, k.shape[0])
+    _check_occupancy(gpu, k, g)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 7, 8, 11, 21])
+def test_occupancy_depths(gpu, depth):
+    rng = np.random.default_rng(40 + depth)
+    g = Grid((0.0, 0.0, 0.0), float(2 ** depth), depth, M)
+    xyz = rng.uniform(0, 1, (3000, 3)).astype(np.float32)
+    k, _ = gpu.cga_build(dev(xyz), g)
+    _check_occupancy(gpu, k, g)
+
+
+def test_occupancy_edges(gpu, w_c1):
+    g = w_c1["grid"]
+    k, _ = gpu.cga_build(dev(w_c1["a"]), g)
+    _check_occupancy(gpu, k[:1], g)
+    codes, counts = gpu.cga_occupancy(k[:0], g)
+    assert codes.numel() == 0 and counts.cpu().numpy().tolist() == [0] * (g.depth + 1)
+    # counts only (no code buffer), and a code buffer one byte short
+    cnt = torch.empty(g.depth + 1, dtype=torch.int64, device="cuda")
+    wcodes, wcounts = oracle.occupancy(u64(k), g.depth)
+    ws = gpu.Workspaces("cuda")
+    wsb = gpu._ws("occupancy", gpu.lib.cga_occupancy_workspace_bytes(
+        gpu.ctypes.byref(gpu.grid_struct(g)), k.shape[0]), ws)
+    assert gpu.lib.cga_occupancy(gpu.ctypes.byref(gpu.grid_struct(g)), gpu._ptr(k), k.shape[0],
+                                 None, None, 0, gpu._ptr(cnt), gpu._ptr(wsb), wsb.numel(),
+                                 gpu._stream()) == 0
+    assert gpu.lib.cga_ws_status(gpu._ptr(wsb), gpu._stream()) == 0
+    np.testing.assert_array_equal(cnt.cpu().numpy(), wcounts)
+    short = torch.empty(len(wcodes) - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_occupancy(k, g, occ_out=short)
+    assert e.value.status == gpu.ECAPACITY
+    np.testing.assert_array_equal(short.cpu().numpy(), wcodes[:-1])
+
+
+def test_occupancy_linear_unsupported(gpu, w_c1):
+    g = w_c1["grid"].with_mode(L)
+    k, _ = gpu.cga_build(dev(w_c1["a"]), g)
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_occupancy(k, g)
+    assert e.value.status == gpu.EUNSUPPORTED
+
+
 def test_knn_linear_unsupported(gpu, w_c1):
     g = w_c1["grid"].with_mode(L)
     k, _ = gpu.cga_build(dev(w_c1["a"]), g)
