@@ -56,6 +56,7 @@ def _load():
         lib.gen_subset.restype = i64
         lib.gen_shuffle_i64.argtypes = [u64, i64, P]
         lib.gen_raw.argtypes = [u64, u64, u64, i32, P]
+        lib.gen_attributes.argtypes = [u64, u64, i64, P]
         _lib = lib
     return _lib
 
@@ -198,6 +199,15 @@ def shuffle(seed: int, a: np.ndarray) -> np.ndarray:
     a = np.ascontiguousarray(a, np.int64).copy()
     lib.gen_shuffle_i64(seed, len(a), _p(a))
     return a
+
+
+def attributes(seed: int, stream: int, n: int) -> np.ndarray:
+    """Seeded per-point attributes: four 8-bit channels packed in uint32
+    (channel c in bits 8c .. 8c + 7), e.g. RGB plus one spare channel."""
+    lib = _load()
+    out = np.empty(n, np.uint32)
+    lib.gen_attributes(seed, stream, n, _p(out))
+    return out
 
 
 def raw(seed: int, stream: int, index: int, n: int) -> np.ndarray:

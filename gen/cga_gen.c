@@ -310,3 +310,15 @@ void gen_raw(uint64_t seed, uint64_t stream, uint64_t index, int n, uint64_t *ou
     rng_init(&r, seed, stream, index);
     for (int i = 0; i < n; ++i) out[i] = rng_next(&r);
 }
+
+/* Seeded per-point attributes: four 8-bit channels packed in a uint32
+ * (channel c in bits 8c .. 8c + 7), uniform, one draw per point from stream
+ * (seed, stream, point index). */
+void gen_attributes(uint64_t seed, uint64_t stream, int64_t n, uint32_t *out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        rng_t r;
+        rng_init(&r, seed, stream, (uint64_t)i);
+        out[i] = (uint32_t)(rng_next(&r) >> 32);
+    }
+}

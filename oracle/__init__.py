@@ -60,6 +60,10 @@ def _load():
         lib.or_lower_bound.argtypes = [P, i64, P, i64, P, P]
         lib.or_mlp_loss_grad.argtypes = [P, P, P, i64, P, P]
         lib.or_occupancy.argtypes = [P, i64, u32, P, P]
+        lib.or_voxel_values.argtypes = [P, i64, P, P, f32, u32, i32, P, P]
+        lib.or_voxel_values.restype = i64
+        lib.or_merge_values.argtypes = [P, P, i64, P, P, i64, i32, P, P]
+        lib.or_merge_values.restype = i64
         lib.or_occupancy.restype = i64
         lib.or_mlp_loss_grad.restype = ctypes.c_double
         _lib = lib
@@ -211,6 +215,36 @@ def lower_bound(keys, q):
     found = np.empty(len(q), np.uint8)
     _load().or_lower_bound(_p(keys), len(keys), _p(q), len(q), _p(rank), _p(found))
     return rank, found
+
+
+def voxel_values(xyz, attr, grid):
+    """Value array (Section V): (keys, per-voxel channel-wise average of the
+    points' packed 4 x 8-bit values, rounded half up)."""
+    xyz = _f32(xyz)
+    attr = np.ascontiguousarray(attr, np.uint32)
+    keys = np.empty(len(xyz), np.uint64)
+    vals = np.empty(len(xyz), np.uint32)
+    u = _load().or_voxel_values(_p(xyz), len(xyz), _p(attr), _p(_origin(grid)), grid.scale,
+                                grid.depth, grid.key_mode, _p(keys), _p(vals))
+    if u < 0:
+        raise NonFinite("non-finite coordinate")
+    return keys[:u].copy(), vals[:u].copy()
+
+
+BASE, AVERAGE = 0, 1
+
+
+def merge_values(ka, va, kb, vb, policy: int):
+    """Merge with values (Eq. (1), Section II-A): (union keys, values) with the
+    base's (a's) value or the rounded channel average on overlapping voxels."""
+    ka, kb = _u64(ka), _u64(kb)
+    va = np.ascontiguousarray(va, np.uint32)
+    vb = np.ascontiguousarray(vb, np.uint32)
+    keys = np.empty(len(ka) + len(kb), np.uint64)
+    vals = np.empty(len(ka) + len(kb), np.uint32)
+    u = _load().or_merge_values(_p(ka), _p(va), len(ka), _p(kb), _p(vb), len(kb), policy,
+                                _p(keys), _p(vals))
+    return keys[:u].copy(), vals[:u].copy()
 
 
 def occupancy(keys, depth: int):

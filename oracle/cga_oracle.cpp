@@ -462,6 +462,71 @@ void or_lower_bound(const uint64_t *keys, int64_t n, const uint64_t *q, int64_t 
     }
 }
 
+/* Attribute payload: the Value array of Section V.  Each point carries four
+ * 8-bit channels packed in a uint32 (channel c in bits 8c .. 8c + 7).  A
+ * voxel's value is the channel-wise average of its points' values, as the
+ * grid downsampling of Section III-B averages the colours of the points in
+ * a box, each channel rounded half up: floor((2 sum + count) / (2 count)).
+ * Outputs keys (ascending) and values; returns U, or -4 for a non-finite
+ * coordinate. */
+static uint32_t channel_average(const uint64_t sum[4], uint64_t count) {
+    uint32_t v = 0;
+    for (int c = 0; c < 4; ++c) {
+        const uint64_t a = (2 * sum[c] + count) / (2 * count);
+        v |= (uint32_t)a << (8 * c);
+    }
+    return v;
+}
+
+int64_t or_voxel_values(const float *xyz, int64_t n, const uint32_t *attr, const float *origin,
+                        float scale, uint32_t depth, int mode, uint64_t *keys, uint32_t *values) {
+    std::map<uint64_t, std::array<uint64_t, 5>> acc;  // channel sums, point count
+    for (int64_t i = 0; i < n; ++i) {
+        Voxel v;
+        if (!quantize_point(xyz + 3 * i, origin, scale, depth, v)) return -4;
+        auto &a = acc[encode(v, depth, mode)];
+        for (int c = 0; c < 4; ++c) a[c] += (attr[i] >> (8 * c)) & 0xFFu;
+        a[4] += 1;
+    }
+    int64_t u = 0;
+    for (const auto &kv : acc) {
+        keys[u] = kv.first;
+        values[u] = channel_average(kv.second.data(), kv.second[4]);
+        ++u;
+    }
+    return u;
+}
+
+/* Values of a merge, Eq. (1): a voxel of only one cloud keeps its value; a
+ * voxel of both keeps the base cloud's (a's) value under policy 0, or takes
+ * the channel-wise average of the two values (rounded half up) under policy
+ * 1 -- the two choices Section II-A gives for overlapping points.  Returns
+ * the union size. */
+int64_t or_merge_values(const uint64_t *ka, const uint32_t *va, int64_t na, const uint64_t *kb,
+                        const uint32_t *vb, int64_t nb, int policy, uint64_t *keys,
+                        uint32_t *values) {
+    std::map<uint64_t, uint32_t> m;
+    for (int64_t i = 0; i < na; ++i) m[ka[i]] = va[i];
+    for (int64_t i = 0; i < nb; ++i) {
+        auto it = m.find(kb[i]);
+        if (it == m.end()) {
+            m[kb[i]] = vb[i];
+        } else if (policy == 1) {
+            uint64_t sum[4];
+            for (int c = 0; c < 4; ++c)
+                sum[c] = ((it->second >> (8 * c)) & 0xFFu) + ((vb[i] >> (8 * c)) & 0xFFu);
+            it->second = channel_average(sum, 2);
+        }
+    }
+    int64_t u = 0;
+    for (const auto &kv : m) {
+        keys[u] = kv.first;
+        values[u] = kv.second;
+        ++u;
+    }
+    return u;
+}
+
 /* Octree occupancy codes (Section II-E, point cloud compression: constructing
  * the octree, coding of the occupancy codes).  The octree of a MORTON key set
  * has, at level L, one occupied cell per distinct key >> 3L; a cell's 8-bit

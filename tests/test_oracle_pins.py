@@ -441,3 +441,81 @@ def test_occupancy_of_the_c1_cloud_decodes():
     keys, _ = oracle.build(d["a"], d["grid"])
     codes, _ = oracle.occupancy(keys, d["grid"].depth)
     np.testing.assert_array_equal(_decode_occupancy(codes, d["grid"].depth), keys)
+
+
+# ------------------------------------------------------------ attribute values
+def _pack(rgb):
+    rgb = np.asarray(rgb, np.uint32)
+    return rgb[:, 0] | (rgb[:, 1] << 8) | (rgb[:, 2] << 16)
+
+
+def _soldier():
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    pts = np.array(json.load(open(os.path.join(here, "table2_points.json")))["soldier"], np.float32)
+    rgb = json.load(open(os.path.join(here, "table2_colors.json")))["soldier_rgb"]
+    return pts, _pack(rgb)
+
+
+def test_values_table2_soldier():
+    pts, col = _soldier()
+    # one voxel per printed point: each keeps its own colour
+    g = Grid((0.0, 0.0, 0.0), 1.0, 8, gen.KEY_MORTON)
+    keys, vals = oracle.voxel_values(pts, col, g)
+    want = {int(k): int(c) for k, c in zip(oracle.encode(oracle.quantize(pts, g), 8, 0), col)}
+    assert {int(k): int(v) for k, v in zip(keys, vals)} == want
+    # at scale 1/4 the first four rows share voxel (31, 3, 39) -- all
+    # (82, 73, 67) -- and the last two share (31, 4, 38): (79, 72, 67) and
+    # (83, 77, 73) average to (81, 74.5 -> 75, 70)
+    g4 = Grid((0.0, 0.0, 0.0), 0.25, 8, gen.KEY_MORTON)
+    keys, vals = oracle.voxel_values(pts, col, g4)
+    got = {tuple(int(c) for c in oracle.decode(np.array([k], np.uint64), 8, 0)[0]): int(v)
+           for k, v in zip(keys, vals)}
+    assert got == {(31, 3, 39): int(_pack([[82, 73, 67]])[0]),
+                   (31, 4, 38): int(_pack([[81, 75, 70]])[0])}
+
+
+def test_values_rounding_and_invariances():
+    g = Grid((0.0, 0.0, 0.0), 1.0, 4, gen.KEY_MORTON)
+    one = np.zeros((2, 3), np.float32)  # two points, one voxel
+    _, v = oracle.voxel_values(one, np.array([0x000000FF, 0x00000001], np.uint32), g)
+    assert v.tolist() == [128]          # (255 + 1) / 2
+    _, v = oracle.voxel_values(one, np.array([0x01020301, 0x01030402], np.uint32), g)
+    assert v.tolist() == [0x01030402]   # halves round up: 1.5 -> 2, 3.5 -> 4, 2.5 -> 3
+    rng = np.random.default_rng(7)
+    xyz = rng.uniform(0, 16, (5000, 3)).astype(np.float32)
+    attr = gen.attributes(7, 1, len(xyz))
+    k1, v1 = oracle.voxel_values(xyz, attr, g)
+    perm = rng.permutation(len(xyz))
+    k2, v2 = oracle.voxel_values(xyz[perm], attr[perm], g)
+    assert np.array_equal(k1, k2) and np.array_equal(v1, v2)   # order of points is irrelevant
+    kb, _ = oracle.build(xyz, g)
+    assert np.array_equal(k1, kb)                              # same voxels as the build
+    kc, vc = oracle.voxel_values(xyz, np.full(len(xyz), 0x11223344, np.uint32), g)
+    assert (vc == 0x11223344).all()                            # constant colour stays
+
+
+def test_merge_values_policies():
+    rng = np.random.default_rng(8)
+    ka = np.unique(rng.integers(0, 4096, 900).astype(np.uint64))
+    kb = np.unique(rng.integers(0, 4096, 900).astype(np.uint64))
+    va = gen.attributes(8, 1, len(ka))
+    vb = gen.attributes(8, 2, len(kb))
+    m, _ = oracle.merge(ka, kb, 4, 0)
+    for pol in (oracle.BASE, oracle.AVERAGE):
+        k, v = oracle.merge_values(ka, va, kb, vb, pol)
+        assert np.array_equal(k, m)
+    kbase, vbase = oracle.merge_values(ka, va, kb, vb, oracle.BASE)
+    kavg, vavg = oracle.merge_values(ka, va, kb, vb, oracle.AVERAGE)
+    both = np.intersect1d(ka, kb)
+    ia, ib, ix = (np.searchsorted(ka, both), np.searchsorted(kb, both), np.searchsorted(kbase, both))
+    assert np.array_equal(vbase[ix], va[ia])                   # base wins
+    ch = lambda x, c: (x >> (8 * c)) & 0xFF
+    for c in range(4):
+        assert np.array_equal(ch(vavg[ix], c), (ch(va[ia], c) + ch(vb[ib], c) + 1) // 2)
+    only_b = np.setdiff1d(kb, ka)
+    assert np.array_equal(vbase[np.searchsorted(kbase, only_b)], vb[np.searchsorted(kb, only_b)])
+    # the average is symmetric; merging with an empty cloud changes nothing
+    k2, v2 = oracle.merge_values(kb, vb, ka, va, oracle.AVERAGE)
+    assert np.array_equal(k2, kavg) and np.array_equal(v2, vavg)
+    k3, v3 = oracle.merge_values(ka, va, ka[:0], va[:0], oracle.AVERAGE)
+    assert np.array_equal(k3, ka) and np.array_equal(v3, va)
