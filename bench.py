@@ -365,6 +365,39 @@ def occupancy_codes(cga, pipe, reps=20):
     return {"keys": n, "codes": codes, "ms": round(ms, 4), "codes_per_s": codes / (ms * 1e-3)}
 
 
+def attribute_values(cga, pipe, d, reps=20):
+    """Value arrays of the step's two sweeps from seeded per-point attributes,
+    and the merged cloud's values (average policy); not part of the step."""
+    import torch
+
+    import gen
+    dev = pipe.m.device
+    aa = torch.from_numpy(gen.attributes(1007, 1, pipe.na).view("int32")).to(dev)
+    ab = torch.from_numpy(gen.attributes(1007, 2, pipe.nb).view("int32")).to(dev)
+    ua, ub, um = [int(x) for x in pipe.cnt[:3].cpu().tolist()]
+    va = torch.empty(max(ua, 1), dtype=torch.int32, device=dev)
+    vb = torch.empty(max(ub, 1), dtype=torch.int32, device=dev)
+    vm = torch.empty(max(um, 1), dtype=torch.int32, device=dev)
+    ws = cga.Workspaces(dev)
+
+    def run():
+        cga.cga_voxel_values(pipe.a, aa, pipe.ka, pipe.g, u=ua, out=va, sync=False, ws=ws)
+        cga.cga_voxel_values(pipe.b, ab, pipe.kb, pipe.g, u=ub, out=vb, sync=False, ws=ws)
+        cga.cga_merge_values(pipe.ka, va, pipe.kb, vb, pipe.m, pipe.g, cga.VALUES_AVERAGE, na=ua,
+                             nb=ub, nm=um, out=vm, sync=False, ws=ws)
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"points": pipe.na + pipe.nb, "voxels": [ua, ub, um], "ms": round(ms, 4),
+            "points_per_s": (pipe.na + pipe.nb) / (ms * 1e-3)}
+
+
 def c4_batched(cga, device, reps):
     """256 LiDAR frames (log-uniform 10k..2M points) built and pair-merged by
     one replay of the captured graph; the sort's digit width and tile size
@@ -529,6 +562,7 @@ def main():
         "cpu_baseline": None,
     }
     line["occupancy"] = occupancy_codes(cga, pipe)
+    line["values"] = attribute_values(cga, pipe, d)
     if not args.no_c5:
         line["c5"] = c5_learned_vs_binary(cga, device, args.c5_reps)
     if not args.no_c4:

@@ -170,6 +170,37 @@ int cga_knn(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *
             const float *d_q, int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2, void *d_ws,
             size_t ws_bytes, cga_stream stream);
 
+/* ------------------------------------------------------------- values
+ * The Value array (Section V): per-voxel attributes from per-point ones.
+ * d_attr holds n packed values, four 8-bit channels each (channel c in bits
+ * 8c .. 8c + 7; RGB as in Table II fits).  d_keys is the CGA of the same
+ * points on the same grid (cga_build): u sorted unique keys, device count
+ * d_u nullable.  d_values (u uint32) receives each voxel's channel-wise
+ * average of its points' values, rounded half up, floor((2 sum + count) /
+ * (2 count)) -- the averaging of colours in a grid box that Section III-B's
+ * downsampling applies.  Workspace: cga_voxel_values_workspace_bytes(u).
+ * Errors: CGA_ENONFINITE (device) for a non-finite point; CGA_EMISMATCH
+ * (device) when a point's voxel is not among the keys or a key has no point. */
+size_t cga_voxel_values_workspace_bytes(int64_t u);
+int cga_voxel_values(const cga_grid *grid, const float *d_xyz, int64_t n, const uint32_t *d_attr,
+                     const void *d_keys, int64_t u, const int64_t *d_u, uint32_t *d_values,
+                     void *d_ws, size_t ws_bytes, cga_stream stream);
+
+/* Values of a merge, Eq. (1): for every key of the union d_keys_m (cga_merge
+ * of the same two CGAs), the value of the input holding it; a key in both
+ * takes a's value (CGA_VALUES_BASE, a is the base cloud) or the channel-wise
+ * average of the two values, rounded half up (CGA_VALUES_AVERAGE) -- the two
+ * rules Section II-A gives for overlapping points.  Device counts nullable.
+ * Errors: CGA_EINVAL for another policy; CGA_EMISMATCH (device) when a union
+ * key is in neither input. */
+enum { CGA_VALUES_BASE = 0, CGA_VALUES_AVERAGE = 1 };
+size_t cga_merge_values_workspace_bytes(void);
+int cga_merge_values(const cga_grid *grid, const void *d_keys_a, const uint32_t *d_values_a,
+                     int64_t na, const int64_t *d_na, const void *d_keys_b,
+                     const uint32_t *d_values_b, int64_t nb, const int64_t *d_nb,
+                     const void *d_keys_m, int64_t nm, const int64_t *d_nm, int policy,
+                     uint32_t *d_values_m, void *d_ws, size_t ws_bytes, cga_stream stream);
+
 /* -------------------------------------------------------------- occupancy
  * Octree occupancy codes (Section II-E: constructing the octree, coding of
  * the occupancy codes) of a sorted unique MORTON key array.  The octree's

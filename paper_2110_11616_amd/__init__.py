@@ -111,6 +111,11 @@ _sig("cga_batch_graph_destroy", ctypes.c_int, _P)
 _sig("cga_autotune_workspace_bytes", _SZ, ctypes.c_uint32, _I64)
 _sig("cga_autotune_sort", ctypes.c_int, _P, ctypes.c_uint32, ctypes.c_uint32, _I64, _P, _SZ, _TP,
      ctypes.POINTER(ctypes.c_float), _P)
+_sig("cga_voxel_values_workspace_bytes", _SZ, _I64)
+_sig("cga_voxel_values", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _P, _P, _SZ, _P)
+_sig("cga_merge_values_workspace_bytes", _SZ)
+_sig("cga_merge_values", ctypes.c_int, _GP, _P, _P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _P,
+     ctypes.c_int, _P, _P, _SZ, _P)
 _sig("cga_occupancy_workspace_bytes", _SZ, _GP, _I64)
 _sig("cga_occupancy", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _P, _SZ, _P)
 _sig("cga_prof_enable", ctypes.c_int, ctypes.c_char_p)
@@ -330,6 +335,47 @@ def cga_knn(keys: torch.Tensor, queries: torch.Tensor, grid, k: int, *, n=None, 
     if sync:
         _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_knn")
     return idx, d2
+
+
+VALUES_BASE, VALUES_AVERAGE = 0, 1
+
+
+def cga_voxel_values(xyz: torch.Tensor, attr: torch.Tensor, keys: torch.Tensor, grid, *, u=None,
+                     d_u=None, out=None, sync: bool = True, ws=None, stream=None) -> torch.Tensor:
+    """Value array (Section V): per-voxel channel averages of the points'
+    packed 4 x 8-bit attributes (int32 tensor of uint32 bit patterns)."""
+    n = xyz.shape[0]
+    u = keys.shape[0] if u is None else int(u)
+    g = grid_struct(grid)
+    vals = out if out is not None else torch.empty(max(u, 1), dtype=torch.int32, device=keys.device)
+    wsb = _ws("values", lib.cga_voxel_values_workspace_bytes(u), ws)
+    _check(lib.cga_voxel_values(ctypes.byref(g), _ptr(xyz), n, _ptr(attr), _ptr(keys), u, _ptr(d_u),
+                                _ptr(vals), _ptr(wsb), wsb.numel(), _stream(stream)),
+           "cga_voxel_values")
+    if sync:
+        _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_voxel_values")
+        return vals[:u]
+    return vals
+
+
+def cga_merge_values(ka, va, kb, vb, km, grid, policy: int, *, na=None, d_na=None, nb=None,
+                     d_nb=None, nm=None, d_nm=None, out=None, sync: bool = True, ws=None,
+                     stream=None) -> torch.Tensor:
+    """Values of the union km of two CGAs (Eq. (1)), base or average on overlap."""
+    na = ka.shape[0] if na is None else int(na)
+    nb = kb.shape[0] if nb is None else int(nb)
+    nm = km.shape[0] if nm is None else int(nm)
+    g = grid_struct(grid)
+    vals = out if out is not None else torch.empty(max(nm, 1), dtype=torch.int32, device=km.device)
+    wsb = _ws("merge_values", lib.cga_merge_values_workspace_bytes(), ws)
+    _check(lib.cga_merge_values(ctypes.byref(g), _ptr(ka), _ptr(va), na, _ptr(d_na), _ptr(kb),
+                                _ptr(vb), nb, _ptr(d_nb), _ptr(km), nm, _ptr(d_nm), int(policy),
+                                _ptr(vals), _ptr(wsb), wsb.numel(), _stream(stream)),
+           "cga_merge_values")
+    if sync:
+        _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_merge_values")
+        return vals[:nm]
+    return vals
 
 
 def occupancy_bound(n: int, depth: int) -> int:

@@ -349,6 +349,65 @@ def test_occupancy_linear_unsupported(gpu, w_c1):
     assert e.value.status == gpu.EUNSUPPORTED
 
 
+# ------------------------------------------------------------------ values
+def _u32(t):
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s", "w_c3s"])
+@pytest.mark.parametrize("mode", [M, L])
+def test_voxel_values(gpu, wl, mode, request):
+    d = _wl(wl, request)
+    g = d["grid"].with_mode(mode)
+    attr = gen.attributes(51, 1, len(d["a"]))
+    k, _ = gpu.cga_build(dev(d["a"]), g)
+    v = gpu.cga_voxel_values(dev(d["a"]), dev(attr.view(np.int32)), k, g)
+    wk, wv = oracle.voxel_values(d["a"], attr, g)
+    np.testing.assert_array_equal(u64(k), wk)
+    np.testing.assert_array_equal(_u32(v), wv)
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s"])
+def test_merge_values(gpu, wl, policy, request):
+    d = _wl(wl, request)
+    g = d["grid"]
+    aa, ab = gen.attributes(52, 1, len(d["a"])), gen.attributes(52, 2, len(d["b"]))
+    ka, _ = gpu.cga_build(dev(d["a"]), g)
+    kb, _ = gpu.cga_build(dev(d["b"]), g)
+    va = gpu.cga_voxel_values(dev(d["a"]), dev(aa.view(np.int32)), ka, g)
+    vb = gpu.cga_voxel_values(dev(d["b"]), dev(ab.view(np.int32)), kb, g)
+    km, _ = gpu.cga_merge(ka, kb, g)
+    vm = gpu.cga_merge_values(ka, va, kb, vb, km, g, policy)
+    wka, wva = oracle.voxel_values(d["a"], aa, g)
+    wkb, wvb = oracle.voxel_values(d["b"], ab, g)
+    wkm, wvm = oracle.merge_values(wka, wva, wkb, wvb, policy)
+    np.testing.assert_array_equal(u64(km), wkm)
+    np.testing.assert_array_equal(_u32(vm), wvm)
+
+
+def test_values_edges(gpu, w_c1):
+    g = w_c1["grid"]
+    pts = np.zeros((5, 3), np.float32)   # all in one voxel
+    attr = np.array([1, 2, 2, 2, 2], np.uint32) | (np.array([255, 255, 0, 0, 0], np.uint32) << 8)
+    k, _ = gpu.cga_build(dev(pts), g)
+    v = gpu.cga_voxel_values(dev(pts), dev(attr.view(np.int32)), k, g)
+    assert _u32(v).tolist() == oracle.voxel_values(pts, attr, g)[1].tolist()
+    # a point whose voxel is not among the keys
+    other = np.ones((1, 3), np.float32) * 0.5
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_voxel_values(dev(other), dev(attr[:1].view(np.int32)), k, g)
+    assert e.value.status == gpu.EMISMATCH
+    # empty clouds
+    ke = k[:0]
+    assert gpu.cga_voxel_values(dev(pts[:0]), dev(attr[:0].view(np.int32)), ke, g).numel() == 0
+    vm = gpu.cga_merge_values(k, v, ke, v[:0], k, g, 1)
+    assert _u32(vm).tolist() == _u32(v).tolist()
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_merge_values(k, v, ke, v[:0], k, g, 2)
+    assert e.value.status == gpu.EINVAL
+
+
 def test_knn_linear_unsupported(gpu, w_c1):
     g = w_c1["grid"].with_mode(L)
     k, _ = gpu.cga_build(dev(w_c1["a"]), g)
