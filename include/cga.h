@@ -161,7 +161,10 @@ int cga_project(const cga_grid *grid, const void *d_keys, int64_t n, const int64
  * d_idx (int64 position in the key array, -1 padding when fewer than k
  * voxels exist) and d_d2 (uint64 squared distance, UINT64_MAX padding).
  * k in [1, 32]; n (the host bound) below 2^31 (else CGA_EINVAL).  MORTON
- * grids only (LINEAR: CGA_EUNSUPPORTED).
+ * grids only (LINEAR: CGA_EUNSUPPORTED).  From 2^18 queries on, the queries
+ * are searched in the order of their Morton keys (results are unchanged;
+ * the workspace then grows by about 24 bytes per query, so size it with the
+ * same nq as the call).
  * Errors: CGA_ENONFINITE for a non-finite query (device); CGA_EMISMATCH
  * (device) when the keys are not sorted, unique and within the grid (the
  * results are then unspecified, but every access stays in bounds). */

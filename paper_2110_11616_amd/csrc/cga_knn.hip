@@ -28,6 +28,7 @@
 #include <cstdlib>
 
 #include "cga_common.h"
+#include "cga_sort.h"
 
 namespace cga {
 
@@ -39,6 +40,11 @@ constexpr int kTreeRows = 4;                       // rows of 256 keys per build
 constexpr int kTreeTile = kTreeRows * 256;         // keys per build tile
 constexpr int kLaDefault = 4;                      // round-0 cell level
 constexpr uint32_t kPackedDepth = 15;              // deepest grid with 32-bit squared distances
+// Large query sets are answered in the order of the top kOrderBits of their
+// Morton keys (a 3-pass sort of index << kOrderBits | key bits), so that the
+// teams of a wave search neighbouring regions: similar costs, shared nodes.
+constexpr int kOrderBits = 24;
+constexpr int64_t kOrderMin = (int64_t)1 << 18;
 
 template <typename K>
 __device__ __forceinline__ int64_t lower_bound_dev(const K *keys, int64_t n, K q) {
@@ -481,8 +487,8 @@ template <int KT, class LIST>
 __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
     const uint64_t *__restrict__ node, const uint32_t *__restrict__ dense,
     const int64_t *__restrict__ lvl, int64_t nodes_max, const float *__restrict__ q, int64_t nq,
-    float o0, float o1, float o2, float scale, uint32_t depth, int k, int la,
-    int64_t *__restrict__ idx_out, uint64_t *__restrict__ d2_out, uint32_t *err) {
+    const uint64_t *__restrict__ order, float o0, float o1, float o2, float scale, uint32_t depth,
+    int k, int la, int64_t *__restrict__ idx_out, uint64_t *__restrict__ d2_out, uint32_t *err) {
     using Dist = typename LIST::Dist;
     extern __shared__ uint64_t s_word[];  // open node word per level, one column per thread
     __shared__ unsigned long long s_bound[kTeamsPerBlock];
@@ -497,8 +503,9 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
     }
     if (tl == 0) s_bound[team] = LIST::kNone;
     __syncthreads();  // the only block-wide barrier; teams run independently after it
-    const int64_t j = (int64_t)blockIdx.x * kTeamsPerBlock + team;
-    if (j >= nq) return;
+    const int64_t slot = (int64_t)blockIdx.x * kTeamsPerBlock + team;
+    if (slot >= nq) return;
+    const int64_t j = order ? (int64_t)(order[slot] >> kOrderBits) : slot;  // query (and output row)
     // an oversized tree (keys that are not a CGA of the grid) searches nothing
     const int64_t n = tree_total(lvl, depth, nodes_max) < 0 ? 0 : lvl[0];
     const int dt = dense_level(depth);
@@ -768,6 +775,30 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
     }
 }
 
+// Ordering code of every query: its index above the top kOrderBits of its
+// Morton key, with the digit histogram of the three 8-bit passes.
+__global__ __launch_bounds__(256) void k_knn_order(const float *__restrict__ q, int64_t nq, float o0,
+                                                   float o1, float o2, float scale,
+                                                   uint32_t depth, uint64_t *__restrict__ out,
+                                                   uint32_t *hist) {
+    constexpr int RB = 8, PASSES = kOrderBits / RB;
+    __shared__ uint32_t s_h[PASSES << RB];
+    for (int i = threadIdx.x; i < (PASSES << RB); i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const float o[3] = {o0, o1, o2};
+    const int drop = 3 * (int)depth > kOrderBits ? 3 * (int)depth - kOrderBits : 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        Vox v;
+        quantize3(q[3 * i], q[3 * i + 1], q[3 * i + 2], o, scale, depth, v);  // the search reports non-finite queries
+        const uint64_t code = ((uint64_t)i << kOrderBits) | (enc3(v.x, v.y, v.z, depth, false) >> drop);
+        out[i] = code;
+        hist_add<RB>(s_h, code, PASSES);
+    }
+    __syncthreads();
+    hist_flush<RB>(s_h, hist, PASSES);
+}
+
 // Launch knob (never changes results): CGA_KNN_LA = level of the round-0 cell.
 static int knn_la(uint32_t depth) {
     int la = kLaDefault;
@@ -776,6 +807,13 @@ static int knn_la(uint32_t depth) {
         if (v >= 1 && v <= kMaxDepth) la = v;
     }
     return la < (int)depth ? la : (int)depth;
+}
+
+// Launch knob (never changes results): CGA_KNN_ORDER = 1 / 0 forces the query
+// ordering on / off; by default it is on from kOrderMin queries.
+static bool knn_order(int64_t nq) {
+    if (const char *e = getenv("CGA_KNN_ORDER")) return atoi(e) != 0 && nq > 0;
+    return nq >= kOrderMin;
 }
 
 // Upper bound on the number of octree nodes of n unique keys: level L has at
@@ -792,6 +830,8 @@ static int64_t tree_nodes_max(int64_t n, uint32_t depth) {
 
 struct KnnLayout {
     Control *ctl;
+    SortWs sort;             // query ordering (when on)
+    uint64_t *oa = nullptr, *ob = nullptr;
     uint32_t *cnt;
     int64_t *lvl;
     uint32_t *first;
@@ -802,12 +842,20 @@ struct KnnLayout {
     size_t bytes;
 };
 
-static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth) {
+static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth, int64_t nq_order = 0) {
     KnnLayout L;
     Carve c(ws);
     L.tiles = n > 0 ? (n + kTreeTile - 1) / kTreeTile : 1;
     L.nodes = tree_nodes_max(n, depth);
     L.ctl = c.take<Control>(1);
+    if (nq_order > 0) {
+        SortCfg cfg;
+        cfg.radix_bits = 8;
+        cfg.items = 16;
+        sort_carve(c, L.sort, nq_order, kOrderBits, cfg);
+        L.oa = c.take<uint64_t>((size_t)nq_order);
+        L.ob = c.take<uint64_t>((size_t)nq_order);
+    }
     L.lvl = c.take<int64_t>(kMaxDepth + 2);
     L.cnt = c.take<uint32_t>((size_t)L.tiles * depth);
     L.first = c.take<uint32_t>((size_t)L.nodes);
@@ -845,11 +893,11 @@ static void knn_launch(const cga_grid *g, const KnnLayout &L, const float *q, in
     const unsigned blocks = (unsigned)((nq + kTeamsPerBlock - 1) / kTeamsPerBlock);
     if (g->depth <= kPackedDepth)
         k_knn_tree<KT, PackedList<KT>><<<blocks, kKnnBlock, lds, s>>>(
-            L.node, L.dense, L.lvl, L.nodes, q, nq, g->origin[0], g->origin[1], g->origin[2],
+            L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
             g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err);
     else
         k_knn_tree<KT, WideList<KT>><<<blocks, kKnnBlock, lds, s>>>(
-            L.node, L.dense, L.lvl, L.nodes, q, nq, g->origin[0], g->origin[1], g->origin[2],
+            L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
             g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err);
 }
 
@@ -876,7 +924,7 @@ extern "C" {
 
 size_t cga_knn_workspace_bytes(const cga_grid *g, int64_t n, int64_t nq) {
     if (!grid_valid(g) || n < 0 || nq < 0) return 0;
-    return knn_layout(nullptr, n, g->depth).bytes;
+    return knn_layout(nullptr, n, g->depth, knn_order(nq) ? nq : 0).bytes;
 }
 
 int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n, const float *d_q,
@@ -887,11 +935,29 @@ int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n
     if (nq > 0 && (!d_q || !d_idx || !d_d2)) return CGA_EINVAL;
     if (n > 0 && !d_keys) return CGA_EINVAL;
     if (g->key_mode != CGA_KEY_MORTON) return CGA_EUNSUPPORTED;
-    KnnLayout L = knn_layout(d_ws, n, g->depth);
+    if (nq >= ((int64_t)1 << (64 - kOrderBits))) return CGA_EUNSUPPORTED;
+    const bool ordered = knn_order(nq);
+    KnnLayout L = knn_layout(d_ws, n, g->depth, ordered ? nq : 0);
     if (ws_bytes < L.bytes) return CGA_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    CGA_TRY(launch_begin(L.ctl, nullptr, 0, nullptr, 0, nullptr, s));
+    CGA_TRY(launch_begin(L.ctl, ordered ? L.sort.hist : nullptr, ordered ? sort_zero_bytes(L.sort) : 0,
+                         nullptr, 0, nullptr, s));
     if (nq > 0) {
+        if (ordered) {
+            int64_t blocks = (nq + 256 * 8 - 1) / (256 * 8);
+            blocks = blocks > 1024 ? 1024 : blocks;
+            {
+                CGA_PROF("knn_order", s);
+                k_knn_order<<<(unsigned)blocks, 256, 0, s>>>(d_q, nq, g->origin[0], g->origin[1],
+                                                              g->origin[2], g->scale, g->depth, L.oa,
+                                                              L.sort.hist);
+            }
+            // three passes: oa -> ob -> oa -> ob
+            sort_launch<uint64_t>(L.sort, L.oa, L.ob, L.oa, L.ob, nq, nullptr, true,
+                                  L.ctl->tile_ctr, s);
+        } else {
+            L.ob = nullptr;
+        }
         if (wide_keys(g->depth))
             tree_build<uint64_t>(L, (const uint64_t *)d_keys, n, d_n, g->depth, s);
         else

@@ -291,6 +291,47 @@ def test_knn_edges(gpu):
     _check_knn(gpu, k21, rng.uniform(0, 1, (500, 3)).astype(np.float32), g21, 4)
 
 
+@pytest.mark.parametrize("k", [1, 8, 16])
+def test_knn_query_order(gpu, w_c2s, monkeypatch, k):
+    """The Morton ordering of the queries (on by default from 2^18 queries,
+    forced here at small sizes) leaves every row where it belongs."""
+    monkeypatch.setenv("CGA_KNN_ORDER", "1")
+    g = w_c2s["grid"]
+    ka, _ = gpu.cga_build(dev(w_c2s["a"]), g)
+    say("knn ordered c2s", k)
+    _check_knn(gpu, ka, w_c2s["q"], g, k)
+    rng = np.random.default_rng(23)
+    g5 = Grid((0.0, 0.0, 0.0), 1.0, 5, M)  # ties; a ragged query count
+    pts = rng.integers(0, 32, (300, 3)).astype(np.float32)
+    k5, _ = gpu.cga_build(dev(pts), g5)
+    q = rng.integers(-3, 35, (4097, 3)).astype(np.float32)
+    _check_knn(gpu, k5, q, g5, k, tier="brute")
+    _check_knn(gpu, k5, q[:1], g5, k, tier="brute")
+    g21 = Grid((0.0, 0.0, 0.0), float(2 ** 21), 21, M)  # key bits beyond the ordering's 24
+    k21, _ = gpu.cga_build(dev(rng.uniform(0, 1, (20_000, 3)).astype(np.float32)), g21)
+    _check_knn(gpu, k21, rng.uniform(0, 1, (3000, 3)).astype(np.float32), g21, k)
+    bad = q[:100].copy()
+    bad[57, 2] = np.nan
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_knn(k5, dev(bad), g5, k)
+    assert e.value.status == gpu.ENONFINITE
+
+
+def test_knn_query_order_auto(gpu, w_c2s):
+    """At 2^18 queries the ordering switches on by itself; the rows equal
+    those of the unordered search on the same queries."""
+    g = w_c2s["grid"]
+    ka, _ = gpu.cga_build(dev(w_c2s["a"]), g)
+    rng = np.random.default_rng(29)
+    q = w_c2s["q"][rng.integers(0, len(w_c2s["q"]), 1 << 18)]
+    q = q + rng.uniform(-0.5, 0.5, q.shape).astype(np.float32)
+    idx, d2 = gpu.cga_knn(ka, dev(q), g, 4)
+    rows = np.sort(rng.choice(len(q), 3000, replace=False))
+    widx, wd2 = oracle.knn_kdtree(u64(ka), q[rows], g, 4)
+    np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint64)[rows], wd2)
+    np.testing.assert_array_equal(idx.cpu().numpy()[rows], widx)
+
+
 # --------------------------------------------------------------- occupancy
 def _check_occupancy(gpu, keys_gpu, g):
     codes, counts = gpu.cga_occupancy(keys_gpu, g)
