@@ -15,15 +15,17 @@
 // A dense table maps every level-DT cell (DT = depth - 7, 2^21 cells) to its
 // node, so a search enters the tree near the bottom instead of at the root.
 //
-// Queries: a team of 8 lanes answers one query.  Round 0 splits the query's
-// level-LA cell among the lanes (one child each), every lane walking its
-// subtree depth-first, nearest child first, pruning cells whose nearest point
-// is strictly farther than the team's current k-th distance (kept in LDS, so
-// ties survive).  The lanes' candidate lists, ordered by (squared distance,
+// Queries: a team of 8 lanes answers one query.  Round 0 searches the
+// query's level-LA cell: lane t walks child t (in visiting order) of each of
+// the cell's eight children, depth-first, nearest child first, pruning cells
+// whose nearest point is strictly farther than the team's current k-th
+// distance (kept in LDS, so ties survive); dealing out grandchildren rather
+// than children spreads the work of the query's own, busiest part of the cell
+// over the team.  The lanes' candidate lists, ordered by (squared distance,
 // key index), are then merged by a butterfly of bitonic merges.  If the
 // k-th distance ball is not inside the searched cell, the next round searches
 // the up to 8 cells of the smallest level that cover the ball's bounding cube
-// (one per lane), and repeats with the grown ball until a round that started
+// (their children dealt out the same way), and repeats with the grown ball until a round that started
 // from a known bound covers it.
 #include <cstdlib>
 
@@ -492,6 +494,7 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
     using Dist = typename LIST::Dist;
     extern __shared__ uint64_t s_word[];  // open node word per level, one column per thread
     __shared__ unsigned long long s_bound[kTeamsPerBlock];
+    __shared__ uint64_t s_sw[kKnnBlock], s_sc[kKnnBlock];  // start cells of the round: word, corner
     __shared__ int64_t s_base[kMaxDepth + 1];
     const int tid = threadIdx.x, team = tid / kTeam, tl = tid % kTeam;
     if (tid == 0) {
@@ -614,95 +617,131 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
             }
         }
         const int64_t cn = ok && !skipped(c[0], c[1], c[2], ls) ? find_node(c[0], c[1], c[2], ls) : -1;
-        // depth-first walk of the start cell, nearest child first
-        if (cn >= 0) {
-            uint32_t x0 = c[0], y0 = c[1], z0 = c[2];
-            const int l0 = ls;
-            auto bound_now = [&]() __attribute__((always_inline)) -> uint64_t {
-                const uint64_t b = s_bound[team];
-                return kth < b ? kth : b;
-            };
-            if (l0 == 0) {
-                const Dist d = box_dist(x0, y0, z0, 0);
+        auto bound_now = [&]() __attribute__((always_inline)) -> uint64_t {
+            const uint64_t b = s_bound[team];
+            return kth < b ? kth : b;
+        };
+        // The start cells are shared out a child at a time: lane tl walks
+        // child near_order(tl) ^ (query octant) of every start cell in turn,
+        // so that the heaviest cell's work is spread over the whole team.
+        // Start cells at level 0 are voxels: each is offered by its lane.
+        const int l0 = ls - 1;  // level of the walked subtrees
+        uint32_t avail = 0;     // start cells that have this lane's child
+        uint32_t qs = 0;
+        if (ls == 0) {
+            if (cn >= 0) {
+                const Dist d = box_dist(c[0], c[1], c[2], 0);
                 if (d <= bound_now()) offer(d, (int32_t)cn);
-            } else if (box_dist(x0, y0, z0, l0) <= bound_now()) {
-                int l = l0;
-                uint64_t w = node[s_base[l] + cn];
-                s_word[l * kKnnBlock + tid] = w;
-                // Per open node: the query's octant one level down, the squared
-                // gap to the low and the high child half on each axis (a
-                // child's box distance is then three selects and two adds),
-                // whether its children are cells of the skipped level, and the
-                // bound, refreshed from the team's at every node.
-                uint32_t qol = 0;
-                Dist gxl = 0, gxh = 0, gyl = 0, gyh = 0, gzl = 0, gzh = 0;
-                bool touch = false;
-                uint64_t bnd = 0;
-                auto enter = [&]() __attribute__((always_inline)) {
-                    const int cl = l - 1;
-                    qol = qo(cl);
-                    const uint32_t h = 1u << cl, e = h - 1u;
-                    const Dist ax = axis_gap(qv.x, x0, x0 + e), bx = axis_gap(qv.x, x0 + h, x0 + h + e);
-                    const Dist ay = axis_gap(qv.y, y0, y0 + e), by = axis_gap(qv.y, y0 + h, y0 + h + e);
-                    const Dist az = axis_gap(qv.z, z0, z0 + e), bz = axis_gap(qv.z, z0 + h, z0 + h + e);
-                    gxl = ax * ax;
-                    gxh = bx * bx;
-                    gyl = ay * ay;
-                    gyh = by * by;
-                    gzl = az * az;
-                    gzh = bz * bz;
-                    touch = skip && cl == sk_l;
-                    bnd = bound_now();
-                };
-                enter();
-                uint32_t pm = slot_mask((uint32_t)w & 0xFFu, qol);
-                // One iteration: either climb back to the parent (its slots
-                // up to the one just finished are done), or take the next
-                // child -- prune it, offer it (a voxel), or descend into it.
-                // Climbing and descending share one node-entry tail, so a
-                // wave whose lanes take different paths runs it once.
-                for (;;) {
-                    const bool up = pm == 0;
-                    if (up && l == l0) break;
-                    bool moved = up;
-                    uint32_t done_oc = 0;
-                    if (up) {
-                        done_oc = (((x0 >> l) & 1u) << 2) | (((y0 >> l) & 1u) << 1) | ((z0 >> l) & 1u);
-                        ++l;
-                        const uint32_t clr = ~((1u << l) - 1u);
-                        x0 &= clr;
-                        y0 &= clr;
-                        z0 &= clr;
-                        w = s_word[l * kKnnBlock + tid];
-                    } else {
-                        const uint32_t sl = __builtin_ctz(pm);
-                        pm &= pm - 1;
-                        const uint32_t oc = near_order(sl) ^ qol;
-                        const Dist bd = ((oc & 4u) ? gxh : gxl) + ((oc & 2u) ? gyh : gyl) + ((oc & 1u) ? gzh : gzl);
-                        const int cl = l - 1;
-                        const uint32_t cx = x0 | (((oc >> 2) & 1u) << cl), cy = y0 | (((oc >> 1) & 1u) << cl),
-                                       cz = z0 | ((oc & 1u) << cl);
-                        if (bd <= bnd && !(touch && skipped(cx, cy, cz, cl))) {
-                            const int32_t ci = (int32_t)(w >> 8) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
-                            if (cl == 0) {
-                                offer(bd, ci);
-                                bnd = kth < bnd ? kth : bnd;
-                            } else {
-                                w = node[s_base[cl] + ci];
-                                s_word[cl * kKnnBlock + tid] = w;
-                                l = cl;
-                                x0 = cx;
-                                y0 = cy;
-                                z0 = cz;
-                                moved = true;
-                            }
+            }
+        } else {
+            s_sw[tid] = cn >= 0 ? node[s_base[ls] + cn] : 0ull;
+            s_sc[tid] = (uint64_t)c[0] | ((uint64_t)c[1] << 21) | ((uint64_t)c[2] << 42);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            qs = near_order((uint32_t)tl) ^ qo(l0);
+#pragma unroll
+            for (int m = 0; m < kTeam; ++m) avail |= (uint32_t)((s_sw[team * kTeam + m] >> qs) & 1u) << m;
+        }
+        if (avail) {
+            // depth-first walk of each subtree, nearest child first
+            int l = l0;
+            uint32_t x0 = 0, y0 = 0, z0 = 0;
+            uint64_t w = 0;
+            // Per open node: the query's octant one level down, the squared
+            // gap to the low and the high child half on each axis (a child's
+            // box distance is then three selects and two adds), whether its
+            // children are cells of the skipped level, and the bound,
+            // refreshed from the team's at every node.
+            uint32_t qol = 0;
+            Dist gxl = 0, gxh = 0, gyl = 0, gyh = 0, gzl = 0, gzh = 0;
+            bool touch = false;
+            uint64_t bnd = 0;
+            auto enter = [&]() __attribute__((always_inline)) {
+                const int cl = l - 1;
+                qol = qo(cl);
+                const uint32_t h = 1u << cl, e = h - 1u;
+                const Dist ax = axis_gap(qv.x, x0, x0 + e), bx = axis_gap(qv.x, x0 + h, x0 + h + e);
+                const Dist ay = axis_gap(qv.y, y0, y0 + e), by = axis_gap(qv.y, y0 + h, y0 + h + e);
+                const Dist az = axis_gap(qv.z, z0, z0 + e), bz = axis_gap(qv.z, z0 + h, z0 + h + e);
+                gxl = ax * ax;
+                gxh = bx * bx;
+                gyl = ay * ay;
+                gyh = by * by;
+                gzl = az * az;
+                gzh = bz * bz;
+                touch = skip && cl == sk_l;
+                bnd = bound_now();
+            };
+            uint32_t pm = 0;
+            // One iteration: start this lane's next subtree, climb back to
+            // the parent (its slots up to the one just finished are done), or
+            // take the next child -- prune it, offer it (a voxel), or descend
+            // into it.  Starting, climbing and descending share one node-entry
+            // tail, so a wave whose lanes take different paths runs it once.
+            for (;;) {
+                const bool up = pm == 0;
+                bool moved = false, climbed = false;
+                uint32_t done_oc = 0;
+                if (up && l == l0) {
+                    if (!avail) break;
+                    const int m = __builtin_ctz(avail);
+                    avail &= avail - 1;
+                    const uint64_t sw = s_sw[team * kTeam + m], sc = s_sc[team * kTeam + m];
+                    const uint32_t cx = ((uint32_t)sc & 0x1FFFFFu) | (((qs >> 2) & 1u) << l0);
+                    const uint32_t cy = ((uint32_t)(sc >> 21) & 0x1FFFFFu) | (((qs >> 1) & 1u) << l0);
+                    const uint32_t cz = ((uint32_t)(sc >> 42) & 0x1FFFFFu) | ((qs & 1u) << l0);
+                    const int32_t ci = (int32_t)(sw >> 8) + __popc((uint32_t)sw & 0xFFu & ((1u << qs) - 1u));
+                    const Dist bd = box_dist(cx, cy, cz, l0);
+                    if (bd <= bound_now() && !skipped(cx, cy, cz, l0)) {
+                        if (l0 == 0) {
+                            offer(bd, ci);
+                        } else {
+                            w = node[s_base[l0] + ci];
+                            s_word[l0 * kKnnBlock + tid] = w;
+                            x0 = cx;
+                            y0 = cy;
+                            z0 = cz;
+                            moved = true;
                         }
                     }
-                    if (moved) {
-                        enter();
-                        const uint32_t done_slots = up ? (2u << near_order(done_oc ^ qol)) - 1u : 0u;
-                        pm = slot_mask((uint32_t)w & 0xFFu, qol) & ~done_slots;
+                } else if (up) {
+                    done_oc = (((x0 >> l) & 1u) << 2) | (((y0 >> l) & 1u) << 1) | ((z0 >> l) & 1u);
+                    ++l;
+                    const uint32_t clr = ~((1u << l) - 1u);
+                    x0 &= clr;
+                    y0 &= clr;
+                    z0 &= clr;
+                    w = s_word[l * kKnnBlock + tid];
+                    moved = climbed = true;
+                } else {
+                    const uint32_t sl = __builtin_ctz(pm);
+                    pm &= pm - 1;
+                    const uint32_t oc = near_order(sl) ^ qol;
+                    const Dist bd = ((oc & 4u) ? gxh : gxl) + ((oc & 2u) ? gyh : gyl) + ((oc & 1u) ? gzh : gzl);
+                    const int cl = l - 1;
+                    const uint32_t cx = x0 | (((oc >> 2) & 1u) << cl), cy = y0 | (((oc >> 1) & 1u) << cl),
+                                   cz = z0 | ((oc & 1u) << cl);
+                    if (bd <= bnd && !(touch && skipped(cx, cy, cz, cl))) {
+                        const int32_t ci = (int32_t)(w >> 8) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
+                        if (cl == 0) {
+                            offer(bd, ci);
+                            bnd = kth < bnd ? kth : bnd;
+                        } else {
+                            w = node[s_base[cl] + ci];
+                            s_word[cl * kKnnBlock + tid] = w;
+                            l = cl;
+                            x0 = cx;
+                            y0 = cy;
+                            z0 = cz;
+                            moved = true;
+                        }
                     }
+                }
+                if (moved) {
+                    enter();
+                    const uint32_t done_slots = climbed ? (2u << near_order(done_oc ^ qol)) - 1u : 0u;
+                    pm = slot_mask((uint32_t)w & 0xFFu, qol) & ~done_slots;
                 }
             }
         }
