@@ -58,6 +58,7 @@ def _load():
         lib.or_knn_kdtree.restype = i32
         lib.or_nn_cga.argtypes = [P, i64, P, P, P, P, u32, i32, P, i64, P, P]
         lib.or_lower_bound.argtypes = [P, i64, P, i64, P, P]
+        lib.or_lookup_cga.argtypes = [P, i64, P, P, P, P, P, i64, P]
         lib.or_mlp_loss_grad.argtypes = [P, P, P, i64, P, P]
         lib.or_occupancy.argtypes = [P, i64, u32, P, P]
         lib.or_voxel_values.argtypes = [P, i64, P, P, f32, u32, i32, P, P]
@@ -206,6 +207,21 @@ def nn_cga(arr: dict, qvox, depth: int, mode: int):
     _load().or_nn_cga(_p(xi), len(xi), _p(xp), _p(yi), _p(yp), _p(zi), depth, mode, _p(qvox),
                       len(qvox), _p(pos), _p(d2))
     return pos, d2
+
+
+def lookup_cga(arr: dict, qvox):
+    """Point lookup on the five arrays (Section V-A, three-level search):
+    position in Z_index order, -1 when absent."""
+    qvox = np.ascontiguousarray(qvox, np.uint32).reshape(-1, 3)
+    pos = np.empty(len(qvox), np.int64)
+    xi = np.ascontiguousarray(arr["x_index"], np.uint32)
+    xp = np.ascontiguousarray(arr["x_pointer"], np.int64)
+    yi = np.ascontiguousarray(arr["y_index"], np.uint32)
+    yp = np.ascontiguousarray(arr["y_pointer"], np.int64)
+    zi = np.ascontiguousarray(arr["z_index"], np.uint32)
+    _load().or_lookup_cga(_p(xi), len(xi), _p(xp), _p(yi), _p(yp), _p(zi), _p(qvox), len(qvox),
+                          _p(pos))
+    return pos
 
 
 def lower_bound(keys, q):

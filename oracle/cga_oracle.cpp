@@ -450,6 +450,33 @@ void or_nn_cga(const uint32_t *x_index, int64_t nx, const int64_t *x_ptr, const 
     }
 }
 
+/* Point lookup on the five coordinate arrays, Section V-A: find the query's x
+ * in X_index; its X_pointer entries bound that x's run of Y_index; find the
+ * query's y in that run; its Y_pointer entries bound the (x, y) run of
+ * Z_index; find the query's z there.  Reading: X_pointer is indexed by the
+ * position of the x in X_index, not by the raw coordinate (the G-Arrays form
+ * the text's formula keeps), and each "find" is a plain search of an
+ * ascending run.  Writes the voxel's position in Z_index order (= the index
+ * of its LINEAR key), or -1 when it is absent. */
+void or_lookup_cga(const uint32_t *x_index, int64_t nx, const int64_t *x_ptr,
+                   const uint32_t *y_index, const int64_t *y_ptr, const uint32_t *z_index,
+                   const uint32_t *qvox, int64_t nq, int64_t *pos_out) {
+    auto find = [](const uint32_t *arr, int64_t lo, int64_t hi, uint32_t v) -> int64_t {
+        const uint32_t *p = std::lower_bound(arr + lo, arr + hi, v);
+        return (p != arr + hi && *p == v) ? p - arr : -1;
+    };
+    for (int64_t j = 0; j < nq; ++j) {
+        const uint32_t qx = qvox[3 * j], qy = qvox[3 * j + 1], qz = qvox[3 * j + 2];
+        int64_t pos = -1;
+        const int64_t a = find(x_index, 0, nx, qx);
+        if (a >= 0) {
+            const int64_t b = find(y_index, x_ptr[a], x_ptr[a + 1], qy);
+            if (b >= 0) pos = find(z_index, y_ptr[b], y_ptr[b + 1], qz);
+        }
+        pos_out[j] = pos;
+    }
+}
+
 /* Point location / range start: rank = lower_bound(keys, q), found = key
  * present.  The exact contract every learned-index lookup must reproduce. */
 void or_lower_bound(const uint64_t *keys, int64_t n, const uint64_t *q, int64_t nq, int64_t *rank,

@@ -25,8 +25,8 @@
 // key index), are then merged by a butterfly of bitonic merges.  If the
 // k-th distance ball is not inside the searched cell, the next round searches
 // the up to 8 cells of the smallest level that cover the ball's bounding cube
-// (their children dealt out the same way), and repeats with the grown ball until a round that started
-// from a known bound covers it.
+// (their children dealt out the same way), and repeats with the grown ball
+// until a round that started from a known bound covers it.
 #include <cstdlib>
 
 #include "cga_common.h"

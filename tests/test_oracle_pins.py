@@ -354,10 +354,55 @@ class TestKnn:
         lin_sorted = np.sort(oracle.encode(oracle.decode(keys, d, mode), d, L))
         assert (np.searchsorted(lin_sorted, lin) == pos).all()
 
+    def test_paper_nn_hand_example(self):
+        """Voxels (0,0,0), (2,0,0), (2,5,1): the nearest-x walk from (3,0,4)
+        lands on (2,0,0) (epsilon^2 = 17), and the box search then finds
+        nothing closer; from (2,4,1) the walk meets (2,5,1) at distance 1."""
+        g = int_grid(3, L)
+        keys, _ = oracle.build(np.array([[0, 0, 0], [2, 0, 0], [2, 5, 1]], np.float32), g)
+        arr = oracle.arrays(keys, 3, L)
+        pos, dd = oracle.nn_cga(arr, np.array([[3, 0, 4], [2, 4, 1], [0, 0, 0]], np.uint32), 3, L)
+        assert pos.tolist() == [1, 2, 0] and dd.tolist() == [17, 1, 0]
+
     def test_nonfinite_query(self):
         keys, _ = oracle.build(np.zeros((1, 3), np.float32), int_grid(4, M))
         with pytest.raises(oracle.NonFinite):
             oracle.knn_brute(keys, np.array([[np.nan, 0, 0]], np.float32), int_grid(4, M), 1)
+
+
+class TestPaperLookup:
+    """Three-level lookup on the five arrays (Section V-A) against membership
+    and rank in the sorted key array (a definition that uses no array but the
+    keys)."""
+
+    @pytest.mark.parametrize("d", [3, 7])
+    def test_matches_key_rank(self, d):
+        rng = np.random.default_rng(60 + d)
+        pts = rng.integers(0, 2 ** d, (3000, 3)).astype(np.float32)
+        g = int_grid(d, L)
+        keys, _ = oracle.build(pts, g)
+        arr = oracle.arrays(keys, d, L)
+        qv = np.concatenate([oracle.decode(keys[rng.integers(0, len(keys), 500)], d, L),
+                             rng.integers(0, 2 ** d, (500, 3))]).astype(np.uint32)
+        pos = oracle.lookup_cga(arr, qv)
+        rank, found = oracle.lower_bound(keys, oracle.encode(qv, d, L))
+        assert (pos == np.where(found.astype(bool), rank, -1)).all()
+        assert (pos[:500] >= 0).all()
+
+    def test_hand_example(self):
+        # voxels (1,2,3), (1,2,5), (1,4,0), (6,0,0): X_index [1, 6], X_pointer
+        # [0, 2, 3], Y_index [2, 4, 0], Y_pointer [0, 2, 3, 4], Z_index [3, 5, 0, 0]
+        g = int_grid(3, L)
+        keys, _ = oracle.build(np.array([[1, 2, 3], [1, 2, 5], [1, 4, 0], [6, 0, 0]],
+                                        np.float32), g)
+        arr = oracle.arrays(keys, 3, L)
+        assert arr["x_index"].tolist() == [1, 6] and arr["x_pointer"].tolist() == [0, 2, 3]
+        assert arr["y_pointer"].tolist() == [0, 2, 3, 4]
+        q = np.array([[1, 2, 5], [1, 4, 0], [6, 0, 0], [1, 2, 4], [1, 3, 0], [2, 0, 0],
+                      [6, 0, 1], [0, 0, 0]], np.uint32)
+        assert oracle.lookup_cga(arr, q).tolist() == [1, 2, 3, -1, -1, -1, -1, -1]
+        empty = oracle.arrays(np.zeros(0, np.uint64), 3, L)
+        assert oracle.lookup_cga(empty, q[:2]).tolist() == [-1, -1]
 
 
 # ----------------------------------------------------------------- lookup
