@@ -130,6 +130,42 @@ int cga_to_arrays(const cga_grid *grid, const void *d_keys, int64_t n, const int
                   uint32_t *d_z_index, int64_t *d_n_x, int64_t *d_n_xy, int64_t *n_x_host,
                   int64_t *n_xy_host, void *d_ws, size_t ws_bytes, cga_stream stream);
 
+/* ------------------------------------------------- paper's array operations
+ * The paper's own algorithms on the five arrays of a LINEAR grid, as
+ * cga_to_arrays writes them: n_x entries of X_index (X_pointer has n_x + 1),
+ * n_xy of Y_index (Y_pointer n_xy + 1), n of Z_index.  d_n_x / d_n_xy are
+ * optional device counts (at most the host bounds), so that the arrays can
+ * stay on the device.  Pointer entries outside those lengths raise
+ * CGA_EMISMATCH (device) and are clamped, so every access stays in bounds.
+ * CGA_EMISMATCH (host) for a MORTON grid.  Workspace:
+ * cga_arrays_ops_workspace_bytes() bytes (the call's error block). */
+size_t cga_arrays_ops_workspace_bytes(void);
+
+/* Point lookup, Section V-A: for each of nq query voxels (uint32 x, y, z,
+ * AoS) the three-level search -- x in X_index, y in that x's run of
+ * Y_index (bounded by X_pointer, indexed by the x's position), z in that
+ * (x, y)'s run of Z_index (bounded by Y_pointer).  d_pos[j] = the voxel's
+ * position in Z_index, which is the index of its LINEAR key, or -1 when it
+ * is absent (also for coordinates outside the grid). */
+int cga_arrays_lookup(const cga_grid *grid, const uint32_t *d_x_index, int64_t n_x,
+                      const int64_t *d_n_x, const int64_t *d_x_ptr, const uint32_t *d_y_index,
+                      int64_t n_xy, const int64_t *d_n_xy, const int64_t *d_y_ptr,
+                      const uint32_t *d_z_index, int64_t n, const uint32_t *d_qvox, int64_t nq,
+                      int64_t *d_pos, void *d_ws, size_t ws_bytes, cga_stream stream);
+
+/* Nearest neighbour, Section V-C: each of nq float32 query points (AoS) is
+ * quantized by the grid rule; the nearest x, then y, then z give a first
+ * point at distance epsilon, and the closest point within epsilon of the
+ * query on every axis is the answer: the same voxel as cga_knn with k = 1
+ * (ties to the smaller key).  d_idx = its position in Z_index (-1 for an
+ * empty CGA), d_d2 = its squared voxel distance (UINT64_MAX when none).
+ * Errors: CGA_ENONFINITE for a non-finite query (device). */
+int cga_arrays_nn(const cga_grid *grid, const uint32_t *d_x_index, int64_t n_x,
+                  const int64_t *d_n_x, const int64_t *d_x_ptr, const uint32_t *d_y_index,
+                  int64_t n_xy, const int64_t *d_n_xy, const int64_t *d_y_ptr,
+                  const uint32_t *d_z_index, int64_t n, const float *d_q, int64_t nq,
+                  int64_t *d_idx, uint64_t *d_d2, void *d_ws, size_t ws_bytes, cga_stream stream);
+
 /* ------------------------------------------------------------------ merge
  * Merge, Eq. (1): the union of two CGAs of the same grid (sorted unique key
  * arrays a, b) as one sorted unique key array.  d_src (nullable) receives a

@@ -76,6 +76,11 @@ _sig("cga_sort_keys", ctypes.c_int, _GP, _P, _I64, _P, ctypes.c_uint32, _P, _P, 
 _sig("cga_to_arrays_workspace_bytes", _SZ, _GP, _I64)
 _sig("cga_to_arrays", ctypes.c_int, _GP, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _I64P, _I64P,
      _P, _SZ, _P)
+_sig("cga_arrays_ops_workspace_bytes", _SZ)
+_sig("cga_arrays_lookup", ctypes.c_int, _GP, _P, _I64, _P, _P, _P, _I64, _P, _P, _P, _I64, _P,
+     _I64, _P, _P, _SZ, _P)
+_sig("cga_arrays_nn", ctypes.c_int, _GP, _P, _I64, _P, _P, _P, _I64, _P, _P, _P, _I64, _P, _I64,
+     _P, _P, _P, _SZ, _P)
 _sig("cga_merge_workspace_bytes", _SZ, _GP, _I64, _I64)
 _sig("cga_merge", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _P, _P, _I64, _P, _I64P, _P, _SZ,
      _P)
@@ -271,6 +276,45 @@ def cga_to_arrays(keys: torch.Tensor, grid, ws=None, stream=None) -> dict:
                              _ptr(wsb), wsb.numel(), _stream(stream)), "cga_to_arrays")
     return dict(x_index=xi[:nx.value], x_pointer=xp[:nx.value + 1], y_index=yi[:nxy.value],
                 y_pointer=yp[:nxy.value + 1], z_index=zi[:n])
+
+
+def _arrays_args(arr: dict):
+    xi, xp, yi, yp, zi = (arr["x_index"], arr["x_pointer"], arr["y_index"], arr["y_pointer"],
+                          arr["z_index"])
+    return (_ptr(xi), xi.shape[0], None, _ptr(xp), _ptr(yi), yi.shape[0], None, _ptr(yp),
+            _ptr(zi), zi.shape[0])
+
+
+def cga_arrays_lookup(arr: dict, qvox: torch.Tensor, grid, *, out=None, sync: bool = True,
+                      ws=None, stream=None) -> torch.Tensor:
+    """Point lookup on the five arrays (Section V-A): int64 position in
+    Z_index order, -1 when absent.  qvox: (nq, 3) int32 voxel coordinates."""
+    g = grid_struct(grid)
+    nq = qvox.shape[0]
+    pos = out if out is not None else torch.empty(nq, dtype=torch.int64, device=qvox.device)
+    wsb = _ws("arrays_ops", lib.cga_arrays_ops_workspace_bytes(), ws)
+    _check(lib.cga_arrays_lookup(ctypes.byref(g), *_arrays_args(arr), _ptr(qvox), nq, _ptr(pos),
+                                 _ptr(wsb), wsb.numel(), _stream(stream)), "cga_arrays_lookup")
+    if sync:
+        _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_arrays_lookup")
+    return pos
+
+
+def cga_arrays_nn(arr: dict, queries: torch.Tensor, grid, *, idx_out=None, d2_out=None,
+                  sync: bool = True, ws=None, stream=None):
+    """The paper's nearest neighbour on the five arrays (Section V-C):
+    (int64 position in Z_index order, uint64 squared distance as int64)."""
+    g = grid_struct(grid)
+    nq = queries.shape[0]
+    dev = queries.device
+    idx = idx_out if idx_out is not None else torch.empty(nq, dtype=torch.int64, device=dev)
+    d2 = d2_out if d2_out is not None else torch.empty(nq, dtype=torch.int64, device=dev)
+    wsb = _ws("arrays_ops", lib.cga_arrays_ops_workspace_bytes(), ws)
+    _check(lib.cga_arrays_nn(ctypes.byref(g), *_arrays_args(arr), _ptr(queries), nq, _ptr(idx),
+                             _ptr(d2), _ptr(wsb), wsb.numel(), _stream(stream)), "cga_arrays_nn")
+    if sync:
+        _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_arrays_nn")
+    return idx, d2
 
 
 def cga_merge(a: torch.Tensor, b: torch.Tensor, grid, *, src: bool = False, cap=None, na=None,

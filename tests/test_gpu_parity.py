@@ -178,6 +178,90 @@ def test_to_arrays_table2(gpu):
         assert got.tolist() == v, name
 
 
+# ------------------------------------------- the paper's array operations
+def _lin_arrays(gpu, xyz, g):
+    k, _ = gpu.cga_build(dev(xyz), g)
+    return k, gpu.cga_to_arrays(k, g), oracle.arrays(u64(k), g.depth, L)
+
+
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s", "w_c3s"])
+def test_arrays_lookup(gpu, wl, request):
+    d = _wl(wl, request)
+    g = d["grid"].with_mode(L)
+    k, arr, oarr = _lin_arrays(gpu, d["a"], g)
+    keys = u64(k)
+    rng = np.random.default_rng(71)
+    top = 2 ** g.depth
+    qv = np.concatenate([oracle.decode(keys[rng.integers(0, len(keys), 20000)], g.depth, L),
+                         rng.integers(0, top, (20000, 3)),
+                         [[0, 0, 0], [top - 1] * 3, [top, 0, 0], [2 ** 32 - 1] * 3]]).astype(np.uint32)
+    say("arrays lookup", wl, len(keys), len(qv))
+    pos = gpu.cga_arrays_lookup(arr, dev(qv.view(np.int32)), g).cpu().numpy()
+    want = oracle.lookup_cga(oarr, qv)
+    np.testing.assert_array_equal(pos, want)
+    assert (pos[:20000] >= 0).all()
+    ok = qv.max(1) < top  # membership and rank in the key array say the same
+    rank, found = oracle.lower_bound(keys, oracle.encode(qv[ok], g.depth, L))
+    np.testing.assert_array_equal(pos[ok], np.where(found.astype(bool), rank, -1))
+
+
+@pytest.mark.parametrize("wl", ["w_c1", "w_c2s", "w_c3s"])
+def test_arrays_nn(gpu, wl, request):
+    d = _wl(wl, request)
+    g = d["grid"].with_mode(L)
+    k, arr, oarr = _lin_arrays(gpu, d["a"], g)
+    q = d["q"]
+    say("arrays nn", wl, len(k), len(q))
+    idx, d2 = gpu.cga_arrays_nn(arr, dev(q), g)
+    idx, d2 = idx.cpu().numpy(), d2.cpu().numpy().view(np.uint64)
+    widx, wd2 = oracle.knn_kdtree(u64(k), q, g, 1)  # same order: (distance, LINEAR key)
+    np.testing.assert_array_equal(d2, wd2[:, 0])
+    np.testing.assert_array_equal(idx, widx[:, 0])
+    rows = np.arange(0, len(q), max(1, len(q) // 300))  # the paper's own steps, on a sample
+    qv = oracle.quantize(q[rows], g).astype(np.uint32)
+    ppos, pd2 = oracle.nn_cga(oarr, qv, g.depth, L)
+    np.testing.assert_array_equal(idx[rows], ppos)
+    np.testing.assert_array_equal(d2[rows], pd2)
+
+
+def test_arrays_edges(gpu):
+    rng = np.random.default_rng(73)
+    g = Grid((0.0, 0.0, 0.0), 1.0, 5, L)  # tiny grid: many exact ties
+    pts = rng.integers(0, 32, (300, 3)).astype(np.float32)
+    k, arr, oarr = _lin_arrays(gpu, pts, g)
+    q = np.concatenate([pts[:50], rng.integers(-3, 35, (400, 3)).astype(np.float32)])
+    idx, d2 = gpu.cga_arrays_nn(arr, dev(q), g)
+    widx, wd2 = oracle.knn_brute(u64(k), q, g, 1)
+    np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint64), wd2[:, 0])
+    np.testing.assert_array_equal(idx.cpu().numpy(), widx[:, 0])
+    for m in (1, 2):  # one voxel; two voxels
+        km, am, _ = _lin_arrays(gpu, pts[:m], g)
+        idx, d2 = gpu.cga_arrays_nn(am, dev(q), g)
+        widx, wd2 = oracle.knn_brute(u64(km), q, g, 1)
+        np.testing.assert_array_equal(idx.cpu().numpy(), widx[:, 0])
+        np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint64), wd2[:, 0])
+    empty = gpu.cga_to_arrays(k[:0], g)
+    idx, d2 = gpu.cga_arrays_nn(empty, dev(q[:5]), g)
+    assert (idx.cpu().numpy() == -1).all() and (d2.cpu().numpy() == -1).all()
+    assert (gpu.cga_arrays_lookup(empty, dev(np.zeros((3, 3), np.int32)), g).cpu().numpy() == -1).all()
+    bad = q[:10].copy()
+    bad[4, 1] = np.inf
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_arrays_nn(arr, dev(bad), g)
+    assert e.value.status == gpu.ENONFINITE
+    with pytest.raises(gpu.CgaError) as e:  # MORTON grids have no such arrays
+        gpu.cga_arrays_nn(arr, dev(q[:3]), g.with_mode(M))
+    assert e.value.status == gpu.EMISMATCH
+    # a pointer past the end of Y_index: flagged, every access clamped in bounds
+    broken = dict(arr)
+    xp = arr["x_pointer"].clone()
+    xp[1:-1] = xp[-1] + 1000
+    broken["x_pointer"] = xp
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_arrays_nn(broken, dev(q), g)
+    assert e.value.status == gpu.EMISMATCH
+
+
 # ------------------------------------------------------------------- merge
 @pytest.mark.parametrize("wl", ["w_c1", "w_c2s", "w_c3s"])
 @pytest.mark.parametrize("mode", [M, L])
