@@ -365,6 +365,68 @@ def occupancy_codes(cga, pipe, reps=20):
     return {"keys": n, "codes": codes, "ms": round(ms, 4), "codes_per_s": codes / (ms * 1e-3)}
 
 
+def _time_ms(run, reps):
+    import torch
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def paper_array_ops(cga, pipe, d, reps=20):
+    """The paper's own lookup and NN on the five arrays of the step's union in
+    LINEAR order (not part of the step): the union rebuilt on a LINEAR grid,
+    cga_to_arrays, then the three-level lookup of 2M voxels (half present)
+    and the epsilon-box NN of the step's queries, next to the octree k-NN of
+    the same queries with k = 1."""
+    import numpy as np
+    import torch
+
+    import gen
+    dev = pipe.m.device
+    g = d["grid"].with_mode(gen.KEY_LINEAR)
+    ka, _ = cga.cga_build(pipe.a, g)
+    kb, _ = cga.cga_build(pipe.b, g)
+    m, _ = cga.cga_merge(ka, kb, g)
+    arr = cga.cga_to_arrays(m, g)
+    n = m.shape[0]
+    rng = np.random.default_rng(1008)
+    mk = m.cpu().numpy().view(np.uint64)[rng.integers(0, n, 1 << 20)]
+    dd = g.depth
+    mask = (1 << dd) - 1
+    present = np.stack([(mk >> np.uint64(2 * dd)) & np.uint64(mask), (mk >> np.uint64(dd)) & np.uint64(mask),
+                        mk & np.uint64(mask)], 1)
+    qv = np.concatenate([present, rng.integers(0, 1 << dd, (1 << 20, 3))]).astype(np.int32)
+    qv = torch.from_numpy(qv).to(dev)
+    pos = torch.empty(qv.shape[0], dtype=torch.int64, device=dev)
+    nq = pipe.q.shape[0]
+    idx = torch.empty(nq, dtype=torch.int64, device=dev)
+    d2 = torch.empty(nq, dtype=torch.int64, device=dev)
+    kidx = torch.empty((nq, 1), dtype=torch.int64, device=dev)
+    kd2 = torch.empty((nq, 1), dtype=torch.int64, device=dev)
+    ws = cga.Workspaces(dev)
+    ms_lookup = _time_ms(lambda: cga.cga_arrays_lookup(arr, qv, g, out=pos, sync=False, ws=ws), reps)
+    ms_nn = _time_ms(lambda: cga.cga_arrays_nn(arr, pipe.q, g, idx_out=idx, d2_out=d2, sync=False,
+                                                ws=ws), reps)
+    ms_knn1 = _time_ms(lambda: cga.cga_knn(pipe.m, pipe.q, pipe.g, 1, n=pipe.nu, idx_out=kidx,
+                                           d2_out=kd2, sync=False, ws=ws), reps)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(d2, kd2[:, 0]))
+    return {"voxels": n, "x_entries": int(arr["x_index"].shape[0]),
+            "xy_entries": int(arr["y_index"].shape[0]),
+            "lookup": {"queries": int(qv.shape[0]), "ms": round(ms_lookup, 4),
+                       "lookups_per_s": qv.shape[0] / (ms_lookup * 1e-3),
+                       "found": int((pos >= 0).sum().item())},
+            "nn": {"queries": nq, "ms": round(ms_nn, 4), "queries_per_s": nq / (ms_nn * 1e-3)},
+            "octree_knn_k1": {"ms": round(ms_knn1, 4), "queries_per_s": nq / (ms_knn1 * 1e-3),
+                              "same_distances": same}}
+
+
 def attribute_values(cga, pipe, d, reps=20):
     """Value arrays of the step's two sweeps from seeded per-point attributes,
     and the merged cloud's values (average policy); not part of the step."""
@@ -563,6 +625,7 @@ def main():
     }
     line["occupancy"] = occupancy_codes(cga, pipe)
     line["values"] = attribute_values(cga, pipe, d)
+    line["paper_array_ops"] = paper_array_ops(cga, pipe, d)
     if not args.no_c5:
         line["c5"] = c5_learned_vs_binary(cga, device, args.c5_reps)
     if not args.no_c4:
