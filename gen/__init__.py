@@ -260,6 +260,39 @@ def c3_bumpy(seed: int = 1003, n: int = 10_000_000, nq: int = 1_000_000,
     return dict(a=a, b=b, q=q, grid=grid, k=16)
 
 
+def c6_frames(seed: int = 1006, n: int = 1_000_000, depth: int = 10) -> dict:
+    """A reference and a predicted frame of a moving object, standing in for
+    the voxelized full-body sequences that point cloud compression is
+    evaluated on (about 10^6 points on a 1024^3 grid per frame): a bumpy
+    sphere of n points squeezed to a standing figure's proportions (0.35 :
+    1 : 0.2); the predicted frame moves the object by an offset of -3 .. 3
+    voxels per axis, each octant (about the centre) by a further -1 .. 1, and
+    draws 2 % of its points afresh.  Colours (RGB + 255, packed as the Value array
+    packs them) are a smooth field of each point's position before the motion
+    plus N(0, 2) noise per channel and frame.  LINEAR cubic grid of the
+    given depth over the object grown by 2 % (room for the motion)."""
+    rng = np.random.default_rng(seed)
+    shape = np.array([0.35, 1.0, 0.2], np.float32)  # a standing figure's proportions
+    ref = bumpy_sphere(seed, n) * shape
+    grid = cubic_grid([ref * np.float32(1.02)], depth, KEY_LINEAR)
+    voxel = 1.0 / grid.scale
+    octant = ((ref[:, 0] > 0).astype(np.int64) << 2) | ((ref[:, 1] > 0).astype(np.int64) << 1) | (
+        ref[:, 2] > 0).astype(np.int64)
+    offsets = rng.integers(-3, 4, (1, 3)) + rng.integers(-1, 2, (8, 3))
+    pred = (ref.astype(np.float64) + offsets[octant] * voxel).astype(np.float32)
+    fresh = rng.random(n) < 0.02
+    pred[fresh] = bumpy_sphere(seed + 1, int(fresh.sum())) * shape
+    base = np.stack([np.sin(3.0 * ref[:, 0]), np.sin(3.0 * ref[:, 1] + 1.0),
+                     np.sin(3.0 * ref[:, 2] + 2.0)], 1) * 100.0 + 128.0
+
+    def colours(noise):
+        c = np.clip(np.rint(base + noise), 0, 255).astype(np.uint32)
+        return c[:, 0] | (c[:, 1] << 8) | (c[:, 2] << 16) | np.uint32(255 << 24)
+
+    return dict(ref=ref, pred=pred, ref_values=colours(rng.normal(0, 2, (n, 3))),
+                pred_values=colours(rng.normal(0, 2, (n, 3))), offsets=offsets, grid=grid)
+
+
 def c4_frames(seed: int = 1004, nframes: int = 256, size_lo: float = 1e4,
               size_hi: float = 2e6, depth: int = 12) -> dict:
     """nframes LiDAR frames of the two-sweep scene, sensed from a random walk

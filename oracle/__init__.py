@@ -59,6 +59,8 @@ def _load():
         lib.or_nn_cga.argtypes = [P, i64, P, P, P, P, u32, i32, P, i64, P, P]
         lib.or_lower_bound.argtypes = [P, i64, P, i64, P, P]
         lib.or_lookup_cga.argtypes = [P, i64, P, P, P, P, P, i64, P]
+        lib.or_temporal_predict.argtypes = [P, P, i64, P, P, i64, u32, i32, i32, i32, P, P, P,
+                                            P, P, P, P, P]
         lib.or_mlp_loss_grad.argtypes = [P, P, P, i64, P, P]
         lib.or_occupancy.argtypes = [P, i64, u32, P, P]
         lib.or_voxel_values.argtypes = [P, i64, P, P, f32, u32, i32, P, P]
@@ -222,6 +224,30 @@ def lookup_cga(arr: dict, qvox):
     _load().or_lookup_cga(_p(xi), len(xi), _p(xp), _p(yi), _p(yp), _p(zi), _p(qvox), len(qvox),
                           _p(pos))
     return pos
+
+
+def temporal_predict(ref_keys, ref_vals, pred_keys, pred_vals, depth: int, mode: int,
+                     window: int = 2, max_iter: int = 20) -> dict:
+    """Temporal prediction of a frame from a reference frame (Section V-D):
+    8-centre k-means of both frames from the bounding-box corners, motion
+    vectors from corresponding centroids, SAD matching of every motion-
+    compensated predicted voxel in a +-window box of the reference, residual."""
+    rk, pk = _u64(ref_keys), _u64(pred_keys)
+    rv = np.ascontiguousarray(ref_vals, np.uint32)
+    pv = np.ascontiguousarray(pred_vals, np.uint32)
+    nr, npred = len(rk), len(pk)
+    out = dict(ref_assign=np.empty(max(nr, 1), np.uint8), pred_assign=np.empty(max(npred, 1), np.uint8),
+               centroids=np.empty((2, 8, 3), np.float64), mv=np.empty((8, 3), np.int32),
+               iters=np.empty(2, np.int32), match=np.empty(max(npred, 1), np.int64),
+               sad=np.empty(max(npred, 1), np.uint32), residual=np.empty((max(npred, 1), 4), np.int16))
+    _load().or_temporal_predict(_p(rk), _p(rv), nr, _p(pk), _p(pv), npred, depth, mode, window,
+                                max_iter, _p(out["ref_assign"]), _p(out["pred_assign"]),
+                                _p(out["centroids"]), _p(out["mv"]), _p(out["iters"]),
+                                _p(out["match"]), _p(out["sad"]), _p(out["residual"]))
+    for name, n in (("ref_assign", nr), ("pred_assign", npred), ("match", npred), ("sad", npred),
+                    ("residual", npred)):
+        out[name] = out[name][:n].copy()
+    return out
 
 
 def lower_bound(keys, q):

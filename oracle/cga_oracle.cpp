@@ -477,6 +477,131 @@ void or_lookup_cga(const uint32_t *x_index, int64_t nx, const int64_t *x_ptr,
     }
 }
 
+/* Temporal prediction of one frame from a reference frame (Section V-D),
+ * both given as CGAs (ascending unique keys of the grid's mode, one packed
+ * 4 x 8-bit value per voxel):
+ *   1. each frame's voxels are clustered by k-means with eight centres
+ *      started at the corners of the frame's bounding box;
+ *   2. cluster i of the predicted frame corresponds to cluster i of the
+ *      reference (the same starting corner); its motion vector is the
+ *      difference of the two centroids, rounded to whole voxels;
+ *   3. every predicted voxel, moved back by its cluster's motion vector, is
+ *      matched to the reference voxel of smallest SAD of the four channels
+ *      among those within `window` voxels on every axis;
+ *   4. the residual is the channel-wise difference predicted - matched.
+ * Readings (the text fixes none of these): corner i has x = max when bit 2
+ * of i is set (else min), y by bit 1, z by bit 0; distances to centres are
+ * squared Euclidean in double precision, summed x, y, z without fused
+ * multiply-add, ties to the lower cluster; a centre is the mean of its
+ * voxels (exact integer sums, one division) and keeps its place when empty;
+ * an iteration assigns every voxel, and the run stops at the first
+ * assignment that repeats the previous one or after max_iter assignments
+ * (so the final assignment is always nearest-centre for the final
+ * centres); rounding is half away from zero; SAD ties go to the smaller
+ * L1 coordinate distance, then to the smaller key; a voxel moved outside the
+ * grid, or with no reference voxel in its window, has match -1, SAD
+ * UINT32_MAX and its own channels as residual. */
+static int kmeans8(const std::vector<Voxel> &pts, int max_iter, uint8_t *assign, double cent[8][3]) {
+    const int64_t n = (int64_t)pts.size();
+    uint32_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            if (i == 0 || pts[i][a] < lo[a]) lo[a] = pts[i][a];
+            if (i == 0 || pts[i][a] > hi[a]) hi[a] = pts[i][a];
+        }
+    for (int c = 0; c < 8; ++c)
+        for (int a = 0; a < 3; ++a) cent[c][a] = (double)(((c >> (2 - a)) & 1) ? hi[a] : lo[a]);
+    int it = 0;
+    while (it < max_iter) {
+        bool changed = false;
+        for (int64_t i = 0; i < n; ++i) {
+            int best = 0;
+            double bd = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const double dx = (double)pts[i][0] - cent[c][0];
+                const double dy = (double)pts[i][1] - cent[c][1];
+                const double dz = (double)pts[i][2] - cent[c][2];
+                const double d = dx * dx + dy * dy + dz * dz;
+                if (c == 0 || d < bd) { bd = d; best = c; }
+            }
+            if (it == 0 || assign[i] != best) changed = true;
+            assign[i] = (uint8_t)best;
+        }
+        ++it;
+        if (!changed || it == max_iter) break;
+        int64_t sum[8][3] = {}, cnt[8] = {};
+        for (int64_t i = 0; i < n; ++i) {
+            ++cnt[assign[i]];
+            for (int a = 0; a < 3; ++a) sum[assign[i]][a] += pts[i][a];
+        }
+        for (int c = 0; c < 8; ++c)
+            if (cnt[c] > 0)
+                for (int a = 0; a < 3; ++a) cent[c][a] = (double)sum[c][a] / (double)cnt[c];
+    }
+    return it;
+}
+
+void or_temporal_predict(const uint64_t *ref_keys, const uint32_t *ref_vals, int64_t n_ref,
+                         const uint64_t *pred_keys, const uint32_t *pred_vals, int64_t n_pred,
+                         uint32_t depth, int mode, int window, int max_iter, uint8_t *ref_assign,
+                         uint8_t *pred_assign, double *centroids, int32_t *mv, int32_t *iters,
+                         int64_t *match, uint32_t *sad, int16_t *residual) {
+    std::vector<Voxel> rv(n_ref), pv(n_pred);
+    std::map<Voxel, int64_t> where;  // reference voxel -> index in its key array
+    for (int64_t i = 0; i < n_ref; ++i) {
+        rv[i] = decode(ref_keys[i], depth, mode);
+        where[rv[i]] = i;
+    }
+    for (int64_t i = 0; i < n_pred; ++i) pv[i] = decode(pred_keys[i], depth, mode);
+    double cr[8][3], cp[8][3];
+    iters[0] = kmeans8(rv, max_iter, ref_assign, cr);
+    iters[1] = kmeans8(pv, max_iter, pred_assign, cp);
+    for (int c = 0; c < 8; ++c)
+        for (int a = 0; a < 3; ++a) {
+            centroids[c * 3 + a] = cr[c][a];
+            centroids[24 + c * 3 + a] = cp[c][a];
+            mv[c * 3 + a] = (int32_t)std::llround(cp[c][a] - cr[c][a]);
+        }
+    const int64_t top = (int64_t)1 << depth;
+    auto chan = [](uint32_t v, int c) { return (int32_t)((v >> (8 * c)) & 0xFFu); };
+    for (int64_t i = 0; i < n_pred; ++i) {
+        int64_t r[3];
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) {
+            r[a] = (int64_t)pv[i][a] - mv[pred_assign[i] * 3 + a];
+            inside = inside && r[a] >= 0 && r[a] < top;
+        }
+        int64_t best = -1;
+        uint64_t bs = UINT64_MAX, bl = 0, bk = 0;
+        if (inside) {
+            for (int64_t dx = -window; dx <= window; ++dx)
+                for (int64_t dy = -window; dy <= window; ++dy)
+                    for (int64_t dz = -window; dz <= window; ++dz) {
+                        const int64_t c[3] = {r[0] + dx, r[1] + dy, r[2] + dz};
+                        if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] >= top || c[1] >= top || c[2] >= top)
+                            continue;
+                        const auto it = where.find(Voxel{(uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2]});
+                        if (it == where.end()) continue;
+                        uint64_t sd = 0;
+                        for (int ch = 0; ch < 4; ++ch)
+                            sd += (uint64_t)std::abs(chan(pred_vals[i], ch) - chan(ref_vals[it->second], ch));
+                        const uint64_t l1 = (uint64_t)(std::llabs(dx) + std::llabs(dy) + std::llabs(dz));
+                        const uint64_t key = ref_keys[it->second];
+                        if (best < 0 || sd < bs || (sd == bs && (l1 < bl || (l1 == bl && key < bk)))) {
+                            best = it->second;
+                            bs = sd;
+                            bl = l1;
+                            bk = key;
+                        }
+                    }
+        }
+        match[i] = best;
+        sad[i] = best < 0 ? UINT32_MAX : (uint32_t)bs;
+        for (int ch = 0; ch < 4; ++ch)
+            residual[4 * i + ch] = (int16_t)(chan(pred_vals[i], ch) - (best < 0 ? 0 : chan(ref_vals[best], ch)));
+    }
+}
+
 /* Point location / range start: rank = lower_bound(keys, q), found = key
  * present.  The exact contract every learned-index lookup must reproduce. */
 void or_lower_bound(const uint64_t *keys, int64_t n, const uint64_t *q, int64_t nq, int64_t *rank,

@@ -564,3 +564,136 @@ def test_merge_values_policies():
     assert np.array_equal(k2, kavg) and np.array_equal(v2, vavg)
     k3, v3 = oracle.merge_values(ka, va, ka[:0], va[:0], oracle.AVERAGE)
     assert np.array_equal(k3, ka) and np.array_equal(v3, va)
+
+
+# ------------------------------------------------------- temporal prediction
+def _chan(v):
+    v = np.asarray(v, np.uint32)
+    return np.stack([(v >> np.uint32(8 * c)) & np.uint32(0xFF) for c in range(4)], -1).astype(np.int64)
+
+
+class TestTemporal:
+    """Temporal prediction steps (Section V-D) against what fixes them: the
+    k-means fixed point (nearest-centre assignment, centres = means), the
+    bounding-box corner seeds, exact recovery of a known translation, and the
+    SAD-minimality of every match over its window."""
+
+    def _frame(self, rng, d, n):
+        g = int_grid(d, M)
+        keys, _ = oracle.build(rng.integers(0, 2 ** d, (n, 3)).astype(np.float32), g)
+        return keys
+
+    def test_kmeans_fixed_point_and_seeds(self):
+        rng = np.random.default_rng(80)
+        d = 7
+        keys = self._frame(rng, d, 3000)
+        vals = rng.integers(0, 2 ** 32, len(keys), dtype=np.uint64).astype(np.uint32)
+        vox = oracle.decode(keys, d, M).astype(np.float64)
+        out = oracle.temporal_predict(keys, vals, keys, vals, d, M, 1, 200)
+        c = out["centroids"][0]
+        dd = ((vox[:, None, :] - c[None]) ** 2)
+        dist = (dd[..., 0] + dd[..., 1]) + dd[..., 2]
+        assert (out["ref_assign"] == np.argmin(dist, 1)).all()  # nearest centre, ties low
+        assert out["iters"][0] < 200  # converged: every centre is the mean of its voxels
+        vi = oracle.decode(keys, d, M).astype(np.int64)
+        for k in range(8):
+            sel = out["ref_assign"] == k
+            if sel.any():
+                assert (c[k] == vi[sel].sum(0) / sel.sum()).all()
+        one = oracle.temporal_predict(keys, vals, keys, vals, d, M, 1, 1)
+        lo, hi = vi.min(0), vi.max(0)
+        for k in range(8):
+            corner = [hi[a] if (k >> (2 - a)) & 1 else lo[a] for a in range(3)]
+            assert one["centroids"][0][k].tolist() == corner
+        assert one["iters"].tolist() == [1, 1]
+
+    def test_translation_recovered(self):
+        rng = np.random.default_rng(81)
+        d = 8
+        vox = rng.integers(20, 200, (4000, 3))
+        t = np.array([3, -5, 2])
+        ga = int_grid(d, L)
+        ref, _ = oracle.build(vox.astype(np.float32), ga)
+        pred, _ = oracle.build((vox + t).astype(np.float32), ga)
+        rv = oracle.decode(ref, d, L).astype(np.int64)
+        ref_vals = (rv[:, 0] * 7 + rv[:, 1] * 3 + rv[:, 2]).astype(np.uint32) * np.uint32(0x010203)
+        pv = oracle.decode(pred, d, L).astype(np.int64) - t
+        pred_vals = (pv[:, 0] * 7 + pv[:, 1] * 3 + pv[:, 2]).astype(np.uint32) * np.uint32(0x010203)
+        out = oracle.temporal_predict(ref, ref_vals, pred, pred_vals, d, L, 2, 50)
+        assert (out["mv"] == t).all()
+        assert (out["ref_assign"] == out["pred_assign"]).all()  # pred is in key order too
+        assert (out["sad"] == 0).all() and (out["residual"] == 0).all()
+        assert (out["match"] == np.arange(len(ref))).all()
+
+    def test_match_is_window_sad_minimum(self):
+        rng = np.random.default_rng(82)
+        d, w = 5, 2
+        ref = self._frame(rng, d, 600)
+        pred = self._frame(rng, d, 300)
+        rvals = rng.integers(0, 2 ** 32, len(ref), dtype=np.uint64).astype(np.uint32)
+        pvals = rng.integers(0, 2 ** 32, len(pred), dtype=np.uint64).astype(np.uint32)
+        out = oracle.temporal_predict(ref, rvals, pred, pvals, d, M, w, 30)
+        rvox = oracle.decode(ref, d, M).astype(np.int64)
+        pvox = oracle.decode(pred, d, M).astype(np.int64)
+        rch, pch = _chan(rvals), _chan(pvals)
+        recon = pvox - out["mv"][out["pred_assign"]]
+        for i in range(len(pred)):
+            inwin = (np.abs(rvox - recon[i]) <= w).all(1)
+            sads = np.abs(rch - pch[i]).sum(1)
+            if not inwin.any() or (recon[i] < 0).any() or (recon[i] >= 2 ** d).any():
+                assert out["match"][i] == -1 and out["sad"][i] == 2 ** 32 - 1
+                assert (out["residual"][i] == pch[i]).all()
+                continue
+            j = out["match"][i]
+            assert inwin[j] and out["sad"][i] == sads[j] == sads[inwin].min()
+            l1 = np.abs(rvox - recon[i]).sum(1)
+            tied = inwin & (sads == sads[j])
+            assert l1[j] == l1[tied].min() and j == np.flatnonzero(tied & (l1 == l1[j]))[0]
+            assert (out["residual"][i] == pch[i] - rch[j]).all()
+
+    def test_hand_example(self):
+        """Reference voxels (4,4,4), (5,4,4), (7,4,4) with red 250, red 190,
+        green 250.  All four x-min corners are (4,4,4): the first pass puts
+        (4,4,4) and (5,4,4) in cluster 0 (ties to the lower cluster), (7,4,4)
+        in cluster 4; cluster 0 moves to x = 4.5, so the second pass gives
+        (4,4,4) to the empty cluster 1 still sitting on the corner, and the
+        third repeats: centroids (5,4,4), (4,4,4), ..., (7,4,4).  A one-voxel
+        predicted frame at (4,4,4) stays in cluster 0 with centroid 4, so its
+        motion vector is -1 on x and it is matched from (5,4,4): with window
+        1, red 190 there (SAD 10) beats the co-located red 250 (SAD 50)."""
+        g = int_grid(4, L)
+        ref, _ = oracle.build(np.array([[4, 4, 4], [5, 4, 4], [7, 4, 4]], np.float32), g)
+        rvals = np.array([250, 190, 250 << 8], np.uint32)  # channel 0 in the low byte
+        pred, _ = oracle.build(np.array([[4, 4, 4]], np.float32), g)
+        out = oracle.temporal_predict(ref, rvals, pred, np.array([200], np.uint32), 4, L, 1, 5)
+        assert out["ref_assign"].tolist() == [1, 0, 4] and out["iters"].tolist() == [3, 2]
+        assert out["centroids"][0][:2].tolist() == [[5, 4, 4], [4, 4, 4]]
+        assert out["centroids"][0][4].tolist() == [7, 4, 4]
+        assert out["mv"].tolist() == [[-1, 0, 0]] + [[0, 0, 0]] * 3 + [[-3, 0, 0]] * 4
+        assert out["match"].tolist() == [1] and out["sad"].tolist() == [10]
+        assert out["residual"].tolist() == [[10, 0, 0, 0]]
+        # (0,0,0) of value 7: motion vector (0,0,0) - (5,4,4) moves it to
+        # (5,4,4); SAD 183 from (5,4,4) beats 243 from (4,4,4)
+        far, _ = oracle.build(np.array([[0, 0, 0]], np.float32), g)
+        out = oracle.temporal_predict(ref, rvals, far, np.array([7], np.uint32), 4, L, 1, 5)
+        assert out["mv"][0].tolist() == [-5, -4, -4] and out["match"].tolist() == [1]
+        assert out["sad"].tolist() == [183] and out["residual"].tolist() == [[7 - 190, 0, 0, 0]]
+        # one pass: the centres are the corners, (0,0,0) - (4,4,4) moves it onto (4,4,4)
+        out = oracle.temporal_predict(ref, rvals, far, np.array([7], np.uint32), 4, L, 0, 1)
+        assert out["mv"][0].tolist() == [-4, -4, -4] and out["match"].tolist() == [0]
+        lone, _ = oracle.build(np.array([[1, 1, 1]], np.float32), g)
+        out = oracle.temporal_predict(lone, np.array([9], np.uint32), far,
+                                      np.array([0x01020304], np.uint32), 4, L, 0, 3)
+        assert out["mv"][0].tolist() == [-1, -1, -1] and out["match"].tolist() == [0]
+        # moved outside the grid: predicted (0,0,0), (7,10,10), (10,10,10)
+        # against a reference (0,0,0): cluster 7 settles at (8.5,10,10), motion
+        # (9,10,10), so (7,10,10) lands on x = -2: no match, SAD UINT32_MAX, its
+        # own channels; (10,10,10) lands on (1,0,0), one step from (0,0,0)
+        origin, _ = oracle.build(np.zeros((1, 3), np.float32), g)
+        moved, _ = oracle.build(np.array([[0, 0, 0], [7, 10, 10], [10, 10, 10]], np.float32), g)
+        out = oracle.temporal_predict(origin, np.array([9], np.uint32), moved,
+                                      np.array([9, 0x01020304, 5], np.uint32), 4, L, 2, 9)
+        assert out["pred_assign"].tolist() == [0, 7, 7]
+        assert out["mv"][7].tolist() == [9, 10, 10] and out["match"].tolist() == [0, -1, 0]
+        assert out["sad"].tolist() == [0, 2 ** 32 - 1, 4]
+        assert out["residual"].tolist() == [[0, 0, 0, 0], [4, 3, 2, 1], [-4, 0, 0, 0]]
