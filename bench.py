@@ -427,6 +427,40 @@ def paper_array_ops(cga, pipe, d, reps=20):
                               "same_distances": same}}
 
 
+def temporal_prediction(cga, device, reps=5):
+    """One inter-frame step of the CGA compression scheme (not part of the
+    step): the moving-object frame pair (about 5.4e5 voxels per frame on a
+    1024^3 grid), both frames built with their Value arrays, then k-means,
+    motion vectors, SAD matching and residuals (window 2, at most 100
+    passes), timed as one cga_temporal_predict call."""
+    import numpy as np
+    import torch
+
+    import gen
+    d = gen.c6_frames()
+    g = d["grid"]
+
+    def frame(xyz, cols):
+        x = torch.from_numpy(xyz).to(device)
+        keys, _ = cga.cga_build(x, g)
+        vals = cga.cga_voxel_values(x, torch.from_numpy(cols.view(np.int32)).to(device), keys, g)
+        return keys, vals
+
+    rk, rv = frame(d["ref"], d["ref_values"])
+    pk, pv = frame(d["pred"], d["pred_values"])
+    out = cga.cga_temporal_predict(rk, rv, pk, pv, g, window=2, max_iter=100)
+    ws = cga.Workspaces(device)
+    ms = _time_ms(lambda: cga.cga_temporal_predict(rk, rv, pk, pv, g, window=2, max_iter=100,
+                                                   out=out, sync=False, ws=ws), reps)
+    torch.cuda.synchronize()
+    res = out["residual"][:pk.shape[0], :3].abs().float().mean().item()
+    matched = (out["match"][:pk.shape[0]] >= 0).float().mean().item()
+    return {"ref_voxels": int(rk.shape[0]), "pred_voxels": int(pk.shape[0]),
+            "passes": out["iters"].cpu().tolist(), "ms": round(ms, 3),
+            "voxels_per_s": (rk.shape[0] + pk.shape[0]) / (ms * 1e-3),
+            "matched": round(matched, 4), "mean_abs_rgb_residual": round(res, 3)}
+
+
 def attribute_values(cga, pipe, d, reps=20):
     """Value arrays of the step's two sweeps from seeded per-point attributes,
     and the merged cloud's values (average policy); not part of the step."""
@@ -626,6 +660,7 @@ def main():
     line["occupancy"] = occupancy_codes(cga, pipe)
     line["values"] = attribute_values(cga, pipe, d)
     line["paper_array_ops"] = paper_array_ops(cga, pipe, d)
+    line["temporal"] = temporal_prediction(cga, device)
     if not args.no_c5:
         line["c5"] = c5_learned_vs_binary(cga, device, args.c5_reps)
     if not args.no_c4:

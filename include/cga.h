@@ -166,6 +166,43 @@ int cga_arrays_nn(const cga_grid *grid, const uint32_t *d_x_index, int64_t n_x,
                   const uint32_t *d_z_index, int64_t n, const float *d_q, int64_t nq,
                   int64_t *d_idx, uint64_t *d_d2, void *d_ws, size_t ws_bytes, cga_stream stream);
 
+/* ---------------------------------------------------- temporal prediction
+ * One inter-frame step of the CGA point cloud compression scheme (Section
+ * V-D): a predicted frame against a reference frame, both CGAs of the same
+ * grid (ascending unique keys of the grid's width and mode, one packed
+ * 4 x 8-bit value per voxel, as cga_voxel_values writes them).
+ *   1. k-means over each frame's voxels with eight centres started at the
+ *      corners of its bounding box (centre i: maximum x if bit 2 of i is
+ *      set, else minimum; y by bit 1; z by bit 0).  A pass assigns every
+ *      voxel to its nearest centre (squared distance in double precision,
+ *      (dx^2 + dy^2) + dz^2 with every operation rounded, ties to the lower
+ *      centre); the run ends at the first pass that changes no assignment,
+ *      or after max_iter passes, else each non-empty cluster moves to its
+ *      mean (exact integer sums, one rounded division).
+ *   2. motion vector of cluster i: predicted minus reference centroid i,
+ *      rounded half away from zero to whole voxels.
+ *   3. each predicted voxel moved back by its cluster's vector is matched to
+ *      the reference voxel of least SAD over the four channels among those
+ *      within `window` voxels on every axis (ties: smaller L1 offset, then
+ *      smaller key).
+ *   4. residual = predicted minus matched channels, as int16.
+ * Outputs: d_ref_assign / d_pred_assign (uint8 cluster per voxel), optional
+ * d_centroids (double [2][8][3]: reference, predicted), d_mv (int32 [8][3]),
+ * d_iters (int32 [2]: passes run), d_match (int64 index into the reference
+ * keys, -1 when the moved voxel left the grid or its window holds no
+ * reference voxel), d_sad (uint32, UINT32_MAX without a match), d_residual
+ * (int16 [n_pred][4]; the voxel's own channels without a match).
+ * window in [0, 15], max_iter in [1, 1000] (else CGA_EINVAL).  The keys
+ * are trusted to be sorted and unique.  Workspace:
+ * cga_temporal_workspace_bytes() bytes. */
+size_t cga_temporal_workspace_bytes(void);
+int cga_temporal_predict(const cga_grid *grid, const void *d_ref_keys, const uint32_t *d_ref_values,
+                         int64_t n_ref, const void *d_pred_keys, const uint32_t *d_pred_values,
+                         int64_t n_pred, int window, int max_iter, uint8_t *d_ref_assign,
+                         uint8_t *d_pred_assign, double *d_centroids, int32_t *d_mv,
+                         int32_t *d_iters, int64_t *d_match, uint32_t *d_sad, int16_t *d_residual,
+                         void *d_ws, size_t ws_bytes, cga_stream stream);
+
 /* ------------------------------------------------------------------ merge
  * Merge, Eq. (1): the union of two CGAs of the same grid (sorted unique key
  * arrays a, b) as one sorted unique key array.  d_src (nullable) receives a

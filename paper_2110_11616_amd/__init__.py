@@ -81,6 +81,9 @@ _sig("cga_arrays_lookup", ctypes.c_int, _GP, _P, _I64, _P, _P, _P, _I64, _P, _P,
      _I64, _P, _P, _SZ, _P)
 _sig("cga_arrays_nn", ctypes.c_int, _GP, _P, _I64, _P, _P, _P, _I64, _P, _P, _P, _I64, _P, _I64,
      _P, _P, _P, _SZ, _P)
+_sig("cga_temporal_workspace_bytes", _SZ)
+_sig("cga_temporal_predict", ctypes.c_int, _GP, _P, _P, _I64, _P, _P, _I64, ctypes.c_int,
+     ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P)
 _sig("cga_merge_workspace_bytes", _SZ, _GP, _I64, _I64)
 _sig("cga_merge", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _P, _P, _I64, _P, _I64P, _P, _SZ,
      _P)
@@ -315,6 +318,39 @@ def cga_arrays_nn(arr: dict, queries: torch.Tensor, grid, *, idx_out=None, d2_ou
     if sync:
         _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_arrays_nn")
     return idx, d2
+
+
+def cga_temporal_predict(ref_keys: torch.Tensor, ref_values: torch.Tensor, pred_keys: torch.Tensor,
+                         pred_values: torch.Tensor, grid, *, window: int = 2, max_iter: int = 20,
+                         out: dict = None, sync: bool = True, ws=None, stream=None) -> dict:
+    """Temporal prediction (Section V-D): 8-centre k-means of both frames,
+    motion vectors, SAD matching in a +-window box, residuals."""
+    g = grid_struct(grid)
+    nr, npd = ref_keys.shape[0], pred_keys.shape[0]
+    dev = pred_keys.device
+    o = out if out is not None else dict(
+        ref_assign=torch.empty(max(nr, 1), dtype=torch.uint8, device=dev),
+        pred_assign=torch.empty(max(npd, 1), dtype=torch.uint8, device=dev),
+        centroids=torch.empty((2, 8, 3), dtype=torch.float64, device=dev),
+        mv=torch.empty((8, 3), dtype=torch.int32, device=dev),
+        iters=torch.empty(2, dtype=torch.int32, device=dev),
+        match=torch.empty(max(npd, 1), dtype=torch.int64, device=dev),
+        sad=torch.empty(max(npd, 1), dtype=torch.int32, device=dev),
+        residual=torch.empty((max(npd, 1), 4), dtype=torch.int16, device=dev))
+    wsb = _ws("temporal", lib.cga_temporal_workspace_bytes(), ws)
+    _check(lib.cga_temporal_predict(ctypes.byref(g), _ptr(ref_keys), _ptr(ref_values), nr,
+                                    _ptr(pred_keys), _ptr(pred_values), npd, int(window),
+                                    int(max_iter), _ptr(o["ref_assign"]), _ptr(o["pred_assign"]),
+                                    _ptr(o["centroids"]), _ptr(o["mv"]), _ptr(o["iters"]),
+                                    _ptr(o["match"]), _ptr(o["sad"]), _ptr(o["residual"]),
+                                    _ptr(wsb), wsb.numel(), _stream(stream)),
+           "cga_temporal_predict")
+    if sync:
+        _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_temporal_predict")
+        for name, n in (("ref_assign", nr), ("pred_assign", npd), ("match", npd), ("sad", npd),
+                        ("residual", npd)):
+            o[name] = o[name][:n]
+    return o
 
 
 def cga_merge(a: torch.Tensor, b: torch.Tensor, grid, *, src: bool = False, cap=None, na=None,

@@ -581,3 +581,55 @@ def test_device_count_pipeline_and_repeat(gpu, w_c2s):
         assert torch.equal(m[: n[2]], ref_m) and torch.equal(p[: n[3]], ref_p)
         assert torch.equal(c[: n[3]], ref_c)
         assert torch.equal(i, ref_i) and torch.equal(dd, ref_d)
+
+
+# ----------------------------------------------------- temporal prediction
+def _temporal_check(gpu, g, ref, rvals, pred, pvals, window=2, max_iter=20):
+    want = oracle.temporal_predict(ref, rvals, pred, pvals, g.depth, g.key_mode, window, max_iter)
+    got = gpu.cga_temporal_predict(keys_dev(ref, g), dev(rvals.view(np.int32)), keys_dev(pred, g),
+                                   dev(pvals.view(np.int32)), g, window=window, max_iter=max_iter)
+    for name in ("ref_assign", "pred_assign", "centroids", "mv", "iters", "match", "residual"):
+        np.testing.assert_array_equal(got[name].cpu().numpy(), want[name], err_msg=name)
+    np.testing.assert_array_equal(got["sad"].cpu().numpy().view(np.uint32), want["sad"])
+    return want
+
+
+@pytest.fixture(scope="module")
+def w_c6s():
+    # the moving-object frame pair at 1/10 of the points, on a 512^3 grid
+    return gen.c6_frames(n=100_000, depth=9)
+
+
+@pytest.mark.parametrize("mode", [L, M])
+def test_temporal_c6s(gpu, w_c6s, mode):
+    d = w_c6s
+    g = d["grid"].with_mode(mode)
+    ref, rvals = oracle.voxel_values(d["ref"], d["ref_values"], g)
+    pred, pvals = oracle.voxel_values(d["pred"], d["pred_values"], g)
+    say("temporal c6s", mode, len(ref), len(pred))
+    want = _temporal_check(gpu, g, ref, rvals, pred, pvals)
+    assert (want["match"] >= 0).mean() > 0.9  # the motion compensation finds most voxels
+
+
+def test_temporal_edges(gpu):
+    rng = np.random.default_rng(91)
+    g = Grid((0.0, 0.0, 0.0), 1.0, 5, M)
+    ref, _ = oracle.build(rng.integers(0, 32, (400, 3)).astype(np.float32), g)
+    pred, _ = oracle.build(rng.integers(0, 32, (300, 3)).astype(np.float32), g)
+    rvals = rng.integers(0, 2 ** 32, len(ref), dtype=np.uint64).astype(np.uint32)
+    pvals = rng.integers(0, 2 ** 32, len(pred), dtype=np.uint64).astype(np.uint32)
+    for window, max_iter in ((0, 1), (1, 3), (2, 50), (5, 1000)):
+        _temporal_check(gpu, g, ref, rvals, pred, pvals, window, max_iter)
+    gl = g.with_mode(L)
+    lref, lr = oracle.voxel_values(oracle.decode(ref, 5, M).astype(np.float32), rvals, gl)
+    lpred, lp = oracle.voxel_values(oracle.decode(pred, 5, M).astype(np.float32), pvals, gl)
+    _temporal_check(gpu, gl, lref, lr, lpred, lp, 3, 20)
+    _temporal_check(gpu, gl, lref[:1], lr[:1], lpred, lp, 2, 20)  # one reference voxel
+    _temporal_check(gpu, gl, lref, lr, lpred[:1], lp[:1], 2, 20)  # one predicted voxel
+    e = np.zeros(0, np.uint64)
+    _temporal_check(gpu, gl, e, lr[:0], lpred, lp, 2, 20)  # empty reference: no matches
+    _temporal_check(gpu, gl, lref, lr, e, lp[:0], 2, 20)  # empty predicted frame
+    with pytest.raises(gpu.CgaError) as err:
+        gpu.cga_temporal_predict(keys_dev(lref, gl), dev(lr.view(np.int32)), keys_dev(lpred, gl),
+                                 dev(lp.view(np.int32)), gl, window=16)
+    assert err.value.status == gpu.EINVAL
