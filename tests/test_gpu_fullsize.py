@@ -9,6 +9,10 @@ sizes:
   with the oracle itself (std::map build, std::set_union merge, coordinate
   drop), k-NN rows on a seeded sample of 2000 queries with the oracle's kd-tree
   over the whole union, and every lookup with std::lower_bound.
+* c2 again on a LINEAR grid: the paper's NN on the five arrays for all 100k
+  queries against the kd-tree 1-NN, and its three-level lookup on 200k voxels.
+* c6: the temporal-prediction step on the full moving-object frame pair,
+  every output against the oracle.
 * c3: 2 x 10M points, depth 14, 1M queries, k = 16 -- build, merge and the
   three projections compared with the definitions the oracle states (its
   per-point quantize and key encode, each deduplicated with numpy: a set of
@@ -128,3 +132,51 @@ def test_c3_full(gpu):
     idx_ref, d2_ref = oracle.knn_brute(m, d["q"][rows], g, d["k"])
     _check_knn_rows(pipe, rows, idx_ref, d2_ref)
     _check_lookups(pipe, m, sample=np.arange(0, len(pipe.lq), 7))
+
+
+def test_c2_paper_array_ops_full(gpu):
+    """The paper's lookup and NN on the five arrays of the full c2 union
+    (LINEAR): every NN row vs the kd-tree 1-NN, lookups vs the oracle's
+    three-level search on 200k voxels."""
+    cga = gpu
+    d = gen.c2_lidar()
+    g = d["grid"].with_mode(gen.KEY_LINEAR)
+    ka, _ = oracle.build(d["a"], g)
+    kb, _ = oracle.build(d["b"], g)
+    m, _ = oracle.merge(ka, kb, g.depth, g.key_mode)
+    say("c2 paper array ops: union", len(m))
+    mk = cga.cga_build(torch.from_numpy(d["a"]).to("cuda:0"), g)[0]
+    mb = cga.cga_build(torch.from_numpy(d["b"]).to("cuda:0"), g)[0]
+    mg, _ = cga.cga_merge(mk, mb, g)
+    arr = cga.cga_to_arrays(mg, g)
+    idx, d2 = cga.cga_arrays_nn(arr, torch.from_numpy(d["q"]).to("cuda:0"), g)
+    widx, wd2 = oracle.knn_kdtree(m, d["q"], g, 1)
+    np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint64), wd2[:, 0])
+    np.testing.assert_array_equal(idx.cpu().numpy(), widx[:, 0])
+    rng = np.random.default_rng(2004)
+    qv = np.concatenate([oracle.decode(m[rng.integers(0, len(m), 100_000)], g.depth, g.key_mode),
+                         rng.integers(0, 2 ** g.depth, (100_000, 3))]).astype(np.uint32)
+    pos = cga.cga_arrays_lookup(arr, torch.from_numpy(qv.view(np.int32)).to("cuda:0"), g)
+    np.testing.assert_array_equal(pos.cpu().numpy(), oracle.lookup_cga(oracle.arrays(m, g.depth, g.key_mode), qv))
+
+
+def test_c6_temporal_full(gpu):
+    """The temporal step on the full moving-object frame pair (1024^3 grid),
+    in the configuration bench.py times (window 2, at most 100 passes):
+    every output vs the oracle."""
+    cga = gpu
+    d = gen.c6_frames()
+    g = d["grid"]
+    ref, rv = oracle.voxel_values(d["ref"], d["ref_values"], g)
+    pred, pv = oracle.voxel_values(d["pred"], d["pred_values"], g)
+    say("c6 temporal full:", len(ref), len(pred))
+    want = oracle.temporal_predict(ref, rv, pred, pv, g.depth, g.key_mode, 2, 100)
+    dev = torch.device("cuda:0")
+    got = cga.cga_temporal_predict(torch.from_numpy(ref.astype(np.uint32).view(np.int32)).to(dev),
+                                   torch.from_numpy(rv.view(np.int32)).to(dev),
+                                   torch.from_numpy(pred.astype(np.uint32).view(np.int32)).to(dev),
+                                   torch.from_numpy(pv.view(np.int32)).to(dev), g, window=2,
+                                   max_iter=100)
+    for name in ("ref_assign", "pred_assign", "centroids", "mv", "iters", "match", "residual"):
+        np.testing.assert_array_equal(got[name].cpu().numpy(), want[name], err_msg=name)
+    np.testing.assert_array_equal(got["sad"].cpu().numpy().view(np.uint32), want["sad"])
