@@ -83,6 +83,10 @@ __global__ __launch_bounds__(256) void k_km_bbox(Frames<K> F, uint32_t depth, bo
             hi[a] = c[a] > hi[a] ? c[a] : hi[a];
         }
     }
+    // wave, then block, then one atomic per block and value
+    __shared__ uint32_t s_m[6];
+    if (threadIdx.x < 6) s_m[threadIdx.x] = 0;
+    __syncthreads();
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         uint32_t l = ~lo[a], h = hi[a];
@@ -92,10 +96,13 @@ __global__ __launch_bounds__(256) void k_km_bbox(Frames<K> F, uint32_t depth, bo
             h = h2 > h ? h2 : h;
         }
         if ((threadIdx.x & 63) == 0) {
-            atomicMax(&st[f].lo_inv[a], l);
-            atomicMax(&st[f].hi[a], h);
+            atomicMax(&s_m[a], l);
+            atomicMax(&s_m[3 + a], h);
         }
     }
+    __syncthreads();
+    if (threadIdx.x < 3) atomicMax(&st[f].lo_inv[threadIdx.x], s_m[threadIdx.x]);
+    else if (threadIdx.x < 6) atomicMax(&st[f].hi[threadIdx.x - 3], s_m[threadIdx.x]);
 }
 
 __global__ void k_km_seed(KmState *st) {
@@ -128,28 +135,55 @@ __global__ __launch_bounds__(256) void k_km_assign(Frames<K> F, uint32_t depth, 
         for (int a = 0; a < 3; ++a) c[k][a] = S.cent[k][a];
     __syncthreads();
     bool changed = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.n[f];
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const Vox v = dec3((uint64_t)F.keys[f][i], depth, linear);
-        const double px = (double)v.x, py = (double)v.y, pz = (double)v.z;
+    const int lane = threadIdx.x & 63;
+    // whole waves step together, so that the sums can be gathered per wave:
+    // neighbouring keys are neighbouring voxels, so a wave rarely spans more
+    // than one or two clusters, and each cluster costs one reduction
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t base = wave * 64; base < F.n[f]; base += waves * 64) {
+        const int64_t i = base + lane;
+        const bool active = i < F.n[f];
+        Vox v{0, 0, 0};
         int best = 0;
-        double bd = 0.0;
+        if (active) {
+            v = dec3((uint64_t)F.keys[f][i], depth, linear);
+            const double px = (double)v.x, py = (double)v.y, pz = (double)v.z;
+            double bd = 0.0;
 #pragma unroll
-        for (int k = 0; k < kCl; ++k) {
-            const double dx = __dsub_rn(px, c[k][0]), dy = __dsub_rn(py, c[k][1]),
-                         dz = __dsub_rn(pz, c[k][2]);
-            const double d = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-            if (k == 0 || d < bd) {
-                bd = d;
-                best = k;
+            for (int k = 0; k < kCl; ++k) {
+                const double dx = __dsub_rn(px, c[k][0]), dy = __dsub_rn(py, c[k][1]),
+                             dz = __dsub_rn(pz, c[k][2]);
+                const double d = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+                if (k == 0 || d < bd) {
+                    bd = d;
+                    best = k;
+                }
             }
+            if (pass == 0 || F.assign[f][i] != best) changed = true;
+            F.assign[f][i] = (uint8_t)best;
         }
-        if (pass == 0 || F.assign[f][i] != best) changed = true;
-        F.assign[f][i] = (uint8_t)best;
-        atomicAdd(&s_sum[best * 4 + 0], (unsigned long long)v.x);
-        atomicAdd(&s_sum[best * 4 + 1], (unsigned long long)v.y);
-        atomicAdd(&s_sum[best * 4 + 2], (unsigned long long)v.z);
-        atomicAdd(&s_sum[best * 4 + 3], 1ull);
+        uint64_t rem = __ballot(active);
+        while (rem) {
+            const int leader = __ffsll((unsigned long long)rem) - 1;
+            const int k = __shfl(best, leader, 64);
+            const bool mine = active && best == k;
+            const uint64_t m = __ballot(mine);
+            // at most 64 coordinates below 2^21 each: 32-bit sums are exact
+            uint32_t sx = mine ? v.x : 0u, sy = mine ? v.y : 0u, sz = mine ? v.z : 0u;
+            for (int o = 32; o > 0; o >>= 1) {
+                sx += __shfl_xor(sx, o, 64);
+                sy += __shfl_xor(sy, o, 64);
+                sz += __shfl_xor(sz, o, 64);
+            }
+            if (lane == leader) {
+                atomicAdd(&s_sum[k * 4 + 0], (unsigned long long)sx);
+                atomicAdd(&s_sum[k * 4 + 1], (unsigned long long)sy);
+                atomicAdd(&s_sum[k * 4 + 2], (unsigned long long)sz);
+                atomicAdd(&s_sum[k * 4 + 3], (unsigned long long)__popcll(m));
+            }
+            rem &= ~m;
+        }
     }
     if (__ballot(changed) && (threadIdx.x & 63) == 0) s_changed = 1;
     __syncthreads();
@@ -314,7 +348,10 @@ static void temporal_launch(const cga_grid *g, const K *rk, const uint32_t *rv, 
                             hipStream_t s) {
     const bool linear = g->key_mode == CGA_KEY_LINEAR;
     Frames<K> F{{rk, pk}, {nr, np}, {ra, pa}};
-    const dim3 grid(temporal_grid(nr > np ? nr : np), 2);
+    // a few blocks per CU, striding over the frame: few global atomics per pass
+    unsigned gb = temporal_grid(nr > np ? nr : np);
+    gb = gb < 512 ? gb : 512;
+    const dim3 grid(gb, 2);
     {
         CGA_PROF("temporal_kmeans", s);
         k_km_bbox<K><<<grid, 256, 0, s>>>(F, g->depth, linear, L.st);
