@@ -657,6 +657,7 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
             Dist gxl = 0, gxh = 0, gyl = 0, gyh = 0, gzl = 0, gzh = 0;
             bool touch = false;
             uint64_t bnd = 0;
+            uint32_t near = 0;  // children (by octant) within the bound at entry
             auto enter = [&]() __attribute__((always_inline)) {
                 const int cl = l - 1;
                 qol = qo(cl);
@@ -672,6 +673,13 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
                 gzh = bz * bz;
                 touch = skip && cl == sk_l;
                 bnd = bound_now();
+                // children already beyond the bound never take a step
+                const Dist xl = gxl, xh = gxh;
+                const Dist q0 = xl + gyl, q1 = xl + gyh, q2 = xh + gyl, q3 = xh + gyh;
+                near = (q0 + gzl <= bnd ? 0x01u : 0u) | (q0 + gzh <= bnd ? 0x02u : 0u) |
+                       (q1 + gzl <= bnd ? 0x04u : 0u) | (q1 + gzh <= bnd ? 0x08u : 0u) |
+                       (q2 + gzl <= bnd ? 0x10u : 0u) | (q2 + gzh <= bnd ? 0x20u : 0u) |
+                       (q3 + gzl <= bnd ? 0x40u : 0u) | (q3 + gzh <= bnd ? 0x80u : 0u);
             };
             uint32_t pm = 0;
             // One iteration: start this lane's next subtree, climb back to
@@ -741,7 +749,7 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
                 if (moved) {
                     enter();
                     const uint32_t done_slots = climbed ? (2u << near_order(done_oc ^ qol)) - 1u : 0u;
-                    pm = slot_mask((uint32_t)w & 0xFFu, qol) & ~done_slots;
+                    pm = slot_mask((uint32_t)w & near, qol) & ~done_slots;
                 }
             }
         }
