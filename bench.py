@@ -632,6 +632,17 @@ def main():
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
             }
         cga.cga_prof_reset()
+    # context for the other kernels of the step that move bytes: algorithmic
+    # bytes per step over their measured time per step (untimed warm passes
+    # above), next to the same HBM peak and, where counted, their traffic
+    by_kernel = {}
+    for lb, kms in kern_ms.items():
+        algo = algorithmic_bytes(lb, pipe, counts)
+        if algo is None or kms <= 0:
+            continue
+        gbs = algo / (kms * 1e-3) / 1e9
+        by_kernel[lb] = {"ms_per_step": kms, "algorithmic_mb_per_step": round(algo / 1e6, 2),
+                         "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
     line = {
         "metric": "CGA build+merge points/s & kNN queries/s at % HBM peak; learned vs binary lookup/s",
@@ -655,6 +666,7 @@ def main():
         },
         "kernels_ms_per_step": kern_ms,
         "roofline": roofline,
+        "hbm_by_kernel": by_kernel,
         "cpu_baseline": None,
     }
     line["occupancy"] = occupancy_codes(cga, pipe)
