@@ -656,23 +656,32 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
             uint32_t qol = 0;
             Dist gxl = 0, gxh = 0, gyl = 0, gyh = 0, gzl = 0, gzh = 0;
             bool touch = false;
-            uint64_t bnd = 0;
+            // the bound in the distance type, saturated (every distance of a
+            // packed-list grid is below 2^32 - 1, so "<=" keeps its meaning)
+            Dist bnd = 0;
+            auto to_dist = [](uint64_t b) __attribute__((always_inline)) -> Dist {
+                return b > (uint64_t)(Dist)~(Dist)0 ? (Dist)~(Dist)0 : (Dist)b;
+            };
             uint32_t near = 0;  // children (by octant) within the bound at entry
             auto enter = [&]() __attribute__((always_inline)) {
                 const int cl = l - 1;
                 qol = qo(cl);
-                const uint32_t h = 1u << cl, e = h - 1u;
-                const Dist ax = axis_gap(qv.x, x0, x0 + e), bx = axis_gap(qv.x, x0 + h, x0 + h + e);
-                const Dist ay = axis_gap(qv.y, y0, y0 + e), by = axis_gap(qv.y, y0 + h, y0 + h + e);
-                const Dist az = axis_gap(qv.z, z0, z0 + e), bz = axis_gap(qv.z, z0 + h, z0 + h + e);
-                gxl = ax * ax;
-                gxh = bx * bx;
-                gyl = ay * ay;
-                gyh = by * by;
-                gzl = az * az;
-                gzh = bz * bz;
+                // gaps to the low half [0, h) and the high half [h, 2h) of the
+                // node along an axis, from the query's signed offset t (every
+                // coordinate is below 2^21): max(-t, t - (h - 1), 0) and
+                // max(h - t, t - (2h - 1), 0)
+                const int32_t h = 1 << cl;
+                auto gaps = [&](uint32_t q, uint32_t c0, Dist &lo2, Dist &hi2) __attribute__((always_inline)) {
+                    const int32_t t = (int32_t)(q - c0);
+                    const int32_t gl = max(max(-t, t - (h - 1)), 0), gh = max(max(h - t, t - (2 * h - 1)), 0);
+                    lo2 = (Dist)gl * (Dist)gl;
+                    hi2 = (Dist)gh * (Dist)gh;
+                };
+                gaps(qv.x, x0, gxl, gxh);
+                gaps(qv.y, y0, gyl, gyh);
+                gaps(qv.z, z0, gzl, gzh);
                 touch = skip && cl == sk_l;
-                bnd = bound_now();
+                bnd = to_dist(bound_now());
                 // children already beyond the bound never take a step
                 const Dist xl = gxl, xh = gxh;
                 const Dist q0 = xl + gyl, q1 = xl + gyh, q2 = xh + gyl, q3 = xh + gyh;
@@ -734,7 +743,7 @@ __global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
                         const int32_t ci = (int32_t)(w >> 8) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
                         if (cl == 0) {
                             offer(bd, ci);
-                            bnd = kth < bnd ? kth : bnd;
+                            bnd = kth < (uint64_t)bnd ? to_dist(kth) : bnd;
                         } else {
                             w = node[s_base[cl] + ci];
                             s_word[cl * kKnnBlock + tid] = w;
