@@ -13,6 +13,10 @@ sizes:
   queries against the kd-tree 1-NN, and its three-level lookup on 200k voxels.
 * c6: the temporal-prediction step on the full moving-object frame pair,
   every output against the oracle.
+* c4: the 256-frame batch through the captured graph -- every frame's key
+  count, and ten frames with their pair unions, against the definitions.
+* c5: the 50M-key learned index (linear and network leaves) -- all 10M
+  lookups against std::lower_bound.
 * c3: 2 x 10M points, depth 14, 1M queries, k = 16 -- build, merge and the
   three projections compared with the definitions the oracle states (its
   per-point quantize and key encode, each deduplicated with numpy: a set of
@@ -180,3 +184,61 @@ def test_c6_temporal_full(gpu):
     for name in ("ref_assign", "pred_assign", "centroids", "mv", "iters", "match", "residual"):
         np.testing.assert_array_equal(got[name].cpu().numpy(), want[name], err_msg=name)
     np.testing.assert_array_equal(got["sad"].cpu().numpy().view(np.uint32), want["sad"])
+
+
+def test_c4_full(gpu):
+    """The 256-frame batch (92.6M points) through the captured graph, as bench.py
+    replays it: ten frames and their pair unions against the definitions
+    (per-point quantize and key encode, np.unique, np.union1d), and every
+    frame's key count against one np.unique over (frame, key)."""
+    cga = gpu
+    d = gen.c4_frames()
+    g, xyz, off = d["grid"], d["xyz"], d["off"]
+    F = len(off) - 1
+    say("c4 full:", F, "frames,", len(xyz), "points")
+    dev = torch.device("cuda:0")
+    graph = cga.BatchGraph(torch.from_numpy(xyz).to(dev), torch.from_numpy(off).to(dev), g)
+    graph.launch()
+    torch.cuda.synchronize()
+    assert graph.status() == 0
+    keys = oracle.encode(oracle.quantize(xyz, g), g.depth, g.key_mode)
+    frame = np.repeat(np.arange(F, dtype=np.uint64), np.diff(off))
+    comp = np.unique((frame << np.uint64(3 * g.depth)) | keys)
+    per_frame = np.bincount((comp >> np.uint64(3 * g.depth)).astype(np.int64), minlength=F)
+    np.testing.assert_array_equal(np.diff(graph.out.key_off.cpu().numpy()), per_frame)
+    rng = np.random.default_rng(2005)
+    picks = sorted(set([0, 1, F - 2] + rng.choice(F - 1, 7, replace=False).tolist()))
+    for f in picks:
+        kf = np.unique(keys[off[f]:off[f + 1]])
+        kn = np.unique(keys[off[f + 1]:off[f + 2]])
+        np.testing.assert_array_equal(_keys(graph.out.frame(f), len(kf)), kf)
+        np.testing.assert_array_equal(u64(graph.out.pair(f)), np.union1d(kf, kn))
+    graph.close()
+
+
+def test_c5_full(gpu):
+    """The 50M-key learned index as bench.py trains it (linear leaves, 65,536
+    leaves, 4096-segment root; and 65,536 network leaves), keys built by the
+    definition (quantize, encode, np.unique, the seeded subset), all 10M
+    lookups against the oracle's std::lower_bound."""
+    cga = gpu
+    d = gen.c5_sweeps()
+    g = d["grid"]
+    keys = np.unique(oracle.encode(oracle.quantize(d["xyz"], g), g.depth, g.key_mode))
+    del d
+    u, target = len(keys), 50_000_000
+    if u > target:
+        keys = keys[gen.subset(1005, u, target)]
+    q = gen.lookup_queries(1005, keys, 10_000_000)
+    say("c5 full:", len(keys), "keys,", len(q), "lookups")
+    rank_want, found_want = oracle.lower_bound(keys, q)
+    dev = torch.device("cuda:0")
+    kd = torch.from_numpy(keys.view(np.int64)).to(dev)
+    qd = torch.from_numpy(q.view(np.int64)).to(dev)
+    for kind, leaves, root in ((0, 65536, 4096), (cga.LEAF_MLP, 65536, 4096)):
+        idx = cga.cga_index_train(kd, n_leaves=leaves, leaf_kind=kind, root_segments=root)
+        r, f, _ = cga.cga_index_lookup(idx, kd, qd)
+        np.testing.assert_array_equal(r.cpu().numpy(), rank_want)
+        np.testing.assert_array_equal(f.cpu().numpy().astype(bool), found_want.astype(bool))
+    r, f = cga.cga_binary_lookup(kd, qd)
+    np.testing.assert_array_equal(r.cpu().numpy(), rank_want)
