@@ -2,8 +2,8 @@
 
 One step of bench.py's own pipeline (build two clouds, merge, project onto
 XY, k-NN of the queries against the union, learned index of the union and
-its lookups next to binary search) runs on the GPU at the workloads' full
-sizes:
+its lookups next to binary search), in the overlapped form bench.py times,
+runs on the GPU at the workloads' full sizes:
 
 * c2: 2 x 1,048,576 LiDAR points, depth 12, 100k queries, k = 8 -- compared
   with the oracle itself (std::map build, std::set_union merge, coordinate
@@ -43,7 +43,7 @@ def _run_step(cga, d):
     pipe.check()
     pipe.nu = int(pipe.cnt[2].item())
     pipe.make_lookups()
-    pipe.step()
+    pipe.step_concurrent()  # the timed form: independent parts on side streams
     torch.cuda.synchronize()
     pipe.check()
     return pipe
