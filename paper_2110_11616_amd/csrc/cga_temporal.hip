@@ -34,16 +34,20 @@ constexpr int kCl = 8;  // clusters (the bounding-box corners)
 constexpr int kTemporalMaxWindow = 15;
 constexpr int kTemporalMaxIter = 1000;
 
-// Per-frame k-means state, zeroed at the start of a call.
+// Per-frame k-means state, zeroed at the start of a call.  Pass t assigns
+// with the centres cent[t & 1] and sums into sum / cnt / changed [t % 3]; it
+// computes its centres itself, in every block, from pass t - 1's sums (so
+// no launch sits between passes), and clears slot (t + 1) % 3, which pass
+// t - 1 finished reading.
 struct KmState {
-    double cent[kCl][3];
-    unsigned long long sum[kCl][3];
-    unsigned long long cnt[kCl];
+    double cent[2][kCl][3];
+    unsigned long long sum[3][kCl][3];
+    unsigned long long cnt[3][kCl];
+    uint32_t changed[3];
     uint32_t lo_inv[3];  // ~min per axis (so that a zeroed block starts at "no voxel")
     uint32_t hi[3];
-    uint32_t changed, done;
-    int32_t iters;
-    uint32_t pad;
+    uint32_t halt;       // the run has ended: later passes do nothing
+    int32_t iters;       // passes run
 };
 
 template <typename K>
@@ -112,28 +116,56 @@ __global__ void k_km_seed(KmState *st) {
         for (int a = 0; a < 3; ++a) {
             uint32_t lo = ~st[f].lo_inv[a], hi = st[f].hi[a];
             if (lo > hi) lo = hi = 0;  // an empty frame: every corner at the origin
-            st[f].cent[c][a] = (double)(((c >> (2 - a)) & 1) ? hi : lo);
+            st[f].cent[0][c][a] = (double)(((c >> (2 - a)) & 1) ? hi : lo);
         }
     }
 }
 
-// One assignment pass over both frames (no-op for a converged frame).
+// One pass over both frames: stop if the previous pass changed nothing,
+// else move to the previous pass's cluster means and assign every voxel.
 template <typename K>
 __global__ __launch_bounds__(256) void k_km_assign(Frames<K> F, uint32_t depth, bool linear, int pass,
                                                    KmState *st) {
     const int f = blockIdx.y;
     KmState &S = st[f];
-    if (S.done) return;
+    if (S.halt) return;  // block-uniform
+    const int cur = pass % 3, prev = (pass + 2) % 3, next = (pass + 1) % 3;
+    if (pass > 0 && !S.changed[prev]) {  // the run ended with the previous pass
+        if (blockIdx.x == 0 && threadIdx.x == 0) S.halt = 1;
+        return;
+    }
     __shared__ unsigned long long s_sum[kCl * 4];
     __shared__ uint32_t s_changed;
     for (int t = threadIdx.x; t < kCl * 4; t += blockDim.x) s_sum[t] = 0;
     if (threadIdx.x == 0) s_changed = 0;
+    // pass 0 starts from the corners in cent[0]; pass t > 0 from the means
+    // of pass t - 1's clusters, an empty cluster keeping pass t - 1's centre
+    // (24 lanes divide, the block reads the results from LDS)
+    __shared__ double s_c[kCl * 3];
+    if (threadIdx.x < kCl * 3) {
+        const int k = threadIdx.x / 3, a = threadIdx.x % 3;
+        const int before = pass > 0 ? (pass + 1) & 1 : 0;
+        const unsigned long long n = pass > 0 ? S.cnt[prev][k] : 0ull;
+        const double v = n > 0 ? __ddiv_rn((double)S.sum[prev][k][a], (double)n) : S.cent[before][k][a];
+        s_c[threadIdx.x] = v;
+        // block 0 keeps this pass's centres (for the next pass's empty
+        // clusters and for the result)
+        if (blockIdx.x == 0 && pass > 0) S.cent[pass & 1][k][a] = v;
+    }
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) S.iters = pass + 1;
+        if (threadIdx.x < kCl * 4) {
+            if ((threadIdx.x & 3) == 3) S.cnt[next][threadIdx.x >> 2] = 0;
+            else S.sum[next][threadIdx.x >> 2][threadIdx.x & 3] = 0;
+        }
+        if (threadIdx.x == 0) S.changed[next] = 0;
+    }
+    __syncthreads();
     double c[kCl][3];
 #pragma unroll
     for (int k = 0; k < kCl; ++k)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) c[k][a] = S.cent[k][a];
-    __syncthreads();
+        for (int a = 0; a < 3; ++a) c[k][a] = s_c[k * 3 + a];
     bool changed = false;
     const int lane = threadIdx.x & 63;
     // whole waves step together, so that the sums can be gathered per wave:
@@ -189,35 +221,9 @@ __global__ __launch_bounds__(256) void k_km_assign(Frames<K> F, uint32_t depth, 
     __syncthreads();
     for (int t = threadIdx.x; t < kCl * 4; t += blockDim.x) {
         const unsigned long long v = s_sum[t];
-        if (v) atomicAdd((t & 3) == 3 ? &S.cnt[t >> 2] : &S.sum[t >> 2][t & 3], v);
+        if (v) atomicAdd((t & 3) == 3 ? &S.cnt[cur][t >> 2] : &S.sum[cur][t >> 2][t & 3], v);
     }
-    if (threadIdx.x == 0 && s_changed) atomicOr(&S.changed, 1u);
-}
-
-// After a pass: stop, or move every non-empty cluster to its mean.
-__global__ void k_km_update(KmState *st, int max_iter) {
-    KmState &S = st[blockIdx.x];
-    if (S.done) return;
-    __shared__ bool stop;
-    if (threadIdx.x == 0) {
-        ++S.iters;
-        stop = !S.changed || S.iters >= max_iter;
-        if (stop) S.done = 1;
-    }
-    __syncthreads();
-    const int k = threadIdx.x;
-    if (k < kCl) {
-        if (!stop && S.cnt[k] > 0) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) S.cent[k][a] = __ddiv_rn((double)S.sum[k][a], (double)S.cnt[k]);
-        }
-        // the next pass starts from zero sums
-#pragma unroll
-        for (int a = 0; a < 3; ++a) S.sum[k][a] = 0;
-        S.cnt[k] = 0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) S.changed = 0;
+    if (threadIdx.x == 0 && s_changed) atomicOr(&S.changed[cur], 1u);
 }
 
 // Centroids, motion vectors and pass counts to the caller's arrays.
@@ -226,7 +232,8 @@ __global__ void k_motion(const KmState *st, double *centroids, int32_t *mv, int3
     const int t = threadIdx.x;  // cluster * 3 + axis
     if (t < kCl * 3) {
         const int k = t / 3, a = t % 3;
-        const double cr = st[0].cent[k][a], cp = st[1].cent[k][a];
+        // the centres of each frame's last pass
+        const double cr = st[0].cent[(st[0].iters + 1) & 1][k][a], cp = st[1].cent[(st[1].iters + 1) & 1][k][a];
         const int32_t m = (int32_t)round(__dsub_rn(cp, cr));
         mv_ws[t] = m;
         if (mv) mv[t] = m;
@@ -356,10 +363,8 @@ static void temporal_launch(const cga_grid *g, const K *rk, const uint32_t *rv, 
         CGA_PROF("temporal_kmeans", s);
         k_km_bbox<K><<<grid, 256, 0, s>>>(F, g->depth, linear, L.st);
         k_km_seed<<<2, 64, 0, s>>>(L.st);
-        for (int pass = 0; pass < max_iter; ++pass) {
+        for (int pass = 0; pass < max_iter; ++pass)
             k_km_assign<K><<<grid, 256, 0, s>>>(F, g->depth, linear, pass, L.st);
-            k_km_update<<<2, 64, 0, s>>>(L.st, max_iter);
-        }
         k_motion<<<1, 64, 0, s>>>(L.st, cent, mv, iters, L.mv);
     }
     if (np > 0) {
