@@ -361,8 +361,11 @@ int cga_index_stats(const void *d_index, int32_t *d_width, int64_t *d_count, cga
 /* Full-batch loss and gradient of one 1-16-1 ReLU leaf network on n samples
  * (x, t), computed by the same device code the training uses: d_params (49
  * float32: w1[16], b1[16], w2[16], b2), d_grad (49 float64), d_loss (1
- * float64).  Mean squared error, (1/n) sum (f(x_i) - t_i)^2.  Exposed so the
- * gradients can be checked against an independent fp64 computation. */
+ * float64).  Mean squared error, (1/n) sum (f(x_i) - t_i)^2.  x must ascend
+ * (as a leaf's samples do): the gradient is formed from prefix sums over each
+ * hidden unit's active run, and x that does not ascend makes every output
+ * NaN.  Exposed so the gradients can be checked against an independent fp64
+ * computation. */
 int cga_mlp_loss_grad(const float *d_params, const float *d_x, const float *d_t, int64_t n,
                       double *d_grad, double *d_loss, cga_stream stream);
 

@@ -144,38 +144,104 @@ __device__ __forceinline__ int64_t leaf_predict(const LeafHead &lh, const float 
     return f0 + ri;
 }
 
-// Sum one sample's loss and gradient into g (w1, b1, w2, b2 order); the
-// loss is accumulated unscaled as r^2 and the gradient as 2 r df/dp.
-__device__ __forceinline__ void mlp_accumulate(const float *p, float x, float t, float *g,
-                                               float &loss) {
-    float z[kMlpHidden], a[kMlpHidden];
-    float f = p[3 * kMlpHidden];
-#pragma unroll
-    for (int h = 0; h < kMlpHidden; ++h) {
-        z[h] = fmaf(p[h], x, p[kMlpHidden + h]);
-        a[h] = fmaxf(z[h], 0.0f);
-        f = fmaf(p[2 * kMlpHidden + h], a[h], f);
-    }
-    const float r = __fsub_rn(f, t);
-    loss = fmaf(r, r, loss);
-    const float dr = __fmul_rn(2.0f, r);
-#pragma unroll
-    for (int h = 0; h < kMlpHidden; ++h) {
-        g[2 * kMlpHidden + h] = fmaf(dr, a[h], g[2 * kMlpHidden + h]);
-        const float dz = z[h] > 0.0f ? __fmul_rn(dr, p[2 * kMlpHidden + h]) : 0.0f;
-        g[h] = fmaf(dz, x, g[h]);
-        g[kMlpHidden + h] = __fadd_rn(g[kMlpHidden + h], dz);
-    }
-    g[3 * kMlpHidden] = __fadd_rn(g[3 * kMlpHidden], dr);
+// Sample s of a network leaf sits at LDS slot s + s / 8, so that the lanes'
+// runs of 8 consecutive samples start in different banks.
+constexpr int kMlpSlots = kMlpBatch + kMlpBatch / 8 + 1;
+__device__ __forceinline__ int lds_pad(int s) { return s + (s >> 3); }
+
+// Inclusive wave-wide prefix sum by DPP row shifts (within rows of 16 lanes)
+// and row broadcasts (across rows); lanes without a source add zero.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_shift(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, kCtrl, kRowMask, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), kCtrl, kRowMask, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double wave_prefix_sum(double v) {
+    v += dpp_shift<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_shift<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_shift<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_shift<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_shift<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_shift<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
 }
 
-// Wave-wide sum of one float partial per lane, combined in a fixed
-// butterfly order in fp64; every lane gets the sum.
-__device__ __forceinline__ double wave_sum(float v) {
-    double x = (double)v;
+// Gradient of the summed squared error of one 1-16-1 network over m <= kMlpBatch
+// samples (sx ascending, st; slots lds_pad(s)) held in LDS, for parameter
+// c = lane (w1, b1, w2, b2 order; 0 for the padding lanes).  Hidden unit h is
+// active where fmaf(w1_h, x, b1_h) > 0; that is monotone in x, so over
+// ascending samples the active set is one contiguous run [a0, a1).  With
+// dr_s = 2 (f(x_s) - t_s) every gradient is a sum of dr_s or dr_s x_s over
+// that run:
+//   dE/dw1_h = w2_h sum dr x,  dE/db1_h = w2_h sum dr,
+//   dE/dw2_h = sum dr (w1_h x + b1_h) = w1_h sum dr x + b1_h sum dr,
+//   dE/db2 = sum dr over all samples,
+// so after one forward pass (lane L takes the consecutive samples
+// [L per, L per + per)) the wave builds the two prefix sums (fp64, in q0 /
+// q1) and each lane finds its unit's run by a binary search.  The lane also
+// returns its samples' unscaled loss, sum (f - t)^2.  One wave; the wave
+// must be converged.
+__device__ __forceinline__ double mlp_grad_sorted(const float *sp, const float *sx, const float *st,
+                                                  int m, double *q0, double *q1, int lane,
+                                                  double *loss) {
+    constexpr int kPer = kMlpBatch / 64;
+    float p[kMlpParams];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    for (int c = 0; c < kMlpParams; ++c) p[c] = sp[c];
+    const int per = (m + 63) >> 6;
+    const int s0 = lane * per < m ? lane * per : m;
+    const int cnt = s0 + per < m ? per : m - s0;
+    double pre0[kPer], pre1[kPer], r0 = 0.0, r1 = 0.0, l2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        // every lane evaluates kPer samples (independent chains the compiler
+        // can interleave); those past its run count zero
+        const int si = s0 + i < m ? s0 + i : (m > 0 ? m - 1 : 0);
+        const float x = sx[lds_pad(si)];
+        const double r = i < cnt ? (double)__fsub_rn(mlp_forward(p, x), st[lds_pad(si)]) : 0.0;
+        l2 += r * r;
+        r0 += 2.0 * r;
+        r1 += (2.0 * r) * (i < cnt ? (double)x : 0.0);
+        pre0[i] = r0;
+        pre1[i] = r1;
+    }
+    const double e0 = wave_prefix_sum(r0) - r0, e1 = wave_prefix_sum(r1) - r1;  // exclusive
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+        if (i < cnt) {
+            q0[lds_pad(s0 + i + 1)] = e0 + pre0[i];
+            q1[lds_pad(s0 + i + 1)] = e1 + pre1[i];
+        }
+    if (lane == 0) {
+        q0[0] = 0.0;
+        q1[0] = 0.0;
+    }
+    __syncthreads();
+    *loss = l2;
+    if (lane == 3 * kMlpHidden) return q0[lds_pad(m)];
+    if (lane > 3 * kMlpHidden) return 0.0;
+    const int h = lane & (kMlpHidden - 1);
+    const float w = sp[h], b = sp[kMlpHidden + h], w2 = sp[2 * kMlpHidden + h];
+    // the samples where activity differs from `up` form a prefix: inactive
+    // ones before an ascending run, active ones before a descending one
+    const bool up = w > 0.0f;
+    int lo = 0, len = m;
+    while (len > 0) {
+        const int half = len >> 1;
+        if ((fmaf(w, sx[lds_pad(lo + half)], b) > 0.0f) != up) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    const int a0 = up ? lo : 0, a1 = up ? m : lo;
+    const double S0 = q0[lds_pad(a1)] - q0[lds_pad(a0)], S1 = q1[lds_pad(a1)] - q1[lds_pad(a0)];
+    if (lane < kMlpHidden) return (double)w2 * S1;
+    if (lane < 2 * kMlpHidden) return (double)w2 * S0;
+    return (double)w * S1 + (double)b * S0;
 }
 
 // ----------------------------------------------------------------- kernels
@@ -375,15 +441,15 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_linear(const uint64_t *
 // piecewise-linear interpolant of the leaf's key -> rank map at 17 rank
 // quantiles, then train it with full-batch Adam on the mean squared error.
 // A leaf of more than kMlpBatch keys trains on kMlpBatch of them spaced
-// evenly by rank (its window is still measured over every key).  Per epoch
-// each lane accumulates the gradient of its samples; a recursive-halving
-// exchange (fixed order, so deterministic) leaves lane c with the sum for
-// parameter c, which it updates with its own Adam moments and publishes
-// through LDS.
+// evenly by rank (its window is still measured over every key).  The
+// samples ascend, so per epoch one forward pass and two prefix sums give lane
+// c the gradient for parameter c (mlp_grad_sorted), which it updates with its
+// own Adam moments and publishes through LDS.
 __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_mlp(const uint64_t *__restrict__ keys,
                                                              char *index, const int64_t *first,
                                                              uint32_t epochs, float lr) {
-    __shared__ float s_x[kMlpBatch], s_t[kMlpBatch];
+    __shared__ float s_x[kMlpSlots], s_t[kMlpSlots];
+    __shared__ double s_q0[kMlpSlots], s_q1[kMlpSlots];
     __shared__ float s_p[kMlpPad];
     __shared__ float s_kx[kMlpHidden + 1], s_kt[kMlpHidden + 1];
     IndexView v;
@@ -413,8 +479,8 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_mlp(const uint64_t *__r
     const int m = nj < kMlpBatch ? (int)nj : kMlpBatch;  // samples per epoch
     for (int i = tid; i < m; i += kLeafBlock) {
         const int64_t r = m == nj ? i : ((int64_t)i * nj) / m;  // < 2^41
-        s_x[i] = __fmul_rn((float)(keys[f0 + r] - kf), isp);
-        s_t[i] = __fdiv_rn((float)r, fnj);
+        s_x[lds_pad(i)] = __fmul_rn((float)(keys[f0 + r] - kf), isp);
+        s_t[lds_pad(i)] = __fdiv_rn((float)r, fnj);
     }
     if (tid <= kMlpHidden) {
         const int64_t r = ((int64_t)tid * (nj - 1)) / kMlpHidden;  // < 2^35
@@ -445,34 +511,18 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_mlp(const uint64_t *__r
     }
     __syncthreads();
 
-    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f, fm = (float)m;
+    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f;
+    const double dm = (double)m;
     float pw1 = 1.0f, pw2 = 1.0f;  // b1c^t, b2c^t
     float own = s_p[tid], am = 0.0f, av = 0.0f;
     for (uint32_t ep = 0; ep < epochs; ++ep) {
-        float p[kMlpParams], gv[kMlpPad];
-#pragma unroll
-        for (int c = 0; c < kMlpParams; ++c) p[c] = s_p[c];
-#pragma unroll
-        for (int c = 0; c < kMlpPad; ++c) gv[c] = 0.0f;
-        float loss = 0.0f;
-        for (int i = tid; i < m; i += kLeafBlock) mlp_accumulate(p, s_x[i], s_t[i], gv, loss);
-        // recursive halving: the partner lane tid ^ w keeps the other half;
-        // afterwards gv[0] is the sum for parameter tid
-#pragma unroll
-        for (int w = kLeafBlock / 2, half = kMlpPad / 2; w > 0; w >>= 1, half >>= 1) {
-            const bool hi = (tid & w) != 0;
-#pragma unroll
-            for (int i = 0; i < half; ++i) {
-                const float send = hi ? gv[i] : gv[i + half];
-                const float keep = hi ? gv[i + half] : gv[i];
-                gv[i] = __fadd_rn(keep, __shfl_xor(send, w, kLeafBlock));
-            }
-        }
+        double loss;
+        const double gsum = mlp_grad_sorted(s_p, s_x, s_t, m, s_q0, s_q1, tid, &loss);
         pw1 = __fmul_rn(pw1, b1c);
         pw2 = __fmul_rn(pw2, b2c);
-        __syncthreads();  // every lane has read this epoch's parameters
+        __syncthreads();  // every lane has read this epoch's parameters and sums
         if (tid < kMlpParams) {
-            const float gr = __fdiv_rn(gv[0], fm);
+            const float gr = (float)(gsum / dm);
             am = fmaf(b1c, am, __fmul_rn(1.0f - b1c, gr));
             av = fmaf(b2c, av, __fmul_rn(__fmul_rn(1.0f - b2c, gr), gr));
             const float mh = __fdiv_rn(am, 1.0f - pw1), vh = __fdiv_rn(av, 1.0f - pw2);
@@ -606,25 +656,38 @@ __global__ void k_index_stats(const char *index, int32_t *width, int64_t *count)
     }
 }
 
+// The gradient the training uses, over n ascending samples in chunks of
+// kMlpBatch (each chunk's units are active on a run of it).  Samples that do
+// not ascend make every output NaN.
 __global__ __launch_bounds__(kLeafBlock) void k_mlp_loss_grad(const float *params, const float *x,
                                                               const float *t, int64_t n,
                                                               double *grad, double *loss) {
-    float p[kMlpParams], g[kMlpParams + 1];
-    for (int c = 0; c < kMlpParams; ++c) {
-        p[c] = params[c];
-        g[c] = 0.0f;
-    }
-    g[kMlpParams] = 0.0f;
-    for (int64_t s = threadIdx.x; s < n; s += blockDim.x) mlp_accumulate(p, x[s], t[s], g, g[kMlpParams]);
-#pragma unroll
-    for (int c = 0; c <= kMlpParams; ++c) {
-        const double sum = wave_sum(g[c]);
-        if (threadIdx.x == 0) {
-            const double mean = n ? sum / (double)n : 0.0;
-            if (c < kMlpParams) grad[c] = mean;
-            else if (loss) *loss = mean;
+    __shared__ float s_x[kMlpSlots], s_t[kMlpSlots], s_p[kMlpPad];
+    __shared__ double s_q0[kMlpSlots], s_q1[kMlpSlots];
+    const int tid = threadIdx.x;
+    s_p[tid] = tid < kMlpParams ? params[tid] : 0.0f;
+    bool bad = false;
+    double g = 0.0, l2 = 0.0;
+    for (int64_t base = 0; base < n; base += kMlpBatch) {
+        const int m = n - base < kMlpBatch ? (int)(n - base) : kMlpBatch;
+        __syncthreads();  // the previous chunk is consumed
+        for (int i = tid; i < m; i += kLeafBlock) {
+            s_x[lds_pad(i)] = x[base + i];
+            s_t[lds_pad(i)] = t[base + i];
+            bad |= base + i > 0 && !(x[base + i] >= x[base + i - 1]);
         }
+        __syncthreads();
+        double l;
+        g += mlp_grad_sorted(s_p, s_x, s_t, m, s_q0, s_q1, tid, &l);
+        l2 += l;
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) l2 += __shfl_xor(l2, o, 64);
+    const double nan = __builtin_nan("");
+    const bool any_bad = __ballot(bad) != 0;
+    const double dn = n ? (double)n : 1.0;
+    if (tid < kMlpParams) grad[tid] = any_bad ? nan : g / dn;
+    if (tid == 0 && loss) *loss = any_bad ? nan : l2 / dn;
 }
 
 constexpr int kRootBlocks = 512;

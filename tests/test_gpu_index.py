@@ -114,7 +114,7 @@ def test_mlp_gradient_matches_fp64_oracle(gpu):
     rng = np.random.default_rng(3)
     for n in (1, 37, 1000, 20000):
         p = rng.normal(0, 1, 49).astype(np.float32)
-        x = rng.uniform(0, 1, n).astype(np.float32)
+        x = np.sort(rng.uniform(0, 1, n)).astype(np.float32)
         t = np.sort(rng.uniform(0, 1, n)).astype(np.float32)
         loss, g = gpu.cga_mlp_loss_grad(dev(p), dev(x), dev(t))
         wl, wg, kinks = oracle.mlp_loss_grad(p.astype(np.float64), x.astype(np.float64),
@@ -124,6 +124,30 @@ def test_mlp_gradient_matches_fp64_oracle(gpu):
         scale = max(1.0, np.abs(wg).max())
         assert np.allclose(g, wg, rtol=1e-4, atol=1e-5 * scale), (n, np.abs(g - wg).max())
         assert abs(loss - wl) <= 1e-4 * max(1.0, wl)
+
+
+def test_mlp_gradient_edges(gpu):
+    """Repeated x values, a unit active everywhere / nowhere / on a run that
+    ascends or descends, and x that does not ascend (NaN outputs)."""
+    rng = np.random.default_rng(4)
+    p = rng.normal(0, 1, 49).astype(np.float32)
+    p[0], p[16] = 0.0, 0.5    # w1 = 0, b1 > 0: active on every sample
+    p[1], p[17] = 0.0, -0.5   # w1 = 0, b1 < 0: never active
+    p[2], p[18] = -3.0, 1.505  # descending: active below x = 0.5017
+    p[3], p[19] = 2.0, -0.25  # ascending: active above x = 0.125
+    x = np.sort(np.round(rng.uniform(0, 1, 700), 2)).astype(np.float32)  # many repeats
+    t = np.sort(rng.uniform(0, 1, 700)).astype(np.float32)
+    loss, g = gpu.cga_mlp_loss_grad(dev(p), dev(x), dev(t))
+    wl, wg, kinks = oracle.mlp_loss_grad(p.astype(np.float64), x.astype(np.float64),
+                                         t.astype(np.float64))
+    assert kinks == 0
+    g = g.cpu().numpy()
+    assert np.allclose(g, wg, rtol=1e-4, atol=1e-5 * max(1.0, np.abs(wg).max()))
+    assert abs(loss - wl) <= 1e-4 * max(1.0, wl)
+    xb = x.copy()
+    xb[[10, 11]] = xb[[11, 10]] if xb[10] != xb[11] else (xb[10], xb[10] - 0.5)
+    loss, g = gpu.cga_mlp_loss_grad(dev(p), dev(xb), dev(t))
+    assert np.isnan(loss) and np.isnan(g.cpu().numpy()).all()
 
 
 def test_trained_network_gain(gpu, lidar_keys):
