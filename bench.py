@@ -302,7 +302,15 @@ def cpu_baseline(d, lookups=None):
     }
 
 
-def c5_learned_vs_binary(cga, device, reps):
+C5_VARIANTS = (("linear_leaves_4194304_pl4096", 0, 1 << 22, 4096),
+               ("linear_leaves_1048576_pl4096", 0, 1 << 20, 4096),
+               ("linear_leaves_65536_pl4096", 0, 65536, 4096),
+               ("mlp_leaves_262144_pl4096", 1, 1 << 18, 4096),
+               ("mlp_leaves_65536_pl4096", 1, 65536, 4096),
+               ("mlp_leaves_4096_pl1024", 1, 4096, 1024))
+
+
+def c5_learned_vs_binary(cga, device, reps, variants=C5_VARIANTS):
     """The 50M-key configuration: build the keys of random-walk LiDAR sweeps at
     depth 16, keep a seeded uniform subset of exactly 50M, train the index,
     then time 10M lookups (half present, half uniform in the key range) with
@@ -328,10 +336,6 @@ def c5_learned_vs_binary(cga, device, reps):
     setup_s = time.perf_counter() - t0
     out = {"keys": n, "unique_before_subset": u, "queries": len(q), "setup_s": round(setup_s, 1)}
     res = {}
-    variants = (("linear_leaves_65536_pl4096", 0, 65536, 4096),
-                ("mlp_leaves_65536_pl4096", cga.LEAF_MLP, 65536, 4096),
-                ("mlp_leaves_4096_pl1024", cga.LEAF_MLP, 4096, 1024),
-                ("mlp_leaves_4096_linear_root", cga.LEAF_MLP, 4096, 0))
     for name, kind, leaves, root in variants:
         torch.cuda.synchronize()
         a = time.perf_counter()

@@ -310,11 +310,13 @@ int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n,
  * III), whose results are always exactly those of cga_binary_lookup.
  *
  * Model (two stages, fitted to the array's own key -> rank function):
- *  root:  x = fl32(key - kmin) * inv_span (clamped to the key range) and
+ *  root:  x = fl64(key - kmin) * inv_span (clamped to the key range) and
  *         leaf = clamp(floor(y(x)), 0, n_leaves - 1) with y monotone, so
- *         that leaf j owns a contiguous rank range [first_j, first_j + n_j).
- *         root_segments = 0: y = fmaf(a, x, b), a > 0, with a, b by least
- *         squares (fp64 sums) of rank * n_leaves / n on x.
+ *         that leaf j owns a contiguous rank range [first_j, first_j + n_j);
+ *         the root computes in fp64 (a float input would send every key of
+ *         one 2^-24 step of the key range, a whole dense cluster, to one leaf).
+ *         root_segments = 0: y = fma(a, x, b), a > 0, with a, b by least
+ *         squares of rank * n_leaves / n on x.
  *         root_segments = R > 0: y is the piecewise-linear interpolant of
  *         (x, rank * n_leaves / n) through the keys at the R + 1 rank
  *         quantiles, clamped inside each segment (monotone by construction);
@@ -336,7 +338,7 @@ int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n,
  * cga_index_bytes; it records n, kmin, kmax and a key fingerprint, and a
  * lookup against a different key array reports CGA_EMISMATCH. */
 typedef struct {
-    uint32_t n_leaves;      /* 1 .. 65536 (4096 typical) */
+    uint32_t n_leaves;      /* 1 .. 2^24 (4096 .. 2^20 typical) */
     uint32_t leaf_kind;     /* 0 = linear, 1 = 1-16-1 ReLU network */
     uint32_t epochs;        /* network leaves: Adam epochs (0 = keep the initialisation) */
     float lr;               /* network leaves: Adam step size */

@@ -15,11 +15,14 @@
 namespace cga {
 
 constexpr uint32_t kIndexMagic = 0x49414743u;  // "CGAI"
-constexpr uint32_t kIndexVersion = 1;
+constexpr uint32_t kIndexVersion = 2;
 constexpr int kMlpHidden = 16;
 constexpr int kMlpParams = 3 * kMlpHidden + 1;  // w1[16], b1[16], w2[16], b2
 constexpr int kLeafBlock = 64;  // one wave per leaf
-constexpr int kLeafCache = 4096;  // leaf inputs kept in LDS (floats)
+// Leaf count limit: leaf ids are exact in the fp32 routing arithmetic up to
+// 2^24.
+constexpr uint32_t kMaxLeaves = 1u << 24;
+constexpr int kLeafCache = 1024;  // leaf inputs kept in LDS (floats)
 constexpr int kMlpBatch = 512;    // training samples per network leaf and epoch
 constexpr int kMlpPad = 64;       // gradient vector length for the halving reduction
 
@@ -27,7 +30,7 @@ struct IndexHeader {
     uint32_t magic, version, n_leaves, leaf_kind;
     int64_t n;
     uint64_t kmin, kmax;
-    float root_a, root_b, inv_span;
+    double root_a, root_b, inv_span;  // root model and input scale (fp64)
     uint32_t nparams;
     uint32_t root_segs;
     uint32_t leaf_stride;  // bytes per leaf record
@@ -45,9 +48,11 @@ struct LeafHead {
 };
 static_assert(sizeof(LeafHead) == 32, "leaf head");
 
-// One root segment: input at its start, output at its start and end, slope.
+// One root segment: input at its start, output at its start and end, slope
+// (fp64: a float input would give every key in one 2^-24 step of the key
+// range the same leaf, and the keys of a dense cluster share such steps).
 struct RootSeg {
-    float x0, y0, y1, slope;
+    double x0, y0, y1, slope;
 };
 
 __host__ __device__ inline size_t idx_align(size_t v) { return (v + 255) / 256 * 256; }
@@ -57,7 +62,7 @@ __host__ __device__ inline uint32_t leaf_stride(uint32_t nparams) {
 
 struct IndexView {
     IndexHeader *h;
-    float *rx;      // R segment start inputs (searched)
+    double *rx;     // R segment start inputs (searched)
     RootSeg *seg;   // R segments
     char *leaves;   // n_leaves records of leaf_stride bytes
     __device__ LeafHead &head(uint32_t j) const { return *(LeafHead *)(leaves + (size_t)j * h->leaf_stride); }
@@ -71,8 +76,8 @@ __host__ __device__ inline size_t index_layout(char *base, uint32_t L, uint32_t 
     size_t off = 256;
     IndexView w;
     w.h = (IndexHeader *)base;
-    w.rx = base ? (float *)(base + off) : nullptr;
-    off = idx_align(off + (size_t)R * 4);
+    w.rx = base ? (double *)(base + off) : nullptr;
+    off = idx_align(off + (size_t)R * sizeof(double));
     w.seg = base ? (RootSeg *)(base + off) : nullptr;
     off = idx_align(off + (size_t)R * sizeof(RootSeg));
     w.leaves = base ? base + off : nullptr;
@@ -83,21 +88,21 @@ __host__ __device__ inline size_t index_layout(char *base, uint32_t L, uint32_t 
 
 // ------------------------------------------------------------- model maths
 // Root input: the key's offset in the array's key range, scaled to [0, 1].
-__device__ __forceinline__ float root_x(uint64_t q, uint64_t kmin, uint64_t kmax, float isp) {
+__device__ __forceinline__ double root_x(uint64_t q, uint64_t kmin, uint64_t kmax, double isp) {
     const uint64_t c = q <= kmin ? 0ull : (q >= kmax ? kmax - kmin : q - kmin);
-    return __fmul_rn((float)c, isp);
+    return __dmul_rn((double)c, isp);
 }
 
 // Root routing; monotone in q.  A piecewise-linear root evaluates segment s
 // (the last segment whose start input is <= x) clamped to its end values,
 // so adjacent segments cannot overlap after rounding.  `rx` may point to an
 // LDS copy of the segment starts.
-__device__ __forceinline__ uint32_t route(const IndexHeader &h, const IndexView &v, const float *rx,
+__device__ __forceinline__ uint32_t route(const IndexHeader &h, const IndexView &v, const double *rx,
                                           uint64_t q) {
-    const float x = root_x(q, h.kmin, h.kmax, h.inv_span);
-    float y;
+    const double x = root_x(q, h.kmin, h.kmax, h.inv_span);
+    double y;
     if (h.root_segs == 0) {
-        y = fmaf(h.root_a, x, h.root_b);
+        y = fma(h.root_a, x, h.root_b);
     } else {
         uint32_t lo = 0, len = h.root_segs;  // last s in [0, R) with rx[s] <= x (rx[0] = 0)
         while (len > 1) {
@@ -106,12 +111,12 @@ __device__ __forceinline__ uint32_t route(const IndexHeader &h, const IndexView 
             len -= half;
         }
         const RootSeg g = v.seg[lo];
-        y = fmaf(g.slope, __fsub_rn(x, g.x0), g.y0);
+        y = fma(g.slope, __dsub_rn(x, g.x0), g.y0);
         y = y >= g.y0 ? (y <= g.y1 ? y : g.y1) : g.y0;
     }
-    y = floorf(y);
-    const float top = (float)(h.n_leaves - 1);
-    const float c = y >= 0.0f ? (y <= top ? y : top) : 0.0f;  // NaN -> 0
+    y = floor(y);
+    const double top = (double)(h.n_leaves - 1);
+    const double c = y >= 0.0 ? (y <= top ? y : top) : 0.0;  // NaN -> 0
     return (uint32_t)c;
 }
 
@@ -259,9 +264,9 @@ __global__ void k_index_header(const uint64_t *keys, int64_t n, uint32_t L, uint
     h->kmin = n > 0 ? keys[0] : 0;
     h->kmax = n > 0 ? keys[n - 1] : 0;
     const uint64_t span = h->kmax - h->kmin;
-    h->inv_span = span ? __fdiv_rn(1.0f, (float)span) : 0.0f;
-    h->root_a = (float)L;  // provisional (k_root_final overwrites)
-    h->root_b = 0.0f;
+    h->inv_span = span ? __ddiv_rn(1.0, (double)span) : 0.0;
+    h->root_a = (double)L;  // provisional (k_root_final overwrites)
+    h->root_b = 0.0;
 }
 
 // Partial least-squares sums of y = rank * L / n on x (fp64).
@@ -269,7 +274,7 @@ __global__ __launch_bounds__(256) void k_root_partial(const uint64_t *__restrict
                                                       const IndexHeader *h, double *partial) {
     __shared__ double s[4][256];
     const uint64_t kmin = h->kmin, kmax = h->kmax;
-    const float isp = h->inv_span;
+    const double isp = h->inv_span;
     const double scale = (double)h->n_leaves / (double)n;
     double sx = 0, sy = 0, sxx = 0, sxy = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -315,13 +320,12 @@ __global__ __launch_bounds__(256) void k_root_final(const double *partial, int b
     const double den = dn * sxx - sx * sx;
     double a = den != 0.0 ? (dn * sxy - sx * sy) / den : 0.0;
     double b = (sy - a * sx) / dn;
-    float af = (float)a, bf = (float)b;
-    if (!(af > 0.0f) || !isfinite(af) || !isfinite(bf)) {
-        af = (float)h->n_leaves;  // degenerate fit: split the key range evenly
-        bf = 0.0f;
+    if (!(a > 0.0) || !isfinite(a) || !isfinite(b)) {
+        a = (double)h->n_leaves;  // degenerate fit: split the key range evenly
+        b = 0.0;
     }
-    h->root_a = af;
-    h->root_b = bf;
+    h->root_a = a;
+    h->root_b = b;
 }
 
 // Piecewise-linear root: segment t runs between the keys at ranks
@@ -331,18 +335,18 @@ __global__ void k_root_knots(const uint64_t *__restrict__ keys, int64_t n, char 
     IndexView v;
     index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
     const uint32_t R = h.root_segs;
-    const float fl = (float)h.n_leaves, fn = (float)n;
+    const double fl = (double)h.n_leaves, fn = (double)n;
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < R; t += gridDim.x * blockDim.x) {
         const int64_t r0 = (int64_t)(((uint64_t)t * (uint64_t)(n - 1)) / R);
         const int64_t r1 = (int64_t)(((uint64_t)(t + 1) * (uint64_t)(n - 1)) / R);
-        const float x0 = t == 0 ? 0.0f : root_x(keys[r0], h.kmin, h.kmax, h.inv_span);
-        const float x1 = root_x(keys[r1], h.kmin, h.kmax, h.inv_span);
+        const double x0 = t == 0 ? 0.0 : root_x(keys[r0], h.kmin, h.kmax, h.inv_span);
+        const double x1 = root_x(keys[r1], h.kmin, h.kmax, h.inv_span);
         RootSeg g;
         g.x0 = x0;
-        g.y0 = __fdiv_rn(__fmul_rn((float)r0, fl), fn);
-        g.y1 = __fdiv_rn(__fmul_rn((float)r1, fl), fn);
-        const float dx = __fsub_rn(x1, x0);
-        g.slope = dx > 0.0f ? __fdiv_rn(__fsub_rn(g.y1, g.y0), dx) : 0.0f;
+        g.y0 = __ddiv_rn(__dmul_rn((double)r0, fl), fn);
+        g.y1 = __ddiv_rn(__dmul_rn((double)r1, fl), fn);
+        const double dx = __dsub_rn(x1, x0);
+        g.slope = dx > 0.0 ? __ddiv_rn(__dsub_rn(g.y1, g.y0), dx) : 0.0;
         v.seg[t] = g;
         v.rx[t] = x0;
     }
@@ -595,10 +599,10 @@ __global__ __launch_bounds__(kLookupBlock) void k_index_lookup(
     const char *__restrict__ index, const uint64_t *__restrict__ keys, int64_t n,
     const uint64_t *__restrict__ q, int64_t nq, int64_t *__restrict__ rank,
     uint8_t *__restrict__ found, unsigned long long *fallbacks, uint32_t *err) {
-    __shared__ float s_rx[kLdsSegs];
+    __shared__ double s_rx[kLdsSegs];
     const IndexHeader h = *(const IndexHeader *)index;
     const bool ok = h.magic == kIndexMagic && h.version == kIndexVersion && h.n == n &&
-                    h.n_leaves >= 1 && h.n_leaves <= 65536 && h.leaf_kind <= 1 &&
+                    h.n_leaves >= 1 && h.n_leaves <= kMaxLeaves && h.leaf_kind <= 1 &&
                     h.nparams == (h.leaf_kind ? (uint32_t)kMlpParams : 2u) &&
                     h.root_segs <= 65536 && h.leaf_stride == leaf_stride(h.nparams) &&
                     (n == 0 || (keys[0] == h.kmin && keys[n - 1] == h.kmax));
@@ -699,14 +703,14 @@ using namespace cga;
 extern "C" {
 
 size_t cga_index_bytes(const cga_index_params *p) {
-    if (!p || p->n_leaves < 1 || p->n_leaves > 65536 || p->leaf_kind > 1) return 0;
+    if (!p || p->n_leaves < 1 || p->n_leaves > kMaxLeaves || p->leaf_kind > 1) return 0;
     if (p->root_segments > 65536) return 0;
     return index_layout(nullptr, p->n_leaves, p->leaf_kind ? kMlpParams : 2, p->root_segments,
                         nullptr);
 }
 
 size_t cga_index_train_workspace_bytes(const cga_index_params *p, int64_t n) {
-    if (!p || n < 0 || p->n_leaves < 1 || p->n_leaves > 65536) return 0;
+    if (!p || n < 0 || p->n_leaves < 1 || p->n_leaves > kMaxLeaves) return 0;
     return kControlBytes + idx_align((size_t)kRootBlocks * 4 * sizeof(double)) +
            idx_align(((size_t)p->n_leaves + 1) * sizeof(int64_t));
 }

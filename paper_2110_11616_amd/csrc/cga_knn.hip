@@ -483,10 +483,20 @@ struct WideList {
     }
 };
 
+// Waves per SIMD the search is compiled for: the search is bound by the
+// latency of dependent node loads, so more waves in flight pay as long as the
+// registers still fit without spilling (packed lists up to k = 8: 96 VGPRs);
+// 1 leaves the choice to the compiler.
+template <int KT, class LIST>
+constexpr int knn_waves_per_eu() {
+    return (KT <= 8 && sizeof(typename LIST::Dist) == 4) ? 5 : 1;
+}
+
 // One query per team of kTeam lanes.  LIST is PackedList (depth <= 15) or
 // WideList.
 template <int KT, class LIST>
-__global__ __launch_bounds__(kKnnBlock) void k_knn_tree(
+__global__ __launch_bounds__(kKnnBlock) __attribute__((amdgpu_waves_per_eu(knn_waves_per_eu<KT, LIST>())))
+void k_knn_tree(
     const uint64_t *__restrict__ node, const uint32_t *__restrict__ dense,
     const int64_t *__restrict__ lvl, int64_t nodes_max, const float *__restrict__ q, int64_t nq,
     const uint64_t *__restrict__ order, float o0, float o1, float o2, float scale, uint32_t depth,

@@ -70,6 +70,33 @@ def test_key_widths_and_workspace_queries(lib):
     assert lib.cga_merge_workspace_bytes(ctypes.byref(grid(12)), 10, 10) >= 256
 
 
+class IndexParams(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_uint32), ("leaf_kind", ctypes.c_uint32),
+                ("epochs", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("root_segments", ctypes.c_uint32)]
+
+
+def test_index_size_limits(lib):
+    """Leaf counts 1 .. 2^24 and root segments 0 .. 65536 are accepted; the
+    index grows by one 64-byte record per linear leaf and one 256-byte
+    record per network leaf."""
+    lib.cga_index_bytes.restype = ctypes.c_size_t
+    lib.cga_index_train_workspace_bytes.restype = ctypes.c_size_t
+    lib.cga_index_train_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    nb = lambda *a: lib.cga_index_bytes(ctypes.byref(IndexParams(*a)))
+    for leaves in (1, 4096, 65536, 65537, 1 << 20, 1 << 24):
+        for kind, rec in ((0, 64), (1, 256)):
+            assert nb(leaves, kind, 50, 1e-4, 4096) >= leaves * rec
+    assert nb(1 << 20, 0, 0, 0.0, 0) - nb(1 << 19, 0, 0, 0.0, 0) == (1 << 19) * 64
+    for bad in ((0, 0, 0, 0.0, 0), ((1 << 24) + 1, 0, 0, 0.0, 0), (16, 2, 0, 0.0, 0),
+                (16, 0, 0, 0.0, 65537)):
+        assert nb(*bad) == 0
+    ws = lambda leaves, n: lib.cga_index_train_workspace_bytes(
+        ctypes.byref(IndexParams(leaves, 0, 0, 0.0, 0)), n)
+    assert ws(1 << 24, 10) > ws(4096, 10) > 0
+    assert ws((1 << 24) + 1, 10) == 0 and ws(16, -1) == 0
+
+
 def test_host_validation_before_any_launch(lib):
     P, I64 = ctypes.c_void_p, ctypes.c_int64
     lib.cga_build.argtypes = [P, P, I64, P, P, I64, P, P, P, ctypes.c_size_t, P, P]
