@@ -302,7 +302,8 @@ def cpu_baseline(d, lookups=None):
     }
 
 
-C5_VARIANTS = (("linear_leaves_4194304_pl4096", 0, 1 << 22, 4096),
+C5_VARIANTS = (("linear_leaves_16777216_pl4096", 0, 1 << 24, 4096),
+               ("linear_leaves_4194304_pl4096", 0, 1 << 22, 4096),
                ("linear_leaves_1048576_pl4096", 0, 1 << 20, 4096),
                ("linear_leaves_65536_pl4096", 0, 65536, 4096),
                ("mlp_leaves_262144_pl4096", 1, 1 << 18, 4096),

@@ -95,20 +95,31 @@ __device__ __forceinline__ double root_x(uint64_t q, uint64_t kmin, uint64_t kma
 
 // Root routing; monotone in q.  A piecewise-linear root evaluates segment s
 // (the last segment whose start input is <= x) clamped to its end values,
-// so adjacent segments cannot overlap after rounding.  `rx` may point to an
-// LDS copy of the segment starts.
+// so adjacent segments cannot overlap after rounding.  The segment search
+// runs over `rx`, every `stride`-th segment start (`nrx` of them, possibly an
+// LDS copy), then over the at most `stride` starts of that block in the
+// index; stride 1 searches the index's starts alone.
 __device__ __forceinline__ uint32_t route(const IndexHeader &h, const IndexView &v, const double *rx,
-                                          uint64_t q) {
+                                          uint32_t stride, uint32_t nrx, uint64_t q) {
     const double x = root_x(q, h.kmin, h.kmax, h.inv_span);
     double y;
     if (h.root_segs == 0) {
         y = fma(h.root_a, x, h.root_b);
     } else {
-        uint32_t lo = 0, len = h.root_segs;  // last s in [0, R) with rx[s] <= x (rx[0] = 0)
+        uint32_t lo = 0, len = nrx;  // last i with rx[i] <= x (rx[0] = 0)
         while (len > 1) {
             const uint32_t half = len >> 1;
             lo = rx[lo + half] <= x ? lo + half : lo;
             len -= half;
+        }
+        if (stride > 1) {
+            lo *= stride;
+            len = h.root_segs - lo < stride ? h.root_segs - lo : stride;
+            while (len > 1) {
+                const uint32_t half = len >> 1;
+                lo = v.rx[lo + half] <= x ? lo + half : lo;
+                len -= half;
+            }
         }
         const RootSeg g = v.seg[lo];
         y = fma(g.slope, __dsub_rn(x, g.x0), g.y0);
@@ -361,8 +372,8 @@ __global__ __launch_bounds__(256) void k_leaf_bounds(const uint64_t *__restrict_
     const uint32_t L = h.n_leaves;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t lj = route(h, v, v.rx, keys[i]);
-        const int64_t lp = i > 0 ? (int64_t)route(h, v, v.rx, keys[i - 1]) : -1;
+        const int64_t lj = route(h, v, v.rx, 1, h.root_segs, keys[i]);
+        const int64_t lp = i > 0 ? (int64_t)route(h, v, v.rx, 1, h.root_segs, keys[i - 1]) : -1;
         for (int64_t j = lp + 1; j <= lj; ++j) first[j] = i;
         if (i == n - 1)
             for (int64_t j = lj + 1; j <= (int64_t)L; ++j) first[j] = n;
@@ -555,7 +566,7 @@ __global__ __launch_bounds__(256) void k_leaf_err(const uint64_t *__restrict__ k
         int32_t ec = 0;
         if (valid) {
             const uint64_t q = keys[i];
-            j = route(h, v, v.rx, q);
+            j = route(h, v, v.rx, 1, h.root_segs, q);
             int64_t f0, f1;
             const int64_t e = i - leaf_predict(v.head(j), v.params(j), h.leaf_kind, q, n, &f0, &f1);
             ec = (int32_t)(e > 0x3FFFFFFF ? 0x3FFFFFFF : (e < -0x3FFFFFFF ? -0x3FFFFFFF : e));
@@ -608,9 +619,11 @@ __global__ __launch_bounds__(kLookupBlock) void k_index_lookup(
                     (n == 0 || (keys[0] == h.kmin && keys[n - 1] == h.kmax));
     IndexView v;
     index_layout((char *)index, h.n_leaves, h.nparams, h.root_segs, &v);
-    const bool lds = ok && h.root_segs > 0 && h.root_segs <= kLdsSegs;
-    if (lds)
-        for (uint32_t i = threadIdx.x; i < h.root_segs; i += blockDim.x) s_rx[i] = v.rx[i];
+    // every stride-th segment start, at most kLdsSegs of them, staged in LDS
+    const uint32_t R = ok ? h.root_segs : 0;
+    const uint32_t stride = R > kLdsSegs ? (R + kLdsSegs - 1) / kLdsSegs : 1;
+    const uint32_t nrx = (R + stride - 1) / stride;
+    for (uint32_t i = threadIdx.x; i < nrx; i += blockDim.x) s_rx[i] = v.rx[(size_t)i * stride];
     __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nq) return;
@@ -624,7 +637,7 @@ __global__ __launch_bounds__(kLookupBlock) void k_index_lookup(
     int64_t r = 0;
     bool fell = false;
     if (n > 0) {
-        const uint32_t j = route(h, v, lds ? s_rx : v.rx, x);
+        const uint32_t j = route(h, v, s_rx, stride, nrx, x);
         const LeafHead lh = v.head(j);
         int64_t f0, f1;
         const int64_t p = leaf_predict(lh, v.params(j), h.leaf_kind, x, n, &f0, &f1);

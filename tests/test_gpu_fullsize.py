@@ -235,7 +235,7 @@ def test_c5_full(gpu):
     dev = torch.device("cuda:0")
     kd = torch.from_numpy(keys.view(np.int64)).to(dev)
     qd = torch.from_numpy(q.view(np.int64)).to(dev)
-    for kind, leaves, root in ((0, 65536, 4096), (cga.LEAF_MLP, 65536, 4096), (0, 1 << 22, 4096),
+    for kind, leaves, root in ((0, 65536, 4096), (cga.LEAF_MLP, 65536, 4096), (0, 1 << 24, 4096),
                                (cga.LEAF_MLP, 1 << 18, 4096)):
         idx = cga.cga_index_train(kd, n_leaves=leaves, leaf_kind=kind, root_segments=root)
         r, f, _ = cga.cga_index_lookup(idx, kd, qd)

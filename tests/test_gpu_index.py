@@ -44,7 +44,8 @@ def _t(a):
 @pytest.mark.parametrize("kind,leaves,root", [(0, 4096, 0), (1, 4096, 0), (0, 4096, 1024),
                                               (1, 4096, 1024), (1, 1, 0), (0, 7, 3), (1, 65536, 64),
                                               (1, 4096, 65536), (0, 1 << 20, 4096),
-                                              (0, 1 << 24, 65536), (1, 1 << 18, 4096)])
+                                              (0, 1 << 24, 65536), (1, 1 << 18, 4096),
+                                              (0, 1 << 16, 4097), (0, 1 << 16, 5000)])
 def test_lookup_exact(gpu, lidar_keys, kind, leaves, root):
     keys = lidar_keys
     q = _queries(keys, 200_000, 7 + kind)
