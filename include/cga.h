@@ -76,7 +76,7 @@ typedef struct {
 } cga_grid;
 
 /* Optional launch tuning (NULL = built-in or autotuned defaults).  Never
- * changes results.  radix_bits in [4, 11]; tile_items in {8, 12, 16}. */
+ * changes results.  radix_bits in [4, 11]; tile_items in {8, 12, 16, 24, 32}. */
 typedef struct {
     uint32_t radix_bits;
     uint32_t tile_items;

@@ -462,7 +462,7 @@ size_t cga_batch_workspace_bytes(const cga_grid *g, int nframes, int64_t n) {
     if (!grid_valid(g) || nframes < 1 || n < 0) return 0;
     size_t m = 0;
     for (int rb = 4; rb <= 11; ++rb)
-        for (int items : {8, 12, 16}) {
+        for (int items : kSortItems) {
             SortCfg c;
             c.radix_bits = rb;
             c.items = items;
@@ -542,7 +542,7 @@ size_t cga_autotune_workspace_bytes(uint32_t key_bytes, int64_t n) {
     if ((key_bytes != 4 && key_bytes != 8) || n < 0) return 0;
     size_t m = 0;
     for (int rb = 4; rb <= 11; ++rb)
-        for (int items : {8, 12, 16}) {
+        for (int items : kSortItems) {
             SortCfg c;
             c.radix_bits = rb;
             c.items = items;
@@ -572,7 +572,7 @@ int cga_autotune_sort(const void *d_keys, uint32_t key_bytes, uint32_t key_bits,
     float best_t = 1e30f;
     int status = CGA_OK;
     for (int rb = 4; rb <= 11 && status == CGA_OK; ++rb)
-        for (int items : {8, 12, 16}) {
+        for (int items : kSortItems) {
             SortCfg c;
             c.radix_bits = rb;
             c.items = items;

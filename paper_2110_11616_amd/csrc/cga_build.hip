@@ -206,7 +206,7 @@ template <typename F>
 static size_t max_over_cfgs(F layout_bytes) {
     size_t m = 0;
     for (int rb = 4; rb <= 11; ++rb)
-        for (int items : {8, 12, 16}) {
+        for (int items : kSortItems) {
             SortCfg c;
             c.radix_bits = rb;
             c.items = items;

@@ -114,7 +114,7 @@ size_t cga_project_workspace_bytes(const cga_grid *g, int64_t n) {
     if (!grid_valid(g) || n < 0) return 0;
     size_t m = 0;
     for (int rb = 4; rb <= 11; ++rb)
-        for (int items : {8, 12, 16}) {
+        for (int items : kSortItems) {
             SortCfg c;
             c.radix_bits = rb;
             c.items = items;

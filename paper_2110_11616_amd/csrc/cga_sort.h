@@ -265,10 +265,15 @@ inline size_t sort_zero_bytes(const SortWs &w) {
     return (size_t)((char *)w.look[1] - (char *)w.hist);
 }
 
+// Items per thread compiled into this library (tiles of 256 x items keys):
+// larger tiles write longer runs per bucket and need fewer look-backs, which
+// pays on large arrays; smaller ones keep more tiles in flight on small ones.
+constexpr int kSortItems[] = {8, 12, 16, 24, 32};
+
 // Digit widths and tile sizes compiled into this library.
 inline bool sort_cfg_supported(const SortCfg &c) {
     return (c.radix_bits >= 4 && c.radix_bits <= 11) &&
-           (c.items == 8 || c.items == 12 || c.items == 16);
+           (c.items == 8 || c.items == 12 || c.items == 16 || c.items == 24 || c.items == 32);
 }
 
 // Autotuned configuration recorded for (key bytes, key bits, n), if any.
@@ -292,6 +297,8 @@ inline void onesweep_items(const SortWs &w, const K *src, K *dst, int64_t n_host
     switch (w.items) {
         case 8: onesweep_launch<K, RB, 8>(w, src, dst, n_host, d_n, pass, tile_ctr, s); break;
         case 12: onesweep_launch<K, RB, 12>(w, src, dst, n_host, d_n, pass, tile_ctr, s); break;
+        case 24: onesweep_launch<K, RB, 24>(w, src, dst, n_host, d_n, pass, tile_ctr, s); break;
+        case 32: onesweep_launch<K, RB, 32>(w, src, dst, n_host, d_n, pass, tile_ctr, s); break;
         default: onesweep_launch<K, RB, 16>(w, src, dst, n_host, d_n, pass, tile_ctr, s); break;
     }
 }

@@ -110,7 +110,7 @@ def test_autotuner_choice_is_used_and_exact(gpu, frames):
     g = frames["grid"]
     rb, items, ms = gpu.cga_autotune_sort(key_bytes=8, key_bits=3 * g.depth, n=len(frames["xyz"]))
     say("autotune", rb, items, ms)
-    assert 4 <= rb <= 11 and items in (8, 12, 16) and ms > 0
+    assert 4 <= rb <= 11 and items in (8, 12, 16, 24, 32) and ms > 0
     k, c = gpu.cga_build(dev(frames["xyz"]), g)  # picks the recorded choice
     wk, wc = oracle.build(frames["xyz"], g)
     assert np.array_equal(u64(k), wk) and np.array_equal(u32(c), wc)

@@ -84,7 +84,7 @@ def test_sort(gpu, n, depth, bits):
 
 
 @pytest.mark.parametrize("rb", [4, 5, 6, 7, 8, 9, 10, 11])
-@pytest.mark.parametrize("items", [8, 12, 16])
+@pytest.mark.parametrize("items", [8, 12, 16, 24, 32])
 def test_sort_every_tuning(gpu, rb, items):
     rng = np.random.default_rng(rb * 100 + items)
     keys = rng.integers(0, 2 ** 44, 70_001, dtype=np.uint64)
