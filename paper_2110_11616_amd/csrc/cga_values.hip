@@ -34,6 +34,13 @@ __device__ __forceinline__ uint32_t round_half_up(uint64_t sum, uint64_t count) 
 }
 
 // acc: 5 words per voxel -- four channel sums, then the point count.
+// Consecutive points often share a voxel (a scan line, a dense surface), so
+// each wave first sums the runs of equal voxels among its 64 points: the
+// point's channels and a count are packed into one word (14 bits per
+// channel sum, 64 * 255 < 2^14; the count from bit 56), a wave prefix sum of
+// the packed words gives every run's total as a difference, and the last
+// lane of a run adds it with at most five atomics.  The sums are integers,
+// so the result does not depend on how the points are grouped.
 template <typename K>
 __global__ __launch_bounds__(256) void k_values_accum(const float *__restrict__ xyz, int64_t n,
                                                       const uint32_t *__restrict__ attr, float o0,
@@ -44,24 +51,52 @@ __global__ __launch_bounds__(256) void k_values_accum(const float *__restrict__ 
                                                       uint32_t *err) {
     const int64_t u = dev_count(u_host, d_u) < u_host ? dev_count(u_host, d_u) : u_host;
     const float o[3] = {o0, o1, o2};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        Vox v;
-        if (!quantize3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], o, scale, depth, v)) {
-            set_err(err, ERR_NONFINITE);
-            continue;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < n; i0 += stride) {
+        const int64_t i = i0 + lane;  // i0 is wave-uniform
+        int64_t j = -1;
+        uint64_t pv = 0;
+        if (i < n) {
+            Vox v;
+            if (!quantize3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], o, scale, depth, v)) {
+                set_err(err, ERR_NONFINITE);
+            } else {
+                const uint64_t key = enc3(v.x, v.y, v.z, depth, linear);
+                const int64_t f = lower_bound_keys(keys, u, key);
+                if (f >= u || (uint64_t)keys[f] != key) {
+                    set_err(err, ERR_MISMATCH);
+                } else {
+                    const uint32_t a = attr[i];
+                    j = f;
+                    pv = (uint64_t)(a & 0xFFu) | ((uint64_t)((a >> 8) & 0xFFu) << 14) |
+                         ((uint64_t)((a >> 16) & 0xFFu) << 28) | ((uint64_t)(a >> 24) << 42) |
+                         (1ull << 56);
+                }
+            }
         }
-        const uint64_t key = enc3(v.x, v.y, v.z, depth, linear);
-        const int64_t j = lower_bound_keys(keys, u, key);
-        if (j >= u || (uint64_t)keys[j] != key) {
-            set_err(err, ERR_MISMATCH);
-            continue;
-        }
-        const uint32_t a = attr[i];
-        unsigned long long *p = acc + 5 * j;
+        const int64_t jp = __shfl_up(j, 1, 64);
+        const uint64_t heads = __ballot(lane == 0 || j != jp);
+        uint64_t p = pv;  // inclusive prefix sum over the wave
 #pragma unroll
-        for (int c = 0; c < 4; ++c) atomicAdd(p + c, (unsigned long long)((a >> (8 * c)) & 0xFFu));
-        atomicAdd(p + 4, 1ull);
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t t = __shfl_up(p, d, 64);
+            if (lane >= d) p += t;
+        }
+        const uint64_t upto = lane == 63 ? heads : heads & ((2ull << lane) - 1);
+        const int start = 63 - __clzll(upto);  // first lane of this lane's run
+        const uint64_t before = __shfl(p, start > 0 ? start - 1 : 0, 64);
+        const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+        if (tail && j >= 0) {
+            const uint64_t sum = p - (start > 0 ? before : 0ull);
+            unsigned long long *q = acc + 5 * j;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const unsigned long long w = (sum >> (14 * c)) & 0x3FFFu;
+                if (w) atomicAdd(q + c, w);
+            }
+            atomicAdd(q + 4, (unsigned long long)(sum >> 56));
+        }
     }
 }
 

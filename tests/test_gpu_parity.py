@@ -533,6 +533,25 @@ def test_values_edges(gpu, w_c1):
     assert e.value.status == gpu.EINVAL
 
 
+def test_values_runs(gpu, w_c1):
+    """Runs of equal voxels among consecutive points: one voxel for a whole
+    wave and longer (all-255 channels, the largest per-wave sums), runs that
+    cross wave boundaries, runs of every length 1..70, and a ragged tail."""
+    g = w_c1["grid"]
+    rng = np.random.default_rng(515)
+    centres = rng.uniform(0.05, 0.95, (400, 3)).astype(np.float32)
+    lens = np.concatenate([[200, 64, 63, 65, 1], rng.integers(1, 71, 395)])
+    pts = np.repeat(centres, lens, axis=0)
+    attr = rng.integers(0, 2 ** 32, len(pts), dtype=np.uint64).astype(np.uint32)
+    attr[:200] = 0xFFFFFFFF
+    for cut in (len(pts), len(pts) - 37):
+        p, a = pts[:cut], attr[:cut]
+        k, _ = gpu.cga_build(dev(p), g)
+        v = gpu.cga_voxel_values(dev(p), dev(a.view(np.int32)), k, g)
+        want_k, want_v = oracle.voxel_values(p, a, g)
+        assert np.array_equal(u64(k), want_k) and _u32(v).tolist() == want_v.tolist()
+
+
 def test_knn_linear_unsupported(gpu, w_c1):
     g = w_c1["grid"].with_mode(L)
     k, _ = gpu.cga_build(dev(w_c1["a"]), g)
