@@ -1,6 +1,6 @@
 // The paper's own operations on the five coordinate arrays of a LINEAR CGA
 // (X_index, X_pointer, Y_index, Y_pointer, Z_index; Section V), one thread
-// per query:
+// per lookup and a team of lanes per nearest-neighbour query:
 //
 // * point lookup, Section V-A: the query's x is searched in X_index, its
 //   X_pointer entries bound the run of Y_index holding that x's y values,
@@ -123,19 +123,36 @@ __global__ __launch_bounds__(256) void k_arrays_lookup(Arrays A, const uint32_t 
     }
 }
 
-__global__ __launch_bounds__(256) void k_arrays_nn(Arrays A, const float *__restrict__ q, int64_t nq,
-                                                   float o0, float o1, float o2, float scale,
-                                                   uint32_t depth, int64_t *__restrict__ idx,
-                                                   uint64_t *__restrict__ d2) {
+// Nearest neighbour, a team of kNnTeam lanes per query.  Every lane finds
+// the same first point; then lane t walks the x entries a0 + t, a0 + t +
+// kNnTeam, ... of the box, keeping its own best and pruning against the
+// smallest distance found so far by any lane of the team (an LDS word).  A
+// pruned point is strictly farther than a point already found, so every
+// point at the final distance is still examined, and the lexicographic
+// minimum of (squared distance, position) over the lanes is the answer of
+// the one-lane walk.
+constexpr int kNnTeam = 8;
+constexpr int kNnBlock = 256;
+
+__global__ __launch_bounds__(kNnBlock) void k_arrays_nn(Arrays A, const float *__restrict__ q,
+                                                        int64_t nq, float o0, float o1, float o2,
+                                                        float scale, uint32_t depth,
+                                                        int64_t *__restrict__ idx,
+                                                        uint64_t *__restrict__ d2) {
+    __shared__ unsigned long long s_bd[kNnBlock / kNnTeam];
     A.resolve();
     const float o[3] = {o0, o1, o2};
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nq;
-         j += (int64_t)gridDim.x * blockDim.x) {
+    const int team = threadIdx.x / kNnTeam, tl = threadIdx.x % kNnTeam;
+    const int64_t teams = (int64_t)gridDim.x * (kNnBlock / kNnTeam);
+    // j is the same for the kNnTeam lanes of a team, so the team stays together
+    for (int64_t j = (int64_t)blockIdx.x * (kNnBlock / kNnTeam) + team; j < nq; j += teams) {
         Vox v;
         if (!quantize3(q[3 * j], q[3 * j + 1], q[3 * j + 2], o, scale, depth, v)) {
-            set_err(A.err, ERR_NONFINITE);
-            idx[j] = -1;
-            d2[j] = ~0ull;
+            if (tl == 0) {
+                set_err(A.err, ERR_NONFINITE);
+                idx[j] = -1;
+                d2[j] = ~0ull;
+            }
             continue;
         }
         int64_t best = -1;
@@ -156,22 +173,26 @@ __global__ __launch_bounds__(256) void k_arrays_nn(Arrays A, const float *__rest
             }
         }
         if (best >= 0 && bd > 0) {
-            // the box |coordinate - query| <= epsilon, narrowed as bd falls
+            s_bd[team] = bd;  // every lane stores the same value
+            // the box |coordinate - query| <= epsilon, narrowed as the team's bound falls
             const uint32_t e = isqrt_u64(bd);
-            for (int64_t a = run_lower(A.xi, 0, A.nx, v.x > e ? v.x - e : 0); a < A.nx; ++a) {
+            const int64_t a0 = run_lower(A.xi, 0, A.nx, v.x > e ? v.x - e : 0);
+            for (int64_t a = a0 + tl; a < A.nx; a += kNnTeam) {
+                uint64_t B = __hip_atomic_load(&s_bd[team], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                B = bd < B ? bd : B;
                 const uint32_t x = A.xi[a];
                 const uint64_t dx2 = sq_gap(x, v.x);
-                if (dx2 > bd) {
+                if (dx2 > B) {
                     if (x > v.x) break;
                     continue;
                 }
                 int64_t b0, b1;
                 A.y_run(a, b0, b1);
-                const uint32_t ey = isqrt_u64(bd - dx2);
+                const uint32_t ey = isqrt_u64(B - dx2);
                 for (int64_t b = run_lower(A.yi, b0, b1, v.y > ey ? v.y - ey : 0); b < b1; ++b) {
                     const uint32_t y = A.yi[b];
                     const uint64_t dxy = dx2 + sq_gap(y, v.y);
-                    if (dxy > bd) {
+                    if (dxy > B) {
                         if (y > v.y) break;
                         continue;
                     }
@@ -192,11 +213,27 @@ __global__ __launch_bounds__(256) void k_arrays_nn(Arrays A, const float *__rest
                             best = p;
                         }
                     }
+                    if (bd < B) {
+                        B = bd;
+                        atomicMin(&s_bd[team], (unsigned long long)bd);
+                    }
                 }
             }
         }
-        idx[j] = best;
-        d2[j] = bd;
+        // lexicographic minimum of (bd, best) over the team
+#pragma unroll
+        for (int m = 1; m < kNnTeam; m <<= 1) {
+            const uint64_t ob = __shfl_xor(bd, m, kNnTeam);
+            const int64_t op = __shfl_xor(best, m, kNnTeam);
+            if (ob < bd || (ob == bd && op < best)) {
+                bd = ob;
+                best = op;
+            }
+        }
+        if (tl == 0) {
+            idx[j] = best;
+            d2[j] = bd;
+        }
     }
 }
 
@@ -262,8 +299,8 @@ int cga_arrays_nn(const cga_grid *g, const uint32_t *d_x_index, int64_t n_x, con
         CGA_PROF("arrays_nn", s);
         const Arrays A{d_x_index, d_x_ptr, d_y_index, d_y_ptr, d_z_index, n_x, n_xy, n,
                        d_n_x, d_n_xy, &ctl->err};
-        k_arrays_nn<<<arrays_grid(nq), 256, 0, s>>>(A, d_q, nq, g->origin[0], g->origin[1],
-                                                    g->origin[2], g->scale, g->depth, d_idx, d_d2);
+        k_arrays_nn<<<arrays_grid(nq * kNnTeam), kNnBlock, 0, s>>>(
+            A, d_q, nq, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth, d_idx, d_d2);
     }
     CGA_HIP(hipGetLastError());
     return CGA_OK;
