@@ -160,10 +160,10 @@ __device__ __forceinline__ int64_t leaf_predict(const LeafHead &lh, const float 
     return f0 + ri;
 }
 
-// Sample s of a network leaf sits at LDS slot s + s / 8, so that the lanes'
-// runs of 8 consecutive samples start in different banks.
-constexpr int kMlpSlots = kMlpBatch + kMlpBatch / 8 + 1;
-__device__ __forceinline__ int lds_pad(int s) { return s + (s >> 3); }
+// Sample s of a network leaf sits at LDS slot s + s / 16, so that the lanes'
+// runs of up to 8 consecutive samples mostly start in different banks.
+constexpr int kMlpSlots = kMlpBatch + kMlpBatch / 16 + 1;
+__device__ __forceinline__ int lds_pad(int s) { return s + (s >> 4); }
 
 // Inclusive wave-wide prefix sum by DPP row shifts (within rows of 16 lanes)
 // and row broadcasts (across rows); lanes without a source add zero.
@@ -195,13 +195,16 @@ __device__ __forceinline__ double wave_prefix_sum(double v) {
 //   dE/dw2_h = sum dr (w1_h x + b1_h) = w1_h sum dr x + b1_h sum dr,
 //   dE/db2 = sum dr over all samples,
 // so after one forward pass (lane L takes the consecutive samples
-// [L per, L per + per)) the wave builds the two prefix sums (fp64, in q0 /
-// q1) and each lane finds its unit's run by a binary search.  The lane also
-// returns its samples' unscaled loss, sum (f - t)^2.  One wave; the wave
-// must be converged.
+// [L per, L per + per)) the wave builds the two prefix sums and each lane
+// finds its unit's run by a binary search.  A prefix sum up to sample s is
+// the fp64 total of the lanes before s's lane (e0 / e1, one per lane) plus
+// the fp32 running sum of at most 8 terms inside that lane (l0 / l1, one per
+// sample), which keeps the LDS of a leaf small enough for four waves per
+// SIMD.  The lane also returns its samples' unscaled loss, sum (f - t)^2.
+// One wave; the wave must be converged.
 __device__ __forceinline__ double mlp_grad_sorted(const float *sp, const float *sx, const float *st,
-                                                  int m, double *q0, double *q1, int lane,
-                                                  double *loss) {
+                                                  int m, float *l0, float *l1, double *e0s,
+                                                  double *e1s, int lane, double *loss) {
     constexpr int kPer = kMlpBatch / 64;
     float p[kMlpParams];
 #pragma unroll
@@ -223,20 +226,31 @@ __device__ __forceinline__ double mlp_grad_sorted(const float *sp, const float *
         pre0[i] = r0;
         pre1[i] = r1;
     }
-    const double e0 = wave_prefix_sum(r0) - r0, e1 = wave_prefix_sum(r1) - r1;  // exclusive
+    e0s[lane] = wave_prefix_sum(r0) - r0;  // exclusive
+    e1s[lane] = wave_prefix_sum(r1) - r1;
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
         if (i < cnt) {
-            q0[lds_pad(s0 + i + 1)] = e0 + pre0[i];
-            q1[lds_pad(s0 + i + 1)] = e1 + pre1[i];
+            l0[lds_pad(s0 + i)] = (float)pre0[i];
+            l1[lds_pad(s0 + i)] = (float)pre1[i];
         }
-    if (lane == 0) {
-        q0[0] = 0.0;
-        q1[0] = 0.0;
-    }
     __syncthreads();
     *loss = l2;
-    if (lane == 3 * kMlpHidden) return q0[lds_pad(m)];
+    // sums of dr and dr x over the samples before a (0 <= a <= m)
+    auto prefix = [&](int a, double &p0, double &p1) {
+        if (a == 0) {
+            p0 = p1 = 0.0;
+            return;
+        }
+        const int sl = a - 1, L = sl / per;
+        p0 = e0s[L] + (double)l0[lds_pad(sl)];
+        p1 = e1s[L] + (double)l1[lds_pad(sl)];
+    };
+    if (lane == 3 * kMlpHidden) {
+        double t0, t1;
+        prefix(m, t0, t1);
+        return t0;
+    }
     if (lane > 3 * kMlpHidden) return 0.0;
     const int h = lane & (kMlpHidden - 1);
     const float w = sp[h], b = sp[kMlpHidden + h], w2 = sp[2 * kMlpHidden + h];
@@ -254,7 +268,10 @@ __device__ __forceinline__ double mlp_grad_sorted(const float *sp, const float *
         }
     }
     const int a0 = up ? lo : 0, a1 = up ? m : lo;
-    const double S0 = q0[lds_pad(a1)] - q0[lds_pad(a0)], S1 = q1[lds_pad(a1)] - q1[lds_pad(a0)];
+    double p00, p01, p10, p11;
+    prefix(a0, p00, p01);
+    prefix(a1, p10, p11);
+    const double S0 = p10 - p00, S1 = p11 - p01;
     if (lane < kMlpHidden) return (double)w2 * S1;
     if (lane < 2 * kMlpHidden) return (double)w2 * S0;
     return (double)w * S1 + (double)b * S0;
@@ -463,10 +480,10 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_linear(const uint64_t *
 __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_mlp(const uint64_t *__restrict__ keys,
                                                              char *index, const int64_t *first,
                                                              uint32_t epochs, float lr) {
-    __shared__ float s_x[kMlpSlots], s_t[kMlpSlots];
-    __shared__ double s_q0[kMlpSlots], s_q1[kMlpSlots];
+    __shared__ float s_x[kMlpSlots], s_t[kMlpSlots], s_l0[kMlpSlots], s_l1[kMlpSlots];
+    __shared__ double s_e0[64], s_e1[64];
     __shared__ float s_p[kMlpPad];
-    __shared__ float s_kx[kMlpHidden + 1], s_kt[kMlpHidden + 1];
+    float *const s_kx = s_l0, *const s_kt = s_l1;  // initial knots, before the first epoch
     IndexView v;
     const IndexHeader &h = *(const IndexHeader *)index;
     index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
@@ -532,7 +549,7 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_mlp(const uint64_t *__r
     float own = s_p[tid], am = 0.0f, av = 0.0f;
     for (uint32_t ep = 0; ep < epochs; ++ep) {
         double loss;
-        const double gsum = mlp_grad_sorted(s_p, s_x, s_t, m, s_q0, s_q1, tid, &loss);
+        const double gsum = mlp_grad_sorted(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, &loss);
         pw1 = __fmul_rn(pw1, b1c);
         pw2 = __fmul_rn(pw2, b2c);
         __syncthreads();  // every lane has read this epoch's parameters and sums
@@ -679,8 +696,8 @@ __global__ void k_index_stats(const char *index, int32_t *width, int64_t *count)
 __global__ __launch_bounds__(kLeafBlock) void k_mlp_loss_grad(const float *params, const float *x,
                                                               const float *t, int64_t n,
                                                               double *grad, double *loss) {
-    __shared__ float s_x[kMlpSlots], s_t[kMlpSlots], s_p[kMlpPad];
-    __shared__ double s_q0[kMlpSlots], s_q1[kMlpSlots];
+    __shared__ float s_x[kMlpSlots], s_t[kMlpSlots], s_l0[kMlpSlots], s_l1[kMlpSlots], s_p[kMlpPad];
+    __shared__ double s_e0[64], s_e1[64];
     const int tid = threadIdx.x;
     s_p[tid] = tid < kMlpParams ? params[tid] : 0.0f;
     bool bad = false;
@@ -695,7 +712,7 @@ __global__ __launch_bounds__(kLeafBlock) void k_mlp_loss_grad(const float *param
         }
         __syncthreads();
         double l;
-        g += mlp_grad_sorted(s_p, s_x, s_t, m, s_q0, s_q1, tid, &l);
+        g += mlp_grad_sorted(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, &l);
         l2 += l;
     }
 #pragma unroll
