@@ -201,11 +201,12 @@ __device__ __forceinline__ double wave_prefix_sum(double v) {
 // the fp32 running sum of at most 8 terms inside that lane (l0 / l1, one per
 // sample), which keeps the LDS of a leaf small enough for four waves per
 // SIMD.  The lane also returns its samples' unscaled loss, sum (f - t)^2.
-// One wave; the wave must be converged.
+// One wave; the wave must be converged.  kPer >= per: the samples a lane
+// evaluates (those past its run count zero).
+template <int kPer>
 __device__ __forceinline__ double mlp_grad_sorted(const float *sp, const float *sx, const float *st,
                                                   int m, float *l0, float *l1, double *e0s,
                                                   double *e1s, int lane, double *loss) {
-    constexpr int kPer = kMlpBatch / 64;
     float p[kMlpParams];
 #pragma unroll
     for (int c = 0; c < kMlpParams; ++c) p[c] = sp[c];
@@ -275,6 +276,16 @@ __device__ __forceinline__ double mlp_grad_sorted(const float *sp, const float *
     if (lane < kMlpHidden) return (double)w2 * S1;
     if (lane < 2 * kMlpHidden) return (double)w2 * S0;
     return (double)w * S1 + (double)b * S0;
+}
+
+// mlp_grad_sorted with the fewest samples per lane that hold m (<= kMlpBatch).
+__device__ __forceinline__ double mlp_grad(const float *sp, const float *sx, const float *st, int m,
+                                           float *l0, float *l1, double *e0s, double *e1s,
+                                           int lane, double *loss) {
+    if (m <= 64) return mlp_grad_sorted<1>(sp, sx, st, m, l0, l1, e0s, e1s, lane, loss);
+    if (m <= 128) return mlp_grad_sorted<2>(sp, sx, st, m, l0, l1, e0s, e1s, lane, loss);
+    if (m <= 256) return mlp_grad_sorted<4>(sp, sx, st, m, l0, l1, e0s, e1s, lane, loss);
+    return mlp_grad_sorted<kMlpBatch / 64>(sp, sx, st, m, l0, l1, e0s, e1s, lane, loss);
 }
 
 // ----------------------------------------------------------------- kernels
@@ -469,6 +480,35 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_linear(const uint64_t *
     }
 }
 
+// Full-batch Adam on the network in s_p (lane c owns parameter c and its
+// moments) for `epochs` epochs over the m samples in LDS.
+template <int kPer>
+__device__ __forceinline__ void mlp_adam(float *s_p, const float *s_x, const float *s_t, int m,
+                                         float *s_l0, float *s_l1, double *s_e0, double *s_e1,
+                                         int tid, uint32_t epochs, float lr) {
+    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f;
+    const double dm = (double)m;
+    float pw1 = 1.0f, pw2 = 1.0f;  // b1c^t, b2c^t
+    float own = s_p[tid], am = 0.0f, av = 0.0f;
+    for (uint32_t ep = 0; ep < epochs; ++ep) {
+        double loss;
+        const double gsum =
+            mlp_grad_sorted<kPer>(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, &loss);
+        pw1 = __fmul_rn(pw1, b1c);
+        pw2 = __fmul_rn(pw2, b2c);
+        __syncthreads();  // every lane has read this epoch's parameters and sums
+        if (tid < kMlpParams) {
+            const float gr = (float)(gsum / dm);
+            am = fmaf(b1c, am, __fmul_rn(1.0f - b1c, gr));
+            av = fmaf(b2c, av, __fmul_rn(__fmul_rn(1.0f - b2c, gr), gr));
+            const float mh = __fdiv_rn(am, 1.0f - pw1), vh = __fdiv_rn(av, 1.0f - pw2);
+            own = __fsub_rn(own, __fdiv_rn(__fmul_rn(lr, mh), __fadd_rn(sqrtf(vh), eps)));
+            s_p[tid] = own;
+        }
+        __syncthreads();
+    }
+}
+
 // Network leaves, one wave per leaf: initialise the 1-16-1 network as the
 // piecewise-linear interpolant of the leaf's key -> rank map at 17 rank
 // quantiles, then train it with full-batch Adam on the mean squared error.
@@ -543,26 +583,11 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_mlp(const uint64_t *__r
     }
     __syncthreads();
 
-    const float b1c = 0.9f, b2c = 0.999f, eps = 1e-8f;
-    const double dm = (double)m;
-    float pw1 = 1.0f, pw2 = 1.0f;  // b1c^t, b2c^t
-    float own = s_p[tid], am = 0.0f, av = 0.0f;
-    for (uint32_t ep = 0; ep < epochs; ++ep) {
-        double loss;
-        const double gsum = mlp_grad_sorted(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, &loss);
-        pw1 = __fmul_rn(pw1, b1c);
-        pw2 = __fmul_rn(pw2, b2c);
-        __syncthreads();  // every lane has read this epoch's parameters and sums
-        if (tid < kMlpParams) {
-            const float gr = (float)(gsum / dm);
-            am = fmaf(b1c, am, __fmul_rn(1.0f - b1c, gr));
-            av = fmaf(b2c, av, __fmul_rn(__fmul_rn(1.0f - b2c, gr), gr));
-            const float mh = __fdiv_rn(am, 1.0f - pw1), vh = __fdiv_rn(av, 1.0f - pw2);
-            own = __fsub_rn(own, __fdiv_rn(__fmul_rn(lr, mh), __fadd_rn(sqrtf(vh), eps)));
-            s_p[tid] = own;
-        }
-        __syncthreads();
-    }
+    // the epoch loop at the fewest samples per lane that hold m
+    if (m <= 64) mlp_adam<1>(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, epochs, lr);
+    else if (m <= 128) mlp_adam<2>(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, epochs, lr);
+    else if (m <= 256) mlp_adam<4>(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, epochs, lr);
+    else mlp_adam<kMlpBatch / 64>(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, epochs, lr);
     for (uint32_t c = tid; c < h.nparams; c += blockDim.x) par[c] = c < (uint32_t)kMlpParams ? s_p[c] : 0.0f;
 }
 
@@ -712,7 +737,7 @@ __global__ __launch_bounds__(kLeafBlock) void k_mlp_loss_grad(const float *param
         }
         __syncthreads();
         double l;
-        g += mlp_grad_sorted(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, &l);
+        g += mlp_grad(s_p, s_x, s_t, m, s_l0, s_l1, s_e0, s_e1, tid, &l);
         l2 += l;
     }
 #pragma unroll
