@@ -39,10 +39,15 @@ constexpr int kTemporalMaxIter = 1000;
 // computes its centres itself, in every block, from pass t - 1's sums (so
 // no launch sits between passes), and clears slot (t + 1) % 3, which pass
 // t - 1 finished reading.
+// Each pass's sums are kept in kRep copies (block b adds to copy b % kRep),
+// so that fewer blocks add to one word; the next pass adds the copies up.
+// The sums are integers, so the copies change no result.
+constexpr int kRep = 8;
+
 struct KmState {
     double cent[2][kCl][3];
-    unsigned long long sum[3][kCl][3];
-    unsigned long long cnt[3][kCl];
+    unsigned long long sum[3][kRep][kCl][3];
+    unsigned long long cnt[3][kRep][kCl];
     uint32_t changed[3];
     uint32_t lo_inv[3];  // ~min per axis (so that a zeroed block starts at "no voxel")
     uint32_t hi[3];
@@ -145,8 +150,14 @@ __global__ __launch_bounds__(256) void k_km_assign(Frames<K> F, uint32_t depth, 
     if (threadIdx.x < kCl * 3) {
         const int k = threadIdx.x / 3, a = threadIdx.x % 3;
         const int before = pass > 0 ? (pass + 1) & 1 : 0;
-        const unsigned long long n = pass > 0 ? S.cnt[prev][k] : 0ull;
-        const double v = n > 0 ? __ddiv_rn((double)S.sum[prev][k][a], (double)n) : S.cent[before][k][a];
+        unsigned long long n = 0, sa = 0;
+        if (pass > 0)
+#pragma unroll
+            for (int r = 0; r < kRep; ++r) {
+                n += S.cnt[prev][r][k];
+                sa += S.sum[prev][r][k][a];
+            }
+        const double v = n > 0 ? __ddiv_rn((double)sa, (double)n) : S.cent[before][k][a];
         s_c[threadIdx.x] = v;
         // block 0 keeps this pass's centres (for the next pass's empty
         // clusters and for the result)
@@ -154,9 +165,10 @@ __global__ __launch_bounds__(256) void k_km_assign(Frames<K> F, uint32_t depth, 
     }
     if (blockIdx.x == 0) {
         if (threadIdx.x == 0) S.iters = pass + 1;
-        if (threadIdx.x < kCl * 4) {
-            if ((threadIdx.x & 3) == 3) S.cnt[next][threadIdx.x >> 2] = 0;
-            else S.sum[next][threadIdx.x >> 2][threadIdx.x & 3] = 0;
+        for (int t = threadIdx.x; t < kRep * kCl * 4; t += blockDim.x) {
+            const int r = t / (kCl * 4), w = t % (kCl * 4);
+            if ((w & 3) == 3) S.cnt[next][r][w >> 2] = 0;
+            else S.sum[next][r][w >> 2][w & 3] = 0;
         }
         if (threadIdx.x == 0) S.changed[next] = 0;
     }
@@ -221,7 +233,8 @@ __global__ __launch_bounds__(256) void k_km_assign(Frames<K> F, uint32_t depth, 
     __syncthreads();
     for (int t = threadIdx.x; t < kCl * 4; t += blockDim.x) {
         const unsigned long long v = s_sum[t];
-        if (v) atomicAdd((t & 3) == 3 ? &S.cnt[cur][t >> 2] : &S.sum[cur][t >> 2][t & 3], v);
+        const int r = blockIdx.x % kRep;
+        if (v) atomicAdd((t & 3) == 3 ? &S.cnt[cur][r][t >> 2] : &S.sum[cur][r][t >> 2][t & 3], v);
     }
     if (threadIdx.x == 0 && s_changed) atomicOr(&S.changed[cur], 1u);
 }
