@@ -743,6 +743,10 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(traffic) if traffic else None,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": per_step_launches,
+                # events bracket the launches of the overlapped step issued
+                # per step (they cannot sit inside the replayed graph, where
+                # the search shares the GPU with the leaf training more tightly)
+                "measured_on": "overlapped step, launched per step",
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
             }
         cga.cga_prof_reset()
