@@ -127,9 +127,17 @@ __global__ __launch_bounds__(256) void k_batch_encode(const float *__restrict__ 
          i += (int64_t)gridDim.x * blockDim.x) {
         Vox v;
         bad |= !quantize3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], o, scale, depth, v);
-        const uint64_t k = ((uint64_t)frame_of(off, F, i) << shift) | enc3(v.x, v.y, v.z, depth, linear != 0);
+        // a frame's points are consecutive, so the wave's first active lane
+        // finds its frame and the others only confirm it
+        const uint64_t act = __ballot(1);
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        uint32_t f0 = 0;
+        if (lane_id() == leader) f0 = frame_of(off, F, i);
+        f0 = __shfl(f0, leader, 64);
+        const uint32_t fr = off[f0] <= i && i < off[f0 + 1] ? f0 : frame_of(off, F, i);
+        const uint64_t k = ((uint64_t)fr << shift) | enc3(v.x, v.y, v.z, depth, linear != 0);
         keys[i] = k;
-        hist_add<RB>(s_h, k, passes);
+        hist_add_coherent<RB>(s_h, k, passes);
     }
     if (bad) s_bad = 1;
     __syncthreads();

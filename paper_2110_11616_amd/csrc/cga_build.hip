@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ xyz, i
         bad |= !quantize3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], o, scale, depth, v);
         K k = (K)enc3(v.x, v.y, v.z, depth, linear != 0);
         keys[i] = k;
-        if (passes) hist_add<RB>(s_h, k, passes);
+        if (passes) hist_add_coherent<RB>(s_h, k, passes);
     }
     if (bad) s_bad = 1;
     __syncthreads();

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_rekey(const K *__restrict__ in, int64_t
         uint32_t w = drop == 2 ? v.y : v.z;
         K2 k2 = linear ? (K2)(((uint64_t)u << depth) | w) : (K2)((spread2(u) << 1) | spread2(w));
         out[i] = k2;
-        hist_add<RB>(s_h, k2, passes);
+        hist_add_coherent<RB>(s_h, k2, passes);
     }
     __syncthreads();
     hist_flush<RB>(s_h, hist, passes);

@@ -43,6 +43,26 @@ __device__ __forceinline__ void hist_add(uint32_t *s_h, K key, int passes) {
     }
 }
 
+// hist_add for keys of neighbouring points (an encode in input order, a
+// re-key of sorted keys): where the active lanes of the wave share a digit,
+// as the high digits of neighbouring keys mostly do, one add of their number
+// replaces theirs.  On unordered keys the check only costs.
+template <int RB, typename K>
+__device__ __forceinline__ void hist_add_coherent(uint32_t *s_h, K key, int passes) {
+    constexpr uint32_t RADIX = 1u << RB;
+    const uint64_t act = __ballot(1);
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    for (int p = 0; p < passes; ++p) {
+        uint32_t d = (uint32_t)(key >> (p * RB)) & (RADIX - 1);
+        const uint32_t d0 = __shfl(d, leader, 64);
+        if (__ballot(d == d0) == act) {
+            if (lane_id() == leader) atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(act));
+        } else {
+            atomicAdd(&s_h[p * RADIX + d], 1u);
+        }
+    }
+}
+
 template <int RB>
 __device__ __forceinline__ void hist_flush(const uint32_t *s_h, uint32_t *g_h, int passes) {
     constexpr uint32_t RADIX = 1u << RB;
