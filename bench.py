@@ -188,12 +188,13 @@ class Pipeline:
         ev[2].record(main)
         for s in (sp, sk, si):
             s.wait_event(ev[2])
-        with torch.cuda.stream(sp):
-            c.cga_project(self.m, g, 2, n=self.nm, d_n=cnt[2:3], out=self.p, counts_out=self.pc,
-                          d_n_out=cnt[3:4], sync=False, ws=self.ws[3])
+        # the k-NN search, the longest branch, is issued first
         with torch.cuda.stream(sk):
             c.cga_knn(self.m, self.q, g, self.k, n=self.nm, d_n=cnt[2:3], idx_out=self.idx,
                       d2_out=self.d2, sync=False, ws=self.ws[4])
+        with torch.cuda.stream(sp):
+            c.cga_project(self.m, g, 2, n=self.nm, d_n=cnt[2:3], out=self.p, counts_out=self.pc,
+                          d_n_out=cnt[3:4], sync=False, ws=self.ws[3])
         with torch.cuda.stream(si):
             c.cga_index_train(self.m, self.nu, out=self.index, ws=self.ws[5], **self.index_kwargs)
             c.cga_index_lookup(self.index, self.m, self.lq, n=self.nu, rank_out=self.lrank,
