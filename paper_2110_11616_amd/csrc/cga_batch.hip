@@ -204,39 +204,58 @@ __global__ void k_batch_pairs(const int64_t *__restrict__ key_off, int F,
     }
 }
 
+// Pair of merge window `tile`: the last p with tile_off[p] <= tile.
+__device__ __forceinline__ int pair_of(const int64_t *tile_off, int P, int64_t tile) {
+    int lo = 0, len = P;
+    while (len > 1) {
+        const int half = len >> 1;
+        lo = tile_off[lo + half] <= tile ? lo + half : lo;
+        len -= half;
+    }
+    return lo;
+}
+
+// part[tile] = A elements before the window's first diagonal, one thread
+// per window, all windows at once (the merge loop below would otherwise
+// wait for two dependent searches per window).
+template <typename K>
+__global__ void k_batch_partition(const K *__restrict__ keys, const int64_t *__restrict__ key_off,
+                                  int F, const int64_t *__restrict__ tile_off,
+                                  const int64_t *total_tiles, int64_t *__restrict__ part) {
+    const int64_t T = *total_tiles;
+    for (int64_t tile = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; tile < T;
+         tile += (int64_t)gridDim.x * blockDim.x) {
+        const int p = pair_of(tile_off, F - 1, tile);
+        const int64_t na = key_off[p + 1] - key_off[p], nb = key_off[p + 2] - key_off[p + 1];
+        part[tile] = merge_path(keys + key_off[p], na, keys + key_off[p + 1], nb,
+                                (tile - tile_off[p]) * kMergeTile);
+    }
+}
+
 // Persistent: workgroups take windows from one queue until all pairs are done.
 template <typename K>
 __global__ __launch_bounds__(kMergeBlock) void k_batch_merge(
     const K *__restrict__ keys, const int64_t *__restrict__ key_off, int F,
     const int64_t *__restrict__ merged_off, const int64_t *__restrict__ tile_off,
-    const int64_t *total_tiles, K *__restrict__ merged, int64_t *__restrict__ merged_cnt,
-    uint64_t *status, uint32_t *tile_ctr, uint32_t *err) {
+    const int64_t *total_tiles, const int64_t *__restrict__ part, K *__restrict__ merged,
+    int64_t *__restrict__ merged_cnt, uint64_t *status, uint32_t *tile_ctr, uint32_t *err) {
     __shared__ uint32_t s_tile;
     __shared__ MergeShared<K> sh;
-    __shared__ int64_t s_a[2];
     const int64_t T = *total_tiles;
     const int P = F - 1;
     for (;;) {
         const int64_t tile = (int64_t)next_tile(tile_ctr, &s_tile);
         if (tile >= T) break;  // uniform across the workgroup
-        // pair of this window: last p with tile_off[p] <= tile
-        int lo = 0, len = P;
-        while (len > 1) {
-            const int half = len >> 1;
-            lo = tile_off[lo + half] <= tile ? lo + half : lo;
-            len -= half;
-        }
-        const int p = lo;
+        const int p = pair_of(tile_off, P, tile);
         const int64_t first_tile = tile_off[p];
         const K *A = keys + key_off[p];
         const K *B = keys + key_off[p + 1];
         const int64_t na = key_off[p + 1] - key_off[p], nb = key_off[p + 2] - key_off[p + 1];
         const int64_t d0 = (tile - first_tile) * kMergeTile;
         const int64_t d1 = d0 + kMergeTile < na + nb ? d0 + kMergeTile : na + nb;
-        if (threadIdx.x == 0) s_a[0] = merge_path(A, na, B, nb, d0);
-        if (threadIdx.x == 64) s_a[1] = merge_path(A, na, B, nb, d1);
-        __syncthreads();
-        const int64_t a0 = s_a[0], a1 = s_a[1];
+        // a window that does not end its pair is followed by the pair's next
+        const int64_t a0 = part[tile], a1 = d1 == na + nb ? na : part[tile + 1];
+        __syncthreads();  // the previous window's use of sh is over
         const int64_t cap = na + nb;
         merge_tile<K>(sh, A, na, B, nb, d0, d1, a0, a1, merged + merged_off[p], nullptr, cap,
                       merged_cnt + p, status, tile, first_tile, err);
@@ -257,6 +276,7 @@ struct BatchLayout {
     uint64_t *buf_a, *buf_b;
     int64_t *tile_off, *total_tiles;
     uint64_t *merge_status;
+    int64_t *merge_part;
     int64_t merge_tiles_bound;
     int frame_bits;
     size_t bytes;
@@ -281,6 +301,7 @@ static BatchLayout batch_layout(void *ws, const cga_grid *g, int F, int64_t n, c
     L.total_tiles = c.take<int64_t>(1);
     L.merge_tiles_bound = (2 * n + kMergeTile - 1) / kMergeTile + F + 1;
     L.merge_status = c.take<uint64_t>((size_t)L.merge_tiles_bound);
+    L.merge_part = c.take<int64_t>((size_t)L.merge_tiles_bound);
     L.bytes = c.size();
     return L;
 }
@@ -400,11 +421,15 @@ static int batch_enqueue(const BatchArgs &a, hipStream_t s) {
         }
         int64_t groups = persistent_groups();
         groups = groups < L.merge_tiles_bound ? groups : L.merge_tiles_bound;
+        int64_t pblocks = (L.merge_tiles_bound + 255) / 256;
+        pblocks = pblocks > 4096 ? 4096 : pblocks;
         CGA_PROF("batch_merge", s);
+        k_batch_partition<K><<<(unsigned)pblocks, 256, 0, s>>>((const K *)a.keys, a.key_off, a.F,
+                                                              L.tile_off, L.total_tiles, L.merge_part);
         k_batch_merge<K><<<(unsigned)groups, kMergeBlock, 0, s>>>(
             (const K *)a.keys, a.key_off, a.F, a.merged_off, L.tile_off, L.total_tiles,
-            (K *)a.merged, a.merged_cnt, L.merge_status, &L.ctl->tile_ctr[kMaxPasses + 1],
-            &L.ctl->err);
+            L.merge_part, (K *)a.merged, a.merged_cnt, L.merge_status,
+            &L.ctl->tile_ctr[kMaxPasses + 1], &L.ctl->err);
     }
     CGA_HIP(hipGetLastError());
     return CGA_OK;
