@@ -108,37 +108,74 @@ __global__ __launch_bounds__(kRleBlock) void k_rle(const K *__restrict__ in, int
     }
     __syncthreads();
 
-    uint32_t rc = s_pc + ex_c;
+    // Outputs go through LDS so that consecutive threads write consecutive
+    // slots: first the values of the runs that start in this tile, then the
+    // counts (or ends) of the runs that end in it.  Each thread first keeps
+    // its items' outputs in registers, as the tile's keys still occupy LDS.
+    const uint32_t rc0 = s_pc + ex_c;  // runs that start before this thread's items
+    uint32_t rc = rc0;
     int32_t rl = s_pl > ex_l ? s_pl : ex_l;
-    bool over = false;
+    K hv[kRleItems];
+    uint32_t ev[kRleItems];
+    uint32_t hbits = 0, ebits = 0;
 #pragma unroll
     for (int it = 0; it < kRleItems; ++it) {
-        int j = j0 + it;
-        int64_t i = base + j;
+        const int j = j0 + it;
+        const int64_t i = base + j;
+        hv[it] = K(0);
+        ev[it] = 0;
         if (i < n) {
-            K v = SV(1 + j);
+            const K v = SV(1 + j);
             if (i == 0 || v != SV(j)) {
                 ++rc;
                 rl = (int32_t)i;
-                if ((int64_t)rc <= cap) {
-                    if (vals) vals[rc - 1] = (OV)((uint64_t)v & out_mask);
-                } else {
-                    over = true;
-                }
+                hbits |= 1u << it;
+                hv[it] = v;
             }
             if (i == n - 1 || v != SV(2 + j)) {
-                if ((int64_t)rc <= cap) {
-                    if (ENDS) {
-                        if (ends) ends[rc] = i + 1;
-                    } else if (counts) {
-                        counts[rc - 1] = (uint32_t)(i + 1 - rl);
-                    }
-                }
+                ebits |= 1u << it;
+                ev[it] = ENDS ? (uint32_t)(i + 1 - base) : (uint32_t)(i + 1 - rl);
                 if (i == n - 1 && n_out) *n_out = rc;
             }
         }
     }
-    if (over) set_err(err, ERR_CAPACITY);
+    const int64_t tile_end = base + kRleTile < n ? base + kRleTile : n;
+    const bool first_head = base == 0 || SV(1) != SV(0);
+    const int jl = (int)(tile_end - 1 - base);
+    const bool last_end = tile_end == n || SV(1 + jl) != SV(2 + jl);
+    __syncthreads();  // every thread has read the tile's keys
+
+    K *st_v = s_v;  // the starts' values, slot = run number - s_pc - 1
+#pragma unroll
+    for (int it = 0; it < kRleItems; ++it)
+        if ((hbits >> it) & 1u) st_v[ex_c + __popc(hbits & ((1u << it) - 1u))] = hv[it];
+    __syncthreads();
+    for (int j = tid; j < (int)tot_c; j += kRleBlock) {
+        const int64_t r = (int64_t)s_pc + j + 1;  // run number, from 1
+        if (r <= cap && vals) vals[r - 1] = (OV)((uint64_t)st_v[j] & out_mask);
+    }
+    if (tid == 0 && (int64_t)s_pc + tot_c > cap) set_err(err, ERR_CAPACITY);
+    __syncthreads();
+
+    // the ends' counts (or end offsets within the tile), slot = run number -
+    // the run number of the tile's first element
+    uint32_t *st_e = (uint32_t *)s_v;
+    const uint32_t r_first = s_pc + (first_head ? 1u : 0u);
+#pragma unroll
+    for (int it = 0; it < kRleItems; ++it)
+        if ((ebits >> it) & 1u) st_e[rc0 + __popc(hbits & ((2u << it) - 1u)) - r_first] = ev[it];
+    __syncthreads();
+    const int ne = (int)tot_c + (first_head ? 0 : 1) - (last_end ? 0 : 1);
+    for (int j = tid; j < ne; j += kRleBlock) {
+        const int64_t r = (int64_t)r_first + j;
+        if (r <= cap) {
+            if (ENDS) {
+                if (ends) ends[r] = base + st_e[j];
+            } else if (counts) {
+                counts[r - 1] = st_e[j];
+            }
+        }
+    }
 #undef SV
 }
 
