@@ -331,9 +331,12 @@ int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n,
  *         of more than 512 keys trains on 512 of them evenly spaced by rank).
  *  window: err_lo_j / err_hi_j = min / max of (rank - p) over the leaf's keys.
  * Lookup: route, predict, take [lo, hi] = p + [err_lo, err_hi] clamped to
- * the leaf, verify (lo == 0 || keys[lo-1] < q) && (hi == n || keys[hi] >= q),
- * then search inside [lo, hi]; a failed check (an absent key the window does
- * not cover) falls back to a full binary search, counted in d_fallbacks.
+ * the leaf [f, f + n_j], verify (lo == f || keys[lo-1] < q) && (hi == f + n_j
+ * || keys[hi] >= q) (routing is monotone, so a window edge at the leaf's edge
+ * holds already), then search inside [lo, hi]; a failed check (an absent key
+ * the window does not cover) falls back to a full binary search, counted in
+ * d_fallbacks.  Any window contents stay exact; the leaf ranges must be the
+ * ones cga_index_train wrote.
  * The index is one caller-owned, position-independent device buffer of
  * cga_index_bytes; it records n, kmin, kmax and a key fingerprint, and a
  * lookup against a different key array reports CGA_EMISMATCH. */

@@ -686,7 +686,11 @@ __global__ __launch_bounds__(kLookupBlock) void k_index_lookup(
         int64_t lo = p + lh.err_lo, hi = p + lh.err_hi;
         lo = lo < f0 ? f0 : (lo > f1 ? f1 : lo);
         hi = hi < lo ? lo : (hi > f1 ? f1 : hi);
-        const bool good = (lo == 0 || keys[lo - 1] < x) && (hi == n || keys[hi] >= x);
+        // Routing is monotone and the leaf holds exactly the ranks routed to
+        // it, so keys[f0 - 1] < x <= keys[f1] already: a window edge at the
+        // leaf's edge needs no check (with 2^24 leaves most windows are
+        // whole leaves).
+        const bool good = (lo == f0 || keys[lo - 1] < x) && (hi == f1 || keys[hi] >= x);
         if (good) {
             r = lb_range(keys, lo, hi, x);  // answer in [lo, hi]
         } else {

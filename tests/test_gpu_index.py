@@ -77,12 +77,12 @@ def test_lookup_small_arrays(gpu):
 
 def _window_offsets(n_leaves, nparams, root):
     """Byte offsets of every leaf's err_lo / err_hi in the index buffer: a
-    256-byte header, the root segment starts (4 B each) and segments (16 B
+    256-byte header, the root segment starts (8 B each) and segments (32 B
     each), then one record per leaf (64 B for linear leaves, 256 B for
     network leaves) whose window sits at bytes 24 and 28."""
     al = lambda v: (v + 255) // 256 * 256
-    off = al(256 + root * 4)
-    off = al(off + root * 16)
+    off = al(256 + root * 8)
+    off = al(off + root * 32)
     stride = 64 if nparams <= 8 else 256
     base = off + np.arange(n_leaves) * stride
     return base + 24, base + 28
@@ -94,6 +94,14 @@ def test_zeroed_windows_fall_back_and_stay_exact(gpu, lidar_keys):
     idx = gpu.cga_index_train(kd, n_leaves=4096, leaf_kind=1, epochs=10, root_segments=1024)
     host = idx.cpu().numpy().copy()
     lo, hi = _window_offsets(4096, 49, 1024)
+    # the offsets land on the leaf records: their key counts (bytes 16..19)
+    # are the index's own, and each leaf's window was ordered
+    i32 = lambda offs: np.array([int(np.frombuffer(host[o:o + 4].tobytes(), np.int32)[0])
+                                 for o in offs])
+    _, cnt = gpu.cga_index_stats(idx, 4096)
+    assert np.array_equal(i32(lo - 8), cnt.cpu().numpy())
+    full = cnt.cpu().numpy() > 0
+    assert (i32(lo)[full] <= i32(hi)[full]).all()
     for off in np.concatenate([lo, hi]):
         host[off:off + 4] = 0
     bad = torch.from_numpy(host).cuda()
