@@ -245,6 +245,15 @@ size_t cga_knn_workspace_bytes(const cga_grid *grid, int64_t n, int64_t nq);
 int cga_knn(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,
             const float *d_q, int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2, void *d_ws,
             size_t ws_bytes, cga_stream stream);
+/* The same search built with work counters, for measurement: identical
+ * outputs, and d_work (device, 4 uint64, accumulated -- the caller zeroes
+ * it) gains the search's node-word loads (8 B each), dense-table loads (4 B
+ * each), voxels offered to the candidate lists and walk-loop steps, summed
+ * over all queries and lanes.  The search is deterministic, so these are the
+ * exact per-call work of cga_knn on the same input. */
+int cga_knn_count(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,
+                  const float *d_q, int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2,
+                  uint64_t *d_work, void *d_ws, size_t ws_bytes, cga_stream stream);
 
 /* ------------------------------------------------------------- values
  * The Value array (Section V): per-voxel attributes from per-point ones.
@@ -331,15 +340,19 @@ int cga_binary_lookup(const uint64_t *d_keys, int64_t n, const int64_t *d_n,
  *         of more than 512 keys trains on 512 of them evenly spaced by rank).
  *  window: err_lo_j / err_hi_j = min / max of (rank - p) over the leaf's keys.
  * Lookup: route, predict, take [lo, hi] = p + [err_lo, err_hi] clamped to
- * the leaf [f, f + n_j], verify (lo == f || keys[lo-1] < q) && (hi == f + n_j
- * || keys[hi] >= q) (routing is monotone, so a window edge at the leaf's edge
- * holds already), then search inside [lo, hi]; a failed check (an absent key
- * the window does not cover) falls back to a full binary search, counted in
- * d_fallbacks.  Any window contents stay exact; the leaf ranges must be the
- * ones cga_index_train wrote.
+ * the leaf [f, f + n_j], and accept it iff (lo == 0 || keys[lo-1] < q) &&
+ * (hi == n || keys[hi] >= q): one lower-bound search over [lo - 1, hi + 1)
+ * decides both and finds the rank.  A failed check (an absent key the window
+ * does not cover, or a key array other than the trained one) falls back to a
+ * full binary search, counted in d_fallbacks.  Ranks are therefore exact for
+ * any sorted key array of n keys, whatever the index holds.
  * The index is one caller-owned, position-independent device buffer of
- * cga_index_bytes; it records n, kmin, kmax and a key fingerprint, and a
- * lookup against a different key array reports CGA_EMISMATCH. */
+ * cga_index_bytes (it includes a 32 KiB fingerprint).  It records n, kmin,
+ * kmax and the keys at min(n, 4096) evenly spaced ranks (s * (n - 1) /
+ * (m - 1) for s < m).  A lookup whose array differs in n, kmin or kmax
+ * writes rank 0 / found 0 and reports CGA_EMISMATCH; one that differs at a
+ * sampled rank reports CGA_EMISMATCH with exact ranks; a difference at
+ * other ranks only goes undetected (the ranks stay exact). */
 typedef struct {
     uint32_t n_leaves;      /* 1 .. 2^24 (4096 .. 2^20 typical) */
     uint32_t leaf_kind;     /* 0 = linear, 1 = 1-16-1 ReLU network */
@@ -435,6 +448,13 @@ int cga_prof_enable(const char *filter);
 int cga_prof_disable(void);
 int cga_prof_reset(void);
 int cga_prof_read(const char *label, double *total_ms, int64_t *launches);
+/* Attainable HBM bandwidth probe (the roofline's measured ceiling beside the
+ * datasheet peak): mode 0 copies `bytes` from d_src to d_dst (each byte read
+ * once and written once), mode 1 only reads d_src (d_dst nullable: a 4-byte
+ * sink that is never written in practice).  bytes a positive multiple of 16;
+ * `blocks` workgroups of 256 threads, grid-stride. */
+int cga_stream_probe(const void *d_src, void *d_dst, size_t bytes, int mode, int blocks,
+                     cga_stream stream);
 
 #ifdef __cplusplus
 }

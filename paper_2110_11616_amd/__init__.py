@@ -92,6 +92,8 @@ _sig("cga_project", ctypes.c_int, _GP, _P, _I64, _P, ctypes.c_int, _P, _P, _I64,
      _SZ, _TP, _P)
 _sig("cga_knn_workspace_bytes", _SZ, _GP, _I64, _I64)
 _sig("cga_knn", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, ctypes.c_int, _P, _P, _P, _SZ, _P)
+_sig("cga_knn_count", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, ctypes.c_int, _P, _P, _P, _P, _SZ,
+     _P)
 _sig("cga_binary_lookup", ctypes.c_int, _P, _I64, _P, _P, _I64, _P, _P, _P)
 
 
@@ -130,6 +132,7 @@ _sig("cga_prof_enable", ctypes.c_int, ctypes.c_char_p)
 _sig("cga_prof_disable", ctypes.c_int)
 _sig("cga_prof_reset", ctypes.c_int)
 _sig("cga_prof_read", ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), _I64P)
+_sig("cga_stream_probe", ctypes.c_int, _P, _P, _SZ, ctypes.c_int, ctypes.c_int, _P)
 
 
 # ------------------------------------------------------------------ helpers
@@ -417,6 +420,27 @@ def cga_knn(keys: torch.Tensor, queries: torch.Tensor, grid, k: int, *, n=None, 
     return idx, d2
 
 
+def cga_knn_count(keys: torch.Tensor, queries: torch.Tensor, grid, k: int, *, n=None, d_n=None,
+                  idx_out=None, d2_out=None, ws=None, stream=None):
+    """cga_knn built with work counters: (indices, squared distances, work)
+    where work = {node_loads, dense_loads, voxels_offered, steps}, totals
+    over all queries (synchronises)."""
+    n = keys.shape[0] if n is None else int(n)
+    nq = queries.shape[0]
+    g = grid_struct(grid)
+    dev = queries.device
+    idx = idx_out if idx_out is not None else torch.empty((nq, k), dtype=torch.int64, device=dev)
+    d2 = d2_out if d2_out is not None else torch.empty((nq, k), dtype=torch.int64, device=dev)
+    work = torch.zeros(4, dtype=torch.int64, device=dev)
+    wsb = _ws("knn", lib.cga_knn_workspace_bytes(ctypes.byref(g), n, nq), ws)
+    rc = lib.cga_knn_count(ctypes.byref(g), _ptr(keys), n, _ptr(d_n), _ptr(queries), nq, int(k),
+                           _ptr(idx), _ptr(d2), _ptr(work), _ptr(wsb), wsb.numel(), _stream(stream))
+    _check(rc, "cga_knn_count")
+    _check(lib.cga_ws_status(_ptr(wsb), _stream(stream)), "cga_knn_count")
+    w = [int(x) for x in work.cpu().tolist()]
+    return idx, d2, dict(zip(("node_loads", "dense_loads", "voxels_offered", "steps"), w))
+
+
 VALUES_BASE, VALUES_AVERAGE = 0, 1
 
 
@@ -668,6 +692,12 @@ def cga_prof_disable():
 
 def cga_prof_reset():
     _check(lib.cga_prof_reset(), "cga_prof_reset")
+
+
+def cga_stream_probe(src: torch.Tensor, dst, nbytes: int, mode: int, blocks: int, stream=None):
+    """Enqueue one bandwidth-probe launch (0 = copy src -> dst, 1 = read src)."""
+    _check(lib.cga_stream_probe(_ptr(src), _ptr(dst), int(nbytes), int(mode), int(blocks),
+                                _stream(stream)), "cga_stream_probe")
 
 
 def cga_prof_read(label: str):

@@ -1,8 +1,8 @@
 // Learned index over a sorted unique uint64 key array: a two-stage model of
-// the key -> rank function (fp32 root linear router, per-leaf linear or
-// 1-16-1 ReLU network), per-leaf max-error windows, and a verified
-// last-mile lookup with binary-search fallback, so that every result equals
-// the plain lower bound.  Trained on the GPU by the kernels below: fp64 sums
+// the key -> rank function (fp64 root router, linear or piecewise linear,
+// per-leaf fp32 linear or 1-16-1 ReLU network), per-leaf max-error windows,
+// and a verified last-mile lookup with binary-search fallback, so that every
+// result equals the plain lower bound for any sorted key array.  Trained on the GPU by the kernels below: fp64 sums
 // for the least-squares fits, a full-batch forward/backward pass plus Adam
 // per network leaf (one workgroup per leaf, fixed reduction order, so
 // training is deterministic).
@@ -15,13 +15,18 @@
 namespace cga {
 
 constexpr uint32_t kIndexMagic = 0x49414743u;  // "CGAI"
-constexpr uint32_t kIndexVersion = 2;
+constexpr uint32_t kIndexVersion = 3;
 constexpr int kMlpHidden = 16;
 constexpr int kMlpParams = 3 * kMlpHidden + 1;  // w1[16], b1[16], w2[16], b2
 constexpr int kLeafBlock = 64;  // one wave per leaf
-// Leaf count limit: leaf ids are exact in the fp32 routing arithmetic up to
-// 2^24.
+// Leaf count limit.  Routing computes the leaf id in fp64 (exact far beyond
+// this); the limit keeps the leaf records within 1 GiB (linear) or 4 GiB
+// (network) and a leaf's int32 window arithmetic far from overflow.
 constexpr uint32_t kMaxLeaves = 1u << 24;
+// Keys at evenly spaced ranks kept in the index as its key fingerprint: a
+// lookup compares the given array at those ranks (CGA_EMISMATCH on a
+// difference).
+constexpr uint32_t kIndexSamples = 4096;
 constexpr int kLeafCache = 1024;  // leaf inputs kept in LDS (floats)
 constexpr int kMlpBatch = 512;    // training samples per network leaf and epoch
 constexpr int kMlpPad = 64;       // gradient vector length for the halving reduction
@@ -34,6 +39,7 @@ struct IndexHeader {
     uint32_t nparams;
     uint32_t root_segs;
     uint32_t leaf_stride;  // bytes per leaf record
+    uint32_t nsamples;     // fingerprint keys: min(n, kIndexSamples)
 };
 static_assert(sizeof(IndexHeader) <= 256, "index header");
 
@@ -64,6 +70,7 @@ struct IndexView {
     IndexHeader *h;
     double *rx;     // R segment start inputs (searched)
     RootSeg *seg;   // R segments
+    uint64_t *samp; // fingerprint: the keys at ranks sample_rank(s)
     char *leaves;   // n_leaves records of leaf_stride bytes
     __device__ LeafHead &head(uint32_t j) const { return *(LeafHead *)(leaves + (size_t)j * h->leaf_stride); }
     __device__ float *params(uint32_t j) const {
@@ -80,10 +87,18 @@ __host__ __device__ inline size_t index_layout(char *base, uint32_t L, uint32_t 
     off = idx_align(off + (size_t)R * sizeof(double));
     w.seg = base ? (RootSeg *)(base + off) : nullptr;
     off = idx_align(off + (size_t)R * sizeof(RootSeg));
+    w.samp = base ? (uint64_t *)(base + off) : nullptr;
+    off = idx_align(off + (size_t)kIndexSamples * sizeof(uint64_t));
     w.leaves = base ? base + off : nullptr;
     off = idx_align(off + (size_t)L * leaf_stride(nparams));
     if (v) *v = w;
     return off;
+}
+
+// Rank of fingerprint key s of m (m = min(n, kIndexSamples)): evenly spaced
+// over [0, n - 1], both ends included.
+__host__ __device__ inline int64_t sample_rank(uint32_t s, uint32_t m, int64_t n) {
+    return m > 1 ? (int64_t)(((uint64_t)s * (uint64_t)(n - 1)) / (m - 1)) : 0;
 }
 
 // ------------------------------------------------------------- model maths
@@ -300,12 +315,23 @@ __global__ void k_index_header(const uint64_t *keys, int64_t n, uint32_t L, uint
     h->leaf_kind = kind;
     h->nparams = np;
     h->n = n;
+    h->nsamples = n < (int64_t)kIndexSamples ? (uint32_t)n : kIndexSamples;
     h->kmin = n > 0 ? keys[0] : 0;
     h->kmax = n > 0 ? keys[n - 1] : 0;
     const uint64_t span = h->kmax - h->kmin;
     h->inv_span = span ? __ddiv_rn(1.0, (double)span) : 0.0;
     h->root_a = (double)L;  // provisional (k_root_final overwrites)
     h->root_b = 0.0;
+}
+
+// The fingerprint: keys at nsamples evenly spaced ranks.
+__global__ void k_index_samples(const uint64_t *__restrict__ keys, int64_t n, char *index) {
+    const IndexHeader &h = *(const IndexHeader *)index;
+    IndexView v;
+    index_layout(index, h.n_leaves, h.nparams, h.root_segs, &v);
+    const uint32_t m = h.nsamples;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < m; s += gridDim.x * blockDim.x)
+        v.samp[s] = keys[sample_rank(s, m, n)];
 }
 
 // Partial least-squares sums of y = rank * L / n on x (fp64).
@@ -391,23 +417,85 @@ __global__ void k_root_knots(const uint64_t *__restrict__ keys, int64_t n, char 
     }
 }
 
-// first[j] = first rank routed to leaf >= j (routing is monotone); first[L] = n.
-__global__ __launch_bounds__(256) void k_leaf_bounds(const uint64_t *__restrict__ keys, int64_t n,
-                                                     const char *index, int64_t *first) {
+// first[j] = first rank routed to a leaf >= j (routing is monotone), so leaf j
+// holds ranks [first[j], first[j + 1]); first[L] = n.  Three passes, each
+// parallel over keys or leaves (an empty leaf takes the next non-empty
+// leaf's first rank, whatever the run of empty leaves):
+//   1. every entry to n;
+//   2. the first key of every run of equal leaf ids writes its rank there;
+//   3. suffix minimum over the L + 1 entries, in tiles of kFirstTile.
+constexpr int kFirstBlock = 1024;
+constexpr int kFirstItems = 4;
+constexpr int kFirstTile = kFirstBlock * kFirstItems;
+
+__global__ __launch_bounds__(256) void k_leaf_first_fill(int64_t *first, int64_t count, int64_t v) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count;
+         j += (int64_t)gridDim.x * blockDim.x)
+        first[j] = v;
+}
+
+__global__ __launch_bounds__(256) void k_leaf_first_scatter(const uint64_t *__restrict__ keys,
+                                                            int64_t n, const char *index,
+                                                            int64_t *first) {
     IndexView v;
     const IndexHeader &h = *(const IndexHeader *)index;
     index_layout((char *)index, h.n_leaves, h.nparams, h.root_segs, &v);
-    const uint32_t L = h.n_leaves;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t lj = route(h, v, v.rx, 1, h.root_segs, keys[i]);
-        const int64_t lp = i > 0 ? (int64_t)route(h, v, v.rx, 1, h.root_segs, keys[i - 1]) : -1;
-        for (int64_t j = lp + 1; j <= lj; ++j) first[j] = i;
-        if (i == n - 1)
-            for (int64_t j = lj + 1; j <= (int64_t)L; ++j) first[j] = n;
+        const uint32_t lj = route(h, v, v.rx, 1, h.root_segs, keys[i]);
+        if (i == 0 || route(h, v, v.rx, 1, h.root_segs, keys[i - 1]) != lj) first[lj] = i;
     }
-    if (n == 0 && blockIdx.x == 0)
-        for (int64_t j = threadIdx.x; j <= (int64_t)L; j += blockDim.x) first[j] = 0;
+}
+
+// Minimum of each tile of first[0 .. count).
+__global__ __launch_bounds__(kFirstBlock) void k_leaf_first_tiles(const int64_t *first,
+                                                                  int64_t count, int64_t *tile_min) {
+    __shared__ int64_t s_w[kFirstBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kFirstTile;
+    int64_t m = INT64_MAX;
+    for (int u = 0; u < kFirstItems; ++u) {
+        const int64_t j = base + (int64_t)threadIdx.x * kFirstItems + u;
+        if (j < count) m = first[j] < m ? first[j] : m;
+    }
+    int64_t tot;
+    block_excl_max<kFirstBlock, int64_t>(-(m == INT64_MAX ? INT64_MAX - 1 : m), INT64_MIN, s_w, &tot);
+    if (threadIdx.x == 0) tile_min[blockIdx.x] = -tot;
+}
+
+// In-place suffix minimum: each tile combines the minimum of the tiles after
+// it (a block reduction over tile_min) with its own entries, scanned from
+// the end (thread t holds the t-th group of kFirstItems entries counted from
+// the tile's end; an exclusive prefix max of the negated group minima over
+// the threads gives each group the minimum of the entries after it).
+__global__ __launch_bounds__(kFirstBlock) void k_leaf_first_suffix(int64_t *first, int64_t count,
+                                                                   const int64_t *tile_min,
+                                                                   int64_t tiles) {
+    __shared__ int64_t s_w[kFirstBlock / 64];
+    const int64_t t = blockIdx.x;
+    int64_t later = INT64_MAX;
+    for (int64_t u = t + 1 + threadIdx.x; u < tiles; u += kFirstBlock)
+        later = tile_min[u] < later ? tile_min[u] : later;
+    int64_t tot;
+    block_excl_max<kFirstBlock, int64_t>(-(later == INT64_MAX ? INT64_MAX - 1 : later), INT64_MIN,
+                                         s_w, &tot);
+    later = -tot;  // minimum over every later tile (INT64_MAX - 1 when none)
+    const int64_t base = t * kFirstTile;
+    const int64_t g0 = base + kFirstTile - (int64_t)(threadIdx.x + 1) * kFirstItems;  // group start
+    int64_t e[kFirstItems];
+    int64_t gm = INT64_MAX - 1;
+    for (int u = 0; u < kFirstItems; ++u) {
+        const int64_t j = g0 + u;
+        e[u] = j < count ? first[j] : INT64_MAX - 1;
+        gm = e[u] < gm ? e[u] : gm;
+    }
+    const int64_t ex = block_excl_max<kFirstBlock, int64_t>(-gm, INT64_MIN, s_w, &tot);
+    int64_t run = ex == INT64_MIN ? INT64_MAX - 1 : -ex;  // minimum of the tile's later groups
+    run = later < run ? later : run;
+    for (int u = kFirstItems - 1; u >= 0; --u) {
+        run = e[u] < run ? e[u] : run;
+        const int64_t j = g0 + u;
+        if (j < count) first[j] = run;
+    }
 }
 
 // Linear leaves, one wave per leaf: least-squares fit, leaf record, window
@@ -439,7 +527,6 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_fit_linear(const uint64_t *
     const uint64_t kf = keys[f0];
     const uint64_t span = keys[f1 - 1] - kf;
     const float isp = span ? __fdiv_rn(1.0f, (float)span) : 0.0f;
-    const float fnj = (float)nj;
     auto xof = [&](int64_t s) -> float {
         return s < kLeafCache ? s_x[s] : __fmul_rn((float)(keys[f0 + s] - kf), isp);
     };
@@ -658,9 +745,20 @@ __global__ __launch_bounds__(kLookupBlock) void k_index_lookup(
                     h.n_leaves >= 1 && h.n_leaves <= kMaxLeaves && h.leaf_kind <= 1 &&
                     h.nparams == (h.leaf_kind ? (uint32_t)kMlpParams : 2u) &&
                     h.root_segs <= 65536 && h.leaf_stride == leaf_stride(h.nparams) &&
+                    h.nsamples == (n < (int64_t)kIndexSamples ? (uint32_t)n : kIndexSamples) &&
                     (n == 0 || (keys[0] == h.kmin && keys[n - 1] == h.kmax));
     IndexView v;
     index_layout((char *)index, h.n_leaves, h.nparams, h.root_segs, &v);
+    // The fingerprint, shared out over the grid: the keys at the sampled
+    // ranks must be the ones the index was trained on.  A difference is
+    // reported (CGA_EMISMATCH); the ranks below stay exact for any sorted
+    // array, because every window is verified.
+    if (ok) {
+        const uint32_t m = h.nsamples;
+        for (uint64_t s = blockIdx.x + (uint64_t)threadIdx.x * gridDim.x; s < m;
+             s += (uint64_t)gridDim.x * blockDim.x)
+            if (keys[sample_rank((uint32_t)s, m, n)] != v.samp[s]) set_err(err, ERR_MISMATCH);
+    }
     // every stride-th segment start, at most kLdsSegs of them, staged in LDS
     const uint32_t R = ok ? h.root_segs : 0;
     const uint32_t stride = R > kLdsSegs ? (R + kLdsSegs - 1) / kLdsSegs : 1;
@@ -686,14 +784,14 @@ __global__ __launch_bounds__(kLookupBlock) void k_index_lookup(
         int64_t lo = p + lh.err_lo, hi = p + lh.err_hi;
         lo = lo < f0 ? f0 : (lo > f1 ? f1 : lo);
         hi = hi < lo ? lo : (hi > f1 ? f1 : hi);
-        // Routing is monotone and the leaf holds exactly the ranks routed to
-        // it, so keys[f0 - 1] < x <= keys[f1] already: a window edge at the
-        // leaf's edge needs no check (with 2^24 leaves most windows are
-        // whole leaves).
-        const bool good = (lo == f0 || keys[lo - 1] < x) && (hi == f1 || keys[hi] >= x);
-        if (good) {
-            r = lb_range(keys, lo, hi, x);  // answer in [lo, hi]
-        } else {
+        // The window [lo, hi] holds the answer iff keys[lo - 1] < x <=
+        // keys[hi] (keys[-1] = -inf, keys[n] = +inf).  Both checks ride on
+        // the search: the lower bound over [lo - 1, hi + 1) lands on lo - 1
+        // exactly when keys[lo - 1] >= x and on hi + 1 exactly when
+        // keys[hi] < x; anything between is the global lower bound.
+        const int64_t sl = lo > 0 ? lo - 1 : 0, sh = hi < n ? hi + 1 : n;
+        r = lb_range(keys, sl, sh, x);
+        if ((lo > 0 && r == lo - 1) || (hi < n && r == hi + 1)) {
             r = lb_range(keys, (int64_t)0, n, x);
             fell = true;
         }
@@ -771,7 +869,8 @@ size_t cga_index_bytes(const cga_index_params *p) {
 size_t cga_index_train_workspace_bytes(const cga_index_params *p, int64_t n) {
     if (!p || n < 0 || p->n_leaves < 1 || p->n_leaves > kMaxLeaves) return 0;
     return kControlBytes + idx_align((size_t)kRootBlocks * 4 * sizeof(double)) +
-           idx_align(((size_t)p->n_leaves + 1) * sizeof(int64_t));
+           idx_align(((size_t)p->n_leaves + 1) * sizeof(int64_t)) +
+           idx_align(((size_t)p->n_leaves + kFirstTile) / kFirstTile * sizeof(int64_t));
 }
 
 int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p, void *d_index,
@@ -788,6 +887,7 @@ int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p
     double *partial = (double *)((char *)d_ws + kControlBytes);
     int64_t *first =
         (int64_t *)((char *)d_ws + kControlBytes + idx_align((size_t)kRootBlocks * 4 * sizeof(double)));
+    int64_t *tile_min = (int64_t *)((char *)first + idx_align(((size_t)p->n_leaves + 1) * sizeof(int64_t)));
     const uint32_t L = p->n_leaves, np = p->leaf_kind ? kMlpParams : 2;
     CGA_TRY(launch_begin(ctl, nullptr, 0, nullptr, 0, nullptr, s));
     char *idx = (char *)d_index;
@@ -796,6 +896,7 @@ int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p
         CGA_PROF("index_root", s);
         k_index_header<<<1, 64, 0, s>>>(d_keys, n, L, p->leaf_kind, np, p->root_segments, h);
         if (n > 0) {
+            k_index_samples<<<kIndexSamples / 256, 256, 0, s>>>(d_keys, n, idx);
             k_root_partial<<<kRootBlocks, 256, 0, s>>>(d_keys, n, h, partial);
             k_root_final<<<1, 256, 0, s>>>(partial, kRootBlocks, n, h);
             if (p->root_segments) {
@@ -808,7 +909,12 @@ int cga_index_train(const uint64_t *d_keys, int64_t n, const cga_index_params *p
     blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
     {
         CGA_PROF("index_bounds", s);
-        k_leaf_bounds<<<(unsigned)blocks, 256, 0, s>>>(d_keys, n, idx, first);
+        const int64_t cnt = (int64_t)L + 1, tiles = (cnt + kFirstTile - 1) / kFirstTile;
+        const int64_t fb = (cnt + 255) / 256 < 4096 ? (cnt + 255) / 256 : 4096;
+        k_leaf_first_fill<<<(unsigned)fb, 256, 0, s>>>(first, cnt, n);
+        if (n > 0) k_leaf_first_scatter<<<(unsigned)blocks, 256, 0, s>>>(d_keys, n, idx, first);
+        k_leaf_first_tiles<<<(unsigned)tiles, kFirstBlock, 0, s>>>(first, cnt, tile_min);
+        k_leaf_first_suffix<<<(unsigned)tiles, kFirstBlock, 0, s>>>(first, cnt, tile_min, tiles);
     }
     {
         CGA_PROF("index_fit", s);

@@ -493,14 +493,18 @@ constexpr int knn_waves_per_eu() {
 }
 
 // One query per team of kTeam lanes.  LIST is PackedList (depth <= 15) or
-// WideList.
-template <int KT, class LIST>
+// WideList.  kCount (a measurement build, same results): every lane counts
+// its node-word loads, dense-table loads, voxels whose distance it took and
+// loop steps, summed into work[0..3].
+template <int KT, class LIST, bool kCount = false>
 __global__ __launch_bounds__(kKnnBlock) __attribute__((amdgpu_waves_per_eu(knn_waves_per_eu<KT, LIST>())))
 void k_knn_tree(
     const uint64_t *__restrict__ node, const uint32_t *__restrict__ dense,
     const int64_t *__restrict__ lvl, int64_t nodes_max, const float *__restrict__ q, int64_t nq,
     const uint64_t *__restrict__ order, float o0, float o1, float o2, float scale, uint32_t depth,
-    int k, int la, int64_t *__restrict__ idx_out, uint64_t *__restrict__ d2_out, uint32_t *err) {
+    int k, int la, int64_t *__restrict__ idx_out, uint64_t *__restrict__ d2_out, uint32_t *err,
+    unsigned long long *work = nullptr) {
+    uint32_t c_node = 0, c_dense = 0, c_vox = 0, c_step = 0;  // kCount only
     using Dist = typename LIST::Dist;
     extern __shared__ uint64_t s_word[];  // open node word per level, one column per thread
     __shared__ unsigned long long s_bound[kTeamsPerBlock];
@@ -550,6 +554,7 @@ void k_knn_tree(
         return gx * gx + gy * gy + gz * gz;
     };
     auto offer = [&](Dist d, int32_t i) __attribute__((always_inline)) {
+        if (kCount) ++c_vox;
         list.offer(d, i);
         kth = list.kth(k);
         if (kth < s_bound[team]) atomicMin(&s_bound[team], (unsigned long long)kth);
@@ -574,6 +579,7 @@ void k_knn_tree(
         int64_t nj;
         if (dt > 0 && l <= dt) {
             const uint32_t v = dense[enc3(x >> dt, y >> dt, z >> dt, 7, false)];
+            if (kCount) ++c_dense;
             if (!v) return -1;
             nj = (int64_t)v - 1;
             L = dt;
@@ -583,6 +589,7 @@ void k_knn_tree(
         }
         while (L > l) {
             const uint64_t w = node[s_base[L] + nj];
+            if (kCount) ++c_node;
             --L;
             const uint32_t oc = (((x >> L) & 1u) << 2) | (((y >> L) & 1u) << 1) | ((z >> L) & 1u);
             if (!((w >> oc) & 1u)) return -1;
@@ -645,6 +652,7 @@ void k_knn_tree(
             }
         } else {
             s_sw[tid] = cn >= 0 ? node[s_base[ls] + cn] : 0ull;
+            if (kCount) c_node += cn >= 0 ? 1u : 0u;
             s_sc[tid] = (uint64_t)c[0] | ((uint64_t)c[1] << 21) | ((uint64_t)c[2] << 42);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -707,6 +715,7 @@ void k_knn_tree(
             // into it.  Starting, climbing and descending share one node-entry
             // tail, so a wave whose lanes take different paths runs it once.
             for (;;) {
+                if (kCount) ++c_step;
                 const bool up = pm == 0;
                 bool moved = false, climbed = false;
                 uint32_t done_oc = 0;
@@ -725,6 +734,7 @@ void k_knn_tree(
                             offer(bd, ci);
                         } else {
                             w = node[s_base[l0] + ci];
+                            if (kCount) ++c_node;
                             s_word[l0 * kKnnBlock + tid] = w;
                             x0 = cx;
                             y0 = cy;
@@ -756,6 +766,7 @@ void k_knn_tree(
                             bnd = kth < (uint64_t)bnd ? to_dist(kth) : bnd;
                         } else {
                             w = node[s_base[cl] + ci];
+                            if (kCount) ++c_node;
                             s_word[cl * kKnnBlock + tid] = w;
                             l = cl;
                             x0 = cx;
@@ -837,6 +848,21 @@ void k_knn_tree(
             list.out(s, idx, d2);
             idx_out[j * k + s] = idx;
             d2_out[j * k + s] = d2;
+        }
+    }
+    if (kCount) {  // the team's sums, one atomic per counter per query
+#pragma unroll
+        for (int o = 1; o < kTeam; o <<= 1) {
+            c_node += __shfl_xor(c_node, o, 64);
+            c_dense += __shfl_xor(c_dense, o, 64);
+            c_vox += __shfl_xor(c_vox, o, 64);
+            c_step += __shfl_xor(c_step, o, 64);
+        }
+        if (tl == 0) {
+            atomicAdd(&work[0], (unsigned long long)c_node);
+            atomicAdd(&work[1], (unsigned long long)c_dense);
+            atomicAdd(&work[2], (unsigned long long)c_vox);
+            atomicAdd(&work[3], (unsigned long long)c_step);
         }
     }
 }
@@ -951,20 +977,32 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
                                                     L.nodes, emit, occ, occ_cap, counts, &L.ctl->err);
 }
 
-template <int KT>
+template <int KT, bool kCount = false>
 static void knn_launch(const cga_grid *g, const KnnLayout &L, const float *q, int64_t nq, int k,
-                       int64_t *idx, uint64_t *d2, hipStream_t s) {
-    CGA_PROF("knn", s);
+                       int64_t *idx, uint64_t *d2, hipStream_t s,
+                       unsigned long long *work = nullptr) {
+    CGA_PROF(kCount ? "knn_count" : "knn", s);
     const size_t lds = (size_t)(g->depth + 1) * kKnnBlock * sizeof(uint64_t);
     const unsigned blocks = (unsigned)((nq + kTeamsPerBlock - 1) / kTeamsPerBlock);
     if (g->depth <= kPackedDepth)
-        k_knn_tree<KT, PackedList<KT>><<<blocks, kKnnBlock, lds, s>>>(
+        k_knn_tree<KT, PackedList<KT>, kCount><<<blocks, kKnnBlock, lds, s>>>(
             L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
-            g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err);
+            g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err, work);
     else
-        k_knn_tree<KT, WideList<KT>><<<blocks, kKnnBlock, lds, s>>>(
+        k_knn_tree<KT, WideList<KT>, kCount><<<blocks, kKnnBlock, lds, s>>>(
             L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
-            g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err);
+            g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err, work);
+}
+
+template <bool kCount>
+static void knn_dispatch(const cga_grid *g, const KnnLayout &L, const float *q, int64_t nq, int k,
+                         int64_t *idx, uint64_t *d2, hipStream_t s, unsigned long long *work) {
+    if (k <= 1) knn_launch<1, kCount>(g, L, q, nq, k, idx, d2, s, work);
+    else if (k <= 2) knn_launch<2, kCount>(g, L, q, nq, k, idx, d2, s, work);
+    else if (k <= 4) knn_launch<4, kCount>(g, L, q, nq, k, idx, d2, s, work);
+    else if (k <= 8) knn_launch<8, kCount>(g, L, q, nq, k, idx, d2, s, work);
+    else if (k <= 16) knn_launch<16, kCount>(g, L, q, nq, k, idx, d2, s, work);
+    else knn_launch<32, kCount>(g, L, q, nq, k, idx, d2, s, work);
 }
 
 // ---------------------------------------------------------- binary lookup
@@ -993,9 +1031,9 @@ size_t cga_knn_workspace_bytes(const cga_grid *g, int64_t n, int64_t nq) {
     return knn_layout(nullptr, n, g->depth, knn_order(nq) ? nq : 0).bytes;
 }
 
-int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n, const float *d_q,
-            int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2, void *d_ws, size_t ws_bytes,
-            cga_stream stream) {
+static int knn_call(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n,
+                    const float *d_q, int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2, void *d_ws,
+                    size_t ws_bytes, cga_stream stream, unsigned long long *work) {
     if (!grid_valid(g) || n < 0 || n > INT32_MAX || nq < 0 || k < 1 || k > 32 || !d_ws)
         return CGA_EINVAL;
     if (nq > 0 && (!d_q || !d_idx || !d_d2)) return CGA_EINVAL;
@@ -1028,15 +1066,25 @@ int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n
             tree_build<uint64_t>(L, (const uint64_t *)d_keys, n, d_n, g->depth, s);
         else
             tree_build<uint32_t>(L, (const uint32_t *)d_keys, n, d_n, g->depth, s);
-        if (k <= 1) knn_launch<1>(g, L, d_q, nq, k, d_idx, d_d2, s);
-        else if (k <= 2) knn_launch<2>(g, L, d_q, nq, k, d_idx, d_d2, s);
-        else if (k <= 4) knn_launch<4>(g, L, d_q, nq, k, d_idx, d_d2, s);
-        else if (k <= 8) knn_launch<8>(g, L, d_q, nq, k, d_idx, d_d2, s);
-        else if (k <= 16) knn_launch<16>(g, L, d_q, nq, k, d_idx, d_d2, s);
-        else knn_launch<32>(g, L, d_q, nq, k, d_idx, d_d2, s);
+        if (work) knn_dispatch<true>(g, L, d_q, nq, k, d_idx, d_d2, s, work);
+        else knn_dispatch<false>(g, L, d_q, nq, k, d_idx, d_d2, s, nullptr);
         CGA_HIP(hipGetLastError());
     }
     return CGA_OK;
+}
+
+int cga_knn(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n, const float *d_q,
+            int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2, void *d_ws, size_t ws_bytes,
+            cga_stream stream) {
+    return knn_call(g, d_keys, n, d_n, d_q, nq, k, d_idx, d_d2, d_ws, ws_bytes, stream, nullptr);
+}
+
+int cga_knn_count(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n,
+                  const float *d_q, int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2,
+                  uint64_t *d_work, void *d_ws, size_t ws_bytes, cga_stream stream) {
+    if (!d_work) return CGA_EINVAL;
+    return knn_call(g, d_keys, n, d_n, d_q, nq, k, d_idx, d_d2, d_ws, ws_bytes, stream,
+                    (unsigned long long *)d_work);
 }
 
 size_t cga_occupancy_workspace_bytes(const cga_grid *g, int64_t n) {

@@ -7,8 +7,8 @@ runs on the GPU at the workloads' full sizes:
 
 * c2: 2 x 1,048,576 LiDAR points, depth 12, 100k queries, k = 8 -- compared
   with the oracle itself (std::map build, std::set_union merge, coordinate
-  drop), k-NN rows on a seeded sample of 2000 queries with the oracle's kd-tree
-  over the whole union, and every lookup with std::lower_bound.
+  drop), every one of the 100k k-NN rows with the oracle's kd-tree over the
+  whole union, and every lookup with std::lower_bound.
 * c2 again on a LINEAR grid: the paper's NN on the five arrays for all 100k
   queries against the kd-tree 1-NN, and its three-level lookup on 200k voxels.
 * c6: the temporal-prediction step on the full moving-object frame pair,
@@ -18,11 +18,14 @@ runs on the GPU at the workloads' full sizes:
 * c5: the 50M-key learned index (linear and network leaves) -- all 10M
   lookups against std::lower_bound.
 * c3: 2 x 10M points, depth 14, 1M queries, k = 16 -- build, merge and the
-  three projections compared with the definitions the oracle states (its
+  step's three projections compared with the definitions the oracle states (its
   per-point quantize and key encode, each deduplicated with numpy: a set of
   keys with multiplicities, a set union, the image under a coordinate drop),
-  k-NN rows on 32 sampled queries with oracle brute force over the ~20M-voxel
-  union, and a sample of lookups with std::lower_bound.
+  k-NN rows of 4096 queries -- 3584 drawn uniformly from the million and
+  the 512 nearest the sphere's centre (those see the whole shell at nearly
+  one distance and take the search's most rounds) -- with the oracle's
+  kd-tree over the ~20M-voxel union, 32 of them (16 near the centre) also by
+  brute force, and a sample of lookups with std::lower_bound.
 """
 import numpy as np
 import pytest
@@ -36,12 +39,11 @@ from helpers import say, u64
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 
-def _run_step(cga, d):
-    pipe = bench.Pipeline(cga, d, torch.device("cuda:0"))
+def _run_step(cga, d, workload):
+    pipe = bench.Pipeline(cga, d, torch.device("cuda:0"), bench.WORKLOADS[workload][1])
     pipe.step()
     torch.cuda.synchronize()
     pipe.check()
-    pipe.nu = int(pipe.cnt[2].item())
     pipe.make_lookups()
     pipe.step_concurrent()  # the timed form: independent parts on side streams
     torch.cuda.synchronize()
@@ -78,7 +80,7 @@ def test_c2_full(gpu):
     d = gen.c2_lidar()
     g = d["grid"]
     say("c2 full: build/merge/project/knn/index at 2 x 1048576 points")
-    pipe = _run_step(cga, d)
+    pipe = _run_step(cga, d, "c2")
     ua, ub, um, up = [int(x) for x in pipe.cnt.cpu().tolist()]
     ka, ca = oracle.build(d["a"], g)
     kb, cb = oracle.build(d["b"], g)
@@ -89,10 +91,12 @@ def test_c2_full(gpu):
     m, _ = oracle.merge(ka, kb, g.depth, g.key_mode)
     np.testing.assert_array_equal(_keys(pipe.m, um), m)
     p, pc = oracle.project(m, g.depth, g.key_mode, 2)
-    np.testing.assert_array_equal(u64(pipe.p[:up]), p)
-    np.testing.assert_array_equal(pipe.pc[:up].cpu().numpy(), pc)
-    rows = np.sort(np.random.default_rng(2002).choice(len(d["q"]), 2000, replace=False))
-    idx_ref, d2_ref = oracle.knn_kdtree(m, d["q"][rows], g, d["k"])
+    np.testing.assert_array_equal(u64(pipe.p[0][:up]), p)
+    np.testing.assert_array_equal(pipe.pc[0][:up].cpu().numpy(), pc)
+    # every query row, by the kd-tree over the whole union
+    idx_ref, d2_ref = oracle.knn_kdtree(m, d["q"], g, d["k"])
+    rows = np.arange(len(d["q"]))
+    assert len(rows) == 100_000
     _check_knn_rows(pipe, rows, idx_ref, d2_ref)
     _check_lookups(pipe, m)
 
@@ -109,13 +113,27 @@ def _defined_project(m, g, drop):
     return np.unique(pk, return_counts=True)
 
 
+def c3_knn_rows(q, n_uniform=3584, n_centre=512, seed=2003):
+    """The k-NN rows checked at full c3 size: a seeded uniform sample of the
+    queries plus the n_centre queries nearest the sphere's centre (the
+    origin), sorted and distinct."""
+    r = np.linalg.norm(q.astype(np.float64), axis=1)
+    centre = np.argsort(r, kind="stable")[:n_centre]
+    assert r[centre[-1]] < 0.2
+    rest = np.setdiff1d(np.arange(len(q)), centre)
+    uni = np.random.default_rng(seed).choice(rest, n_uniform, replace=False)
+    return np.sort(np.concatenate([centre, uni]))
+
+
 def test_c3_full(gpu):
     cga = gpu
     d = gen.c3_bumpy()
     g = d["grid"]
     say("c3 full: build/merge/project/knn/index at 2 x 10M points")
-    pipe = _run_step(cga, d)
-    ua, ub, um, up = [int(x) for x in pipe.cnt.cpu().tolist()]
+    pipe = _run_step(cga, d, "c3")
+    cnt = [int(x) for x in pipe.cnt.cpu().tolist()]
+    ua, ub, um = cnt[:3]
+    assert pipe.drops == (0, 1, 2)
     ka, ca = _defined_build(d["a"], g)
     np.testing.assert_array_equal(_keys(pipe.ka, ua), ka)
     np.testing.assert_array_equal(pipe.ca[:ua].cpu().numpy(), ca)
@@ -124,17 +142,23 @@ def test_c3_full(gpu):
     np.testing.assert_array_equal(pipe.cb[:ub].cpu().numpy(), cb)
     m = np.union1d(ka, kb)
     np.testing.assert_array_equal(_keys(pipe.m, um), m)
-    p, pc = _defined_project(m, g, 2)
-    np.testing.assert_array_equal(u64(pipe.p[:up]), p)
-    np.testing.assert_array_equal(pipe.pc[:up].cpu().numpy(), pc)
-    for drop in (0, 1):  # the other two axis projections of the workload
-        gk, gc = cga.cga_project(pipe.m[:um], g, drop)
+    for i, drop in enumerate(pipe.drops):  # the step's three axis projections
         pk, pcnt = _defined_project(m, g, drop)
-        np.testing.assert_array_equal(u64(gk), pk)
-        np.testing.assert_array_equal(gc.cpu().numpy(), pcnt)
-    rows = np.sort(np.random.default_rng(2003).choice(len(d["q"]), 32, replace=False))
-    idx_ref, d2_ref = oracle.knn_brute(m, d["q"][rows], g, d["k"])
+        up = cnt[3 + i]
+        np.testing.assert_array_equal(u64(pipe.p[i][:up]), pk)
+        np.testing.assert_array_equal(pipe.pc[i][:up].cpu().numpy(), pcnt)
+    rows = c3_knn_rows(d["q"])
+    assert len(rows) == 4096
+    say("c3 full: kd-tree k-NN of", len(rows), "rows")
+    idx_ref, d2_ref = oracle.knn_kdtree(m, d["q"][rows], g, d["k"])
     _check_knn_rows(pipe, rows, idx_ref, d2_ref)
+    # a brute-force cross-check of the kd-tree on 32 of them, half near the centre
+    near = rows[np.linalg.norm(d["q"][rows].astype(np.float64), axis=1) < 0.2]
+    assert len(near) >= 16
+    sub = np.sort(np.concatenate([near[:16], rows[~np.isin(rows, near)][::224][:16]]))
+    say("c3 full: brute-force k-NN of", len(sub), "rows")
+    idx_b, d2_b = oracle.knn_brute(m, d["q"][sub], g, d["k"])
+    _check_knn_rows(pipe, sub, idx_b, d2_b)
     _check_lookups(pipe, m, sample=np.arange(0, len(pipe.lq), 7))
 
 

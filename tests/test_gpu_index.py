@@ -78,11 +78,13 @@ def test_lookup_small_arrays(gpu):
 def _window_offsets(n_leaves, nparams, root):
     """Byte offsets of every leaf's err_lo / err_hi in the index buffer: a
     256-byte header, the root segment starts (8 B each) and segments (32 B
-    each), then one record per leaf (64 B for linear leaves, 256 B for
-    network leaves) whose window sits at bytes 24 and 28."""
+    each), the 4096-key fingerprint (8 B each), then one record per leaf (64 B
+    for linear leaves, 256 B for network leaves) whose window sits at bytes
+    24 and 28."""
     al = lambda v: (v + 255) // 256 * 256
     off = al(256 + root * 8)
     off = al(off + root * 32)
+    off = al(off + 4096 * 8)
     stride = 64 if nparams <= 8 else 256
     base = off + np.arange(n_leaves) * stride
     return base + 24, base + 28
@@ -118,6 +120,51 @@ def test_mismatched_keys_rejected(gpu, lidar_keys):
     with pytest.raises(gpu.CgaError) as e:
         gpu.cga_index_lookup(idx, _t(keys[:-1]), _t(keys[:10]))
     assert e.value.status == gpu.EMISMATCH
+
+
+def _same_ends(keys, seed):
+    """Another sorted unique array with the same size and the same first and
+    last keys: every interior key redrawn uniformly between them."""
+    rng = np.random.default_rng(seed)
+    inner = np.unique(rng.integers(keys[0] + np.uint64(1), keys[-1], 2 * len(keys), dtype=np.uint64))
+    inner = np.sort(rng.choice(inner, len(keys) - 2, replace=False))
+    out = np.concatenate([keys[:1], inner, keys[-1:]])
+    assert len(out) == len(keys) and (np.diff(out) > 0).all()
+    return out
+
+
+@pytest.mark.parametrize("kind,leaves,root", [(0, 4096, 0), (1, 4096, 1024), (0, 1 << 20, 4096)])
+def test_same_size_same_ends_other_keys(gpu, lidar_keys, kind, leaves, root):
+    """An array with the index's n, first and last key but other interior
+    keys: the lookup reports CGA_EMISMATCH (the fingerprint ranks differ),
+    and its ranks are still the exact lower bounds in that array (every
+    window is verified against the array it searches)."""
+    keys = lidar_keys
+    other = _same_ends(keys, 31 + kind)
+    idx = gpu.cga_index_train(_t(keys), n_leaves=leaves, leaf_kind=kind, epochs=10,
+                              root_segments=root)
+    q = _queries(other, 100_000, 13)
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_index_lookup(idx, _t(other), _t(q))
+    assert e.value.status == gpu.EMISMATCH
+    ws = gpu.Workspaces()
+    r, f, fb = gpu.cga_index_lookup(idx, _t(other), _t(q), sync=False, ws=ws)
+    torch.cuda.synchronize()
+    wr, wf = oracle.lower_bound(other, q)
+    assert np.array_equal(r.cpu().numpy(), wr) and np.array_equal(f.cpu().numpy(), wf)
+    assert int(fb.item()) > 0
+    # one interior key changed at a sampled rank is caught as well
+    one = keys.copy()
+    mid = (2048 * (len(keys) - 1)) // 4095
+    assert keys[mid - 1] + np.uint64(1) < keys[mid]
+    one[mid] = keys[mid] - np.uint64(1)
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_index_lookup(idx, _t(one), _t(q))
+    assert e.value.status == gpu.EMISMATCH
+    # the trained array itself passes
+    r, f, _ = gpu.cga_index_lookup(idx, _t(keys), _t(q))
+    wr, wf = oracle.lower_bound(keys, q)
+    assert np.array_equal(r.cpu().numpy(), wr) and np.array_equal(f.cpu().numpy(), wf)
 
 
 def test_mlp_gradient_matches_fp64_oracle(gpu):

@@ -416,6 +416,42 @@ def test_knn_query_order_auto(gpu, w_c2s):
     np.testing.assert_array_equal(idx.cpu().numpy()[rows], widx)
 
 
+@pytest.mark.parametrize("k", [1, 8, 16])
+def test_knn_count_same_results(gpu, w_c2s, k):
+    """The counting build of the search returns the rows of cga_knn (checked
+    against the kd-tree) and deterministic work totals: at least one node
+    load and loop step per query and at least k offered voxels per query."""
+    g = w_c2s["grid"]
+    ka, _ = gpu.cga_build(dev(w_c2s["a"]), g)
+    q = dev(w_c2s["q"])
+    idx, d2 = gpu.cga_knn(ka, q, g, k)
+    ci, cd, w1 = gpu.cga_knn_count(ka, q, g, k)
+    assert torch.equal(ci, idx) and torch.equal(cd, d2)
+    _, _, w2 = gpu.cga_knn_count(ka, q, g, k)
+    assert w1 == w2
+    nq = len(w_c2s["q"])
+    assert w1["node_loads"] >= nq and w1["steps"] >= nq and w1["voxels_offered"] >= k * nq
+    widx, wd2 = oracle.knn_kdtree(u64(ka), w_c2s["q"], g, k)
+    assert np.array_equal(ci.cpu().numpy(), widx) and np.array_equal(cd.cpu().numpy().view(np.uint64), wd2)
+
+
+def test_stream_probe_copies(gpu):
+    """The bandwidth probe's copy writes exactly its source; its read mode
+    writes nothing."""
+    n = (64 << 20) + 16 * 1001
+    src = torch.randint(-2 ** 31, 2 ** 31 - 1, (n // 4,), dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    for blocks in (1, 977, 4096):
+        dst.zero_()
+        gpu.cga_stream_probe(src, dst, n, 0, blocks)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+    sink = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    gpu.cga_stream_probe(src, sink, n, 1, 4096)
+    torch.cuda.synchronize()
+    assert int(sink.item()) == 7 or int(sink.item()) == 0x9E3779B9 - 2 ** 32
+
+
 # --------------------------------------------------------------- occupancy
 def _check_occupancy(gpu, keys_gpu, g):
     codes, counts = gpu.cga_occupancy(keys_gpu, g)
