@@ -16,8 +16,10 @@
  *    *_host pointers are host pointers.  The library never allocates or frees
  *    device memory; calls that need scratch space take a caller-owned
  *    workspace (d_ws, ws_bytes) whose minimum size the matching
- *    *_workspace_bytes function returns.  A workspace may be reused by later
- *    calls on the same stream, never by two calls in flight at once.
+ *    *_workspace_bytes function returns (one call, cga_merge_noalloc, uses
+ *    a static device array of the library instead).  A workspace may be
+ *    reused by later calls on the same stream, never by two calls in flight
+ *    at once.
  *  - All work is enqueued on `stream` (a hipStream_t; NULL = default stream)
  *    and the call returns without waiting, unless a *_host output pointer is
  *    non-NULL: then the call synchronises the stream, fills it, and also
@@ -213,6 +215,24 @@ int cga_merge(const cga_grid *grid, const void *d_a, int64_t na, const int64_t *
               const void *d_b, int64_t nb, const int64_t *d_nb, void *d_out, uint8_t *d_src,
               int64_t cap, int64_t *d_n_out, int64_t *n_out_host, void *d_ws, size_t ws_bytes,
               cga_stream stream);
+
+/* The same merge with no workspace argument and no allocation, for callers
+ * that cannot allocate device memory (code under hipGraph capture, serving
+ * loops, harnesses that forbid hipMalloc).  Its scratch space is a static
+ * device array of the library (about 2 MiB, one copy per GPU, held until the
+ * process ends), found for the current device on its first call there; the
+ * current device must be the stream's.  Inputs, outputs and results are as
+ * for cga_merge.  na + nb above CGA_MERGE_NOALLOC_MAX_KEYS: CGA_EWORKSPACE,
+ * before anything is enqueued.  Every call on one GPU shares that array:
+ * calls that overlap in time on one GPU (two streams, two host threads) race
+ * and give undefined results; calls in stream order are safe.  Device errors
+ * (CGA_ECAPACITY) come back only through n_out_host (and a device count above
+ * cap in d_n_out). */
+#define CGA_MERGE_NOALLOC_MAX_KEYS ((int64_t)1 << 28)
+int cga_merge_noalloc(const cga_grid *grid, const void *d_a, int64_t na, const int64_t *d_na,
+                      const void *d_b, int64_t nb, const int64_t *d_nb, void *d_out,
+                      uint8_t *d_src, int64_t cap, int64_t *d_n_out, int64_t *n_out_host,
+                      cga_stream stream);
 
 /* ------------------------------------------------------------- projection
  * Orthogonal projection, Eq. (3) with m_x = m_y = 1 (Section V-B), along

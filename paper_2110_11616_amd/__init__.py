@@ -87,6 +87,9 @@ _sig("cga_temporal_predict", ctypes.c_int, _GP, _P, _P, _I64, _P, _P, _I64, ctyp
 _sig("cga_merge_workspace_bytes", _SZ, _GP, _I64, _I64)
 _sig("cga_merge", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _P, _P, _I64, _P, _I64P, _P, _SZ,
      _P)
+_sig("cga_merge_noalloc", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _P, _P, _I64, _P, _I64P,
+     _P)
+MERGE_NOALLOC_MAX_KEYS = 1 << 28
 _sig("cga_project_workspace_bytes", _SZ, _GP, _I64)
 _sig("cga_project", ctypes.c_int, _GP, _P, _I64, _P, ctypes.c_int, _P, _P, _I64, _P, _I64P, _P,
      _SZ, _TP, _P)
@@ -373,6 +376,30 @@ def cga_merge(a: torch.Tensor, b: torch.Tensor, grid, *, src: bool = False, cap=
                        _ptr(s), cap, _ptr(d_n_out), ctypes.byref(h) if sync else None, _ptr(wsb),
                        wsb.numel(), _stream(stream))
     _check(rc, "cga_merge")
+    if sync:
+        u = h.value
+        return out[:u], (s[:u] if s is not None else None)
+    return out, s, d_n_out
+
+
+def cga_merge_noalloc(a: torch.Tensor, b: torch.Tensor, grid, *, src: bool = False, cap=None,
+                      na=None, d_na=None, nb=None, d_nb=None, out=None, src_out=None,
+                      d_n_out=None, sync: bool = True, stream=None):
+    """cga_merge over the library's static scratch array (no workspace, no
+    allocation inside the call; na + nb <= MERGE_NOALLOC_MAX_KEYS).  Returns
+    what cga_merge returns; the output tensors are allocated here unless given."""
+    na = a.shape[0] if na is None else int(na)
+    nb = b.shape[0] if nb is None else int(nb)
+    g = grid_struct(grid)
+    cap = na + nb if cap is None else int(cap)
+    dev = a.device
+    out = out if out is not None else _cap_tensor(cap, key_dtype(grid), dev)
+    s = src_out if src_out is not None else (_cap_tensor(cap, torch.uint8, dev) if src else None)
+    h = _hostcount()
+    rc = lib.cga_merge_noalloc(ctypes.byref(g), _ptr(a), na, _ptr(d_na), _ptr(b), nb, _ptr(d_nb),
+                               _ptr(out), _ptr(s), cap, _ptr(d_n_out),
+                               ctypes.byref(h) if sync else None, _stream(stream))
+    _check(rc, "cga_merge_noalloc")
     if sync:
         u = h.value
         return out[:u], (s[:u] if s is not None else None)

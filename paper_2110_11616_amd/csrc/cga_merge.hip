@@ -7,6 +7,8 @@
 #include "cga_common.h"
 #include "cga_merge.h"
 
+#include <mutex>
+
 namespace cga {
 
 template <typename K>
@@ -74,24 +76,12 @@ static void merge_enqueue(const K *a, int64_t na, const int64_t *d_na, const K *
                                                        &L.ctl->err);
 }
 
-}  // namespace cga
-
-using namespace cga;
-
-extern "C" {
-
-size_t cga_merge_workspace_bytes(const cga_grid *g, int64_t na, int64_t nb) {
-    if (!grid_valid(g) || na < 0 || nb < 0) return 0;
-    return merge_layout(nullptr, na, nb).bytes;
-}
-
-int cga_merge(const cga_grid *g, const void *d_a, int64_t na, const int64_t *d_na, const void *d_b,
-              int64_t nb, const int64_t *d_nb, void *d_out, uint8_t *d_src, int64_t cap,
-              int64_t *d_n_out, int64_t *n_out_host, void *d_ws, size_t ws_bytes,
-              cga_stream stream) {
-    if (!grid_valid(g) || na < 0 || nb < 0 || cap < 0 || !d_ws) return CGA_EINVAL;
-    if ((na > 0 && !d_a) || (nb > 0 && !d_b) || (na + nb > 0 && !d_out)) return CGA_EINVAL;
-    if (na + nb >= ((int64_t)1 << 31)) return CGA_EUNSUPPORTED;
+// The merge body shared by cga_merge and cga_merge_noalloc; d_ws is the
+// workspace device address (a caller buffer or the static scratch array).
+static int merge_call(const cga_grid *g, const void *d_a, int64_t na, const int64_t *d_na,
+                      const void *d_b, int64_t nb, const int64_t *d_nb, void *d_out, uint8_t *d_src,
+                      int64_t cap, int64_t *d_n_out, int64_t *n_out_host, void *d_ws,
+                      size_t ws_bytes, cga_stream stream) {
     MergeLayout L = merge_layout(d_ws, na, nb);
     if (ws_bytes < L.bytes) return CGA_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
@@ -113,6 +103,76 @@ int cga_merge(const cga_grid *g, const void *d_a, int64_t na, const int64_t *d_n
         return st;
     }
     return CGA_OK;
+}
+
+static bool merge_args_valid(const cga_grid *g, const void *d_a, int64_t na, const void *d_b,
+                             int64_t nb, const void *d_out, int64_t cap) {
+    if (!grid_valid(g) || na < 0 || nb < 0 || cap < 0) return false;
+    return !((na > 0 && !d_a) || (nb > 0 && !d_b) || (na + nb > 0 && !d_out));
+}
+
+// Workspace of cga_merge_noalloc: a file-scope device array, one copy per
+// GPU, sized for CGA_MERGE_NOALLOC_MAX_KEYS merged positions (a control
+// block, then one partition and one look-back word per 2048-key window).
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address); it uses the address hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+constexpr size_t kMergeScratchBytes = (size_t)2 << 20 | 4096;
+static __device__ __align__(256) char scratch[kMergeScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static int merge_scratch(void **out) {
+    int dev = -1;
+    CGA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return CGA_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        CGA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return CGA_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CGA_OK;
+}
+
+}  // namespace cga
+
+using namespace cga;
+
+extern "C" {
+
+size_t cga_merge_workspace_bytes(const cga_grid *g, int64_t na, int64_t nb) {
+    if (!grid_valid(g) || na < 0 || nb < 0) return 0;
+    return merge_layout(nullptr, na, nb).bytes;
+}
+
+int cga_merge(const cga_grid *g, const void *d_a, int64_t na, const int64_t *d_na, const void *d_b,
+              int64_t nb, const int64_t *d_nb, void *d_out, uint8_t *d_src, int64_t cap,
+              int64_t *d_n_out, int64_t *n_out_host, void *d_ws, size_t ws_bytes,
+              cga_stream stream) {
+    if (!merge_args_valid(g, d_a, na, d_b, nb, d_out, cap) || !d_ws) return CGA_EINVAL;
+    if (na + nb >= ((int64_t)1 << 31)) return CGA_EUNSUPPORTED;
+    return merge_call(g, d_a, na, d_na, d_b, nb, d_nb, d_out, d_src, cap, d_n_out, n_out_host, d_ws,
+                      ws_bytes, stream);
+}
+
+int cga_merge_noalloc(const cga_grid *g, const void *d_a, int64_t na, const int64_t *d_na,
+                      const void *d_b, int64_t nb, const int64_t *d_nb, void *d_out,
+                      uint8_t *d_src, int64_t cap, int64_t *d_n_out, int64_t *n_out_host,
+                      cga_stream stream) {
+    if (!merge_args_valid(g, d_a, na, d_b, nb, d_out, cap)) return CGA_EINVAL;
+    if (na > CGA_MERGE_NOALLOC_MAX_KEYS || nb > CGA_MERGE_NOALLOC_MAX_KEYS - na)
+        return CGA_EWORKSPACE;
+    static_assert(CGA_MERGE_NOALLOC_MAX_KEYS % kMergeTile == 0, "whole windows");
+    if (merge_layout(nullptr, CGA_MERGE_NOALLOC_MAX_KEYS, 0).bytes > kMergeScratchBytes)
+        return CGA_EWORKSPACE;  // unreachable: the array holds the largest layout
+    void *ws = nullptr;
+    CGA_TRY(merge_scratch(&ws));
+    return merge_call(g, d_a, na, d_na, d_b, nb, d_nb, d_out, d_src, cap, d_n_out, n_out_host, ws,
+                      kMergeScratchBytes, stream);
 }
 
 }  // extern "C"

@@ -131,3 +131,28 @@ def test_host_validation_before_any_launch(lib):
                              fake, None, None, None, None, fake, 1 << 30, None) == EMISMATCH
     lib.cga_strerror.restype = ctypes.c_char_p
     assert lib.cga_strerror(-4) == b"non-finite coordinate"
+
+
+def test_merge_noalloc_rejects_sizes_beyond_its_static_scratch(lib):
+    """cga_merge_noalloc (no workspace argument) refuses more than
+    CGA_MERGE_NOALLOC_MAX_KEYS merged positions, and bad arguments, on the
+    host, before it touches the device."""
+    P, I64 = ctypes.c_void_p, ctypes.c_int64
+    lib.cga_merge_noalloc.argtypes = [P, P, I64, P, P, I64, P, P, P, I64, P, P, P]
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+    EINVAL, EWORKSPACE = -1, -6
+    text = open(HEADER).read()
+    cap = int(re.search(r"CGA_MERGE_NOALLOC_MAX_KEYS \(\(int64_t\)1 << (\d+)\)", text).group(1))
+    mx = 1 << cap
+    g = grid(12)
+    call = lambda na, nb, gg=g, a=fake, out=fake: lib.cga_merge_noalloc(
+        ctypes.byref(gg), a, na, None, fake, nb, None, out, None, min(max(na + nb, 0), 1 << 62),
+        None, None, None)
+    assert call(mx, 1) == EWORKSPACE
+    assert call(1, mx) == EWORKSPACE
+    assert call(mx // 2 + 1, mx // 2) == EWORKSPACE
+    assert call(1 << 62, 1 << 62) == EWORKSPACE
+    assert call(-1, 5) == EINVAL
+    assert call(5, 5, gg=grid(0)) == EINVAL
+    assert call(5, 5, a=None) == EINVAL
+    assert call(5, 5, out=None) == EINVAL
