@@ -75,7 +75,12 @@ def parse():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the Value / occupancy / paper-array / temporal legs")
     ap.add_argument("--no-probe", action="store_true", help="skip the bandwidth probe")
-    ap.add_argument("--only", default="", choices=["", "build_merge", "step"],
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the sort autotuner on this workload's key sizes first")
+    ap.add_argument("--sort-tune", default="", metavar="RB,ITEMS,RB2,ITEMS2",
+                    help="use these sort settings for the builds (RB, ITEMS) and projections "
+                         "(RB2, ITEMS2) instead of running the autotuner (profiling runs)")
+    ap.add_argument("--only", default="", choices=["", "build_merge", "step", "knn"],
                     help="time only this part (for external profilers)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (a plain copy "
@@ -147,6 +152,7 @@ class Pipeline:
         self.fb = torch.zeros(1, dtype=torch.int64, device=device)
         # side streams (default priority) for the independent parts of a step
         self.side = [torch.cuda.Stream(device=device) for _ in range(3 + len(self.drops))]
+        self.tune_build = self.tune_proj = None  # (radix bits, tile items) or None
         self.ev = [torch.cuda.Event() for _ in range(6 + len(self.drops))]
 
     def make_lookups(self, seed=1006):
@@ -164,10 +170,10 @@ class Pipeline:
         c, g, cnt = self.cga, self.g, self.cnt
         if which == 0:
             c.cga_build(self.a, g, keys_out=self.ka, counts_out=self.ca, d_n_out=cnt[0:1],
-                        sync=False, ws=self.ws[0])
+                        sync=False, ws=self.ws[0], tune=self.tune_build)
         else:
             c.cga_build(self.b, g, keys_out=self.kb, counts_out=self.cb, d_n_out=cnt[1:2],
-                        sync=False, ws=self.ws[1])
+                        sync=False, ws=self.ws[1], tune=self.tune_build)
 
     def _merge(self):
         c, cnt = self.cga, self.cnt
@@ -178,7 +184,7 @@ class Pipeline:
         c, cnt = self.cga, self.cnt
         c.cga_project(self.m, self.g, self.drops[i], n=self.nm, d_n=cnt[2:3], out=self.p[i],
                       counts_out=self.pc[i], d_n_out=cnt[3 + i:4 + i], sync=False,
-                      ws=self.ws[6 + i])
+                      ws=self.ws[6 + i], tune=self.tune_proj)
 
     def _knn(self):
         self.cga.cga_knn(self.m, self.q, self.g, self.k, n=self.nm, d_n=self.cnt[2:3],
@@ -339,14 +345,26 @@ def sort_passes(bits, rb=8):
     return -(-bits // rb)
 
 
-def algorithmic_bytes(label, pipe, counts, build_merge_only=False):
+def library_sort_default(key_bytes, key_bits, n):
+    """The library's default (radix bits, tile items) for a sort (restated
+    here for the report): the fewest passes 8-bit digits allow, each as
+    narrow as that count permits; 16 items per thread below 2^22 keys, else
+    24 (64-bit keys) or 32 (32-bit keys)."""
+    passes = sort_passes(key_bits)
+    rb = max(4, -(-key_bits // passes))
+    items = 16 if n < (1 << 22) else (24 if key_bytes == 8 else 32)
+    return rb, items
+
+
+def algorithmic_bytes(label, pipe, counts, build_merge_only=False, rb=(8, 8)):
     """Bytes the method itself must move for a kernel label over one step
     (reads + writes of its essential inputs and outputs); build_merge_only
-    restricts it to the build + merge part."""
+    restricts it to the build + merge part; rb = the digit widths of the
+    build's and the projections' sorts."""
     kb = 8 if 3 * pipe.g.depth > 32 else 4
     k2b = 8 if 2 * pipe.g.depth > 32 else 4
-    passes3 = sort_passes(3 * pipe.g.depth)
-    passes2 = sort_passes(2 * pipe.g.depth)
+    passes3 = sort_passes(3 * pipe.g.depth, rb[0])
+    passes2 = sort_passes(2 * pipe.g.depth, rb[1])
     ua, ub, um = counts[:3]
     ups = counts[3:] if not build_merge_only else []
     nproj = len(ups)
@@ -879,6 +897,24 @@ def main():
     pipe = Pipeline(cga, d, device, drops)
     progress("inputs on the device")
 
+    # the autotuner picks the sort's digit width and tile size for this
+    # workload's key sizes (the cloud's own keys, and synthetic pixel keys
+    # of the projections' width); builds and projections then use them
+    kb2 = 8 if 2 * pipe.g.depth > 32 else 4
+    if args.sort_tune:
+        t = [int(x) for x in args.sort_tune.split(",")]
+        tuned = {"build": (t[0], t[1], float("nan")), "project": (t[2], t[3], float("nan"))}
+        pipe.tune_build, pipe.tune_proj = (t[0], t[1]), (t[2], t[3])
+    elif args.autotune:
+        tuned = {"build": cga.cga_autotune_sort(cga.cga_encode_keys(pipe.a, pipe.g),
+                                                key_bits=3 * pipe.g.depth),
+                 "project": cga.cga_autotune_sort(None, key_bytes=kb2, key_bits=2 * pipe.g.depth,
+                                                  n=pipe.nm)}
+    else:
+        kb3 = 8 if 3 * pipe.g.depth > 32 else 4
+        tuned = {"build": library_sort_default(kb3, 3 * pipe.g.depth, pipe.na) + (float("nan"),),
+                 "project": library_sort_default(kb2, 2 * pipe.g.depth, pipe.nm) + (float("nan"),)}
+    progress(f"sort settings (radix bits, tile items, tuned ms): {tuned}")
     pipe.step()
     torch.cuda.synchronize()
     pipe.check()
@@ -893,17 +929,21 @@ def main():
         raise RuntimeError("learned and binary lookups disagree")
     progress(f"warm-up done; counts {counts}")
 
-    if args.only == "build_merge":
+    if args.only:
+        # one part only, launched `steps` times (profiler runs); the live
+        # event timing of its main kernel is printed for comparison
+        part = {"build_merge": (pipe.build_merge_concurrent, "onesweep"),
+                "step": (pipe.step_concurrent, "knn"), "knn": (pipe._knn, "knn")}[args.only]
+        if not args.no_kernel_timing:
+            cga.cga_prof_reset()
+            cga.cga_prof_enable([part[1]])
         for _ in range(args.steps):
-            pipe.build_merge_concurrent()
+            part[0]()
         torch.cuda.synchronize()
-        progress("build+merge only: done")
-        return
-    if args.only == "step":
-        for _ in range(args.steps):
-            pipe.step_concurrent()
-        torch.cuda.synchronize()
-        progress("steps only: done")
+        cga.cga_prof_disable()
+        ms, n = cga.cga_prof_read(part[1]) if not args.no_kernel_timing else (0.0, 0)
+        progress(f"{args.only} only: done; {part[1]}: {n} launches, "
+                 f"{ms / max(n, 1) * 1e3:.1f} us average (HIP events)")
         return
 
     # per-kernel breakdown (untimed serial steps)
@@ -925,6 +965,7 @@ def main():
         cga.cga_prof_reset()
         progress(f"per-kernel timing: {kern_ms}")
 
+    rbs = (tuned["build"][0], tuned["project"][0])
     # build + merge: eager runs with the sort passes timed live (roofline),
     # then graph replays (value)
     n_points = pipe.na + pipe.nb
@@ -942,7 +983,8 @@ def main():
     pipe.check()
     ms_bm_eager = e0.elapsed_time(e1) / args.steps
     if not args.no_kernel_timing:
-        bm_roof = roofline_from_prof("onesweep", algorithmic_bytes("onesweep", pipe, counts, True),
+        bm_roof = roofline_from_prof("onesweep", algorithmic_bytes("onesweep", pipe, counts, True,
+                                                                   rbs),
                                      args.steps, load_traffic("onesweep", args.workload),
                                      "build+merge launched per run (both clouds' sort passes)")
         cga.cga_prof_reset()
@@ -1023,7 +1065,7 @@ def main():
 
     by_kernel = {}
     for lb, kms in kern_ms.items():
-        algo = algorithmic_bytes(lb, pipe, counts)
+        algo = algorithmic_bytes(lb, pipe, counts, rb=rbs)
         if lb == "knn":
             algo = nq * knn_bytes_q
         if algo is None or kms <= 0:
@@ -1048,6 +1090,9 @@ def main():
         "config": {"workload": wl_label, "points_per_step": n_points, "queries": nq, "k": pipe.k,
                    "depth": pipe.g.depth, "projections_drop_axes": list(drops),
                    "counts": counts,
+                   "sort_tuning": {k: {"radix_bits": v[0], "tile_items": v[1],
+                                       "tuned_sort_ms": round(v[2], 4) if v[2] == v[2] else None}
+                                   for k, v in tuned.items()},
                    "streams": "build A | build B, merge, then projections | k-NN | index "
                               "training + lookups, captured once as one HIP graph and replayed"},
         "stages": {

@@ -30,7 +30,7 @@
 
 namespace cga {
 
-SortCfg default_sort_cfg(bool wide, int64_t n);
+SortCfg default_sort_cfg(bool wide, int64_t n, int key_bits);
 
 // ------------------------------------------------------------ tuning cache
 namespace {
@@ -91,7 +91,7 @@ static int resolve_cfg(const cga_tune *t, int key_bytes, int key_bits, int64_t n
         *out = c;
         return CGA_OK;
     }
-    if (!tuned_sort_cfg(key_bytes, key_bits, n, out)) *out = default_sort_cfg(key_bytes == 8, n);
+    if (!tuned_sort_cfg(key_bytes, key_bits, n, out)) *out = default_sort_cfg(key_bytes == 8, n, key_bits);
     return CGA_OK;
 }
 
@@ -601,7 +601,7 @@ int cga_autotune_sort(const void *d_keys, uint32_t key_bytes, uint32_t key_bits,
     hipEvent_t e0, e1;
     CGA_HIP(hipEventCreate(&e0));
     CGA_HIP(hipEventCreate(&e1));
-    SortCfg best_cfg = default_sort_cfg(key_bytes == 8, n);
+    SortCfg best_cfg = default_sort_cfg(key_bytes == 8, n, (int)key_bits);
     float best_t = 1e30f;
     int status = CGA_OK;
     for (int rb = 4; rb <= 11 && status == CGA_OK; ++rb)

@@ -73,20 +73,26 @@ static int read_count(const int64_t *d, int64_t *h, hipStream_t s) {
     return CGA_OK;
 }
 
-// Default tuning; the autotuner cache may override it per (key width, n).
-// 8-bit digits and 4096-key tiles were the fastest measured for 1M to 96M
-// keys of either width (fewer tiles, shorter look-backs).
-SortCfg default_sort_cfg(bool wide, int64_t n) {
+// Default tuning; the autotuner cache may override it per (key width, key
+// bits, n).  Digits: the fewest passes that 8-bit digits allow, each as
+// narrow as that pass count permits (42-bit keys: six 7-bit passes; 36-bit:
+// five 8-bit) -- fewer buckets per tile mean longer bucket runs in the
+// scatter and fewer look-back words.  Tiles: 256 threads x 16 keys below 2^22
+// keys (enough tiles to fill the chip), else x 24 (64-bit keys) or x 32
+// (32-bit keys).  These are the autotuner's picks on MI355X for 10M 64-bit
+// keys of 42 bits and 20M 32-bit keys of 28 bits.
+SortCfg default_sort_cfg(bool wide, int64_t n, int key_bits) {
     SortCfg c;
-    c.radix_bits = 8;
-    c.items = 16;
-    (void)wide;
-    (void)n;
+    const int bits = key_bits > 0 ? key_bits : (wide ? 64 : 32);
+    const int passes = (bits + 7) / 8;
+    c.radix_bits = (bits + passes - 1) / passes;
+    if (c.radix_bits < 4) c.radix_bits = 4;
+    c.items = n < ((int64_t)1 << 22) ? 16 : (wide ? 24 : 32);
     return c;
 }
 
 static int pick_cfg(const cga_tune *t, bool wide, int64_t n, SortCfg *out, int key_bits = 0) {
-    SortCfg c = default_sort_cfg(wide, n);
+    SortCfg c = default_sort_cfg(wide, n, key_bits);
     if (!t && key_bits > 0) tuned_sort_cfg(wide ? 8 : 4, key_bits, n, &c);
     if (t) {
         c.radix_bits = (int)t->radix_bits;

@@ -8,7 +8,7 @@
 
 namespace cga {
 
-SortCfg default_sort_cfg(bool wide, int64_t n);
+SortCfg default_sort_cfg(bool wide, int64_t n, int key_bits);
 
 template <typename K, typename K2, int RB>
 __global__ __launch_bounds__(256) void k_rekey(const K *__restrict__ in, int64_t n_host,
@@ -133,7 +133,7 @@ int cga_project(const cga_grid *g, const void *d_keys, int64_t n, const int64_t 
     if (n > 0 && (!d_keys || !d_out2d)) return CGA_EINVAL;
     if (n >= (int64_t)1 << 30) return CGA_EUNSUPPORTED;
     const bool wide2 = wide_keys2(g->depth);
-    SortCfg cfg = default_sort_cfg(wide2, n);
+    SortCfg cfg = default_sort_cfg(wide2, n, 2 * (int)g->depth);
     if (!tune) tuned_sort_cfg(wide2 ? 8 : 4, 2 * (int)g->depth, n, &cfg);
     if (tune) {
         cfg.radix_bits = (int)tune->radix_bits;
