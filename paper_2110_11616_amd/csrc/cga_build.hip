@@ -104,6 +104,8 @@ static int pick_cfg(const cga_tune *t, bool wide, int64_t n, SortCfg *out, int k
 }
 
 // ------------------------------------------------------------ kernels
+constexpr int kEncodeUnroll = 4;
+
 // Quantize + encode one point per thread (grid-stride), with the digit
 // histogram of every sort pass accumulated on the side.
 template <typename K, int RB>
@@ -119,13 +121,32 @@ __global__ __launch_bounds__(256) void k_encode(const float *__restrict__ xyz, i
     __syncthreads();
     const float o[3] = {o0, o1, o2};
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        Vox v;
-        bad |= !quantize3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], o, scale, depth, v);
-        K k = (K)enc3(v.x, v.y, v.z, depth, linear != 0);
-        keys[i] = k;
-        if (passes) hist_add_coherent<RB>(s_h, k, passes);
+    // kEncodeUnroll points per thread and step, all loaded before any is
+    // encoded (more bytes in flight per CU); the wave's points stay
+    // consecutive, which the coherent histogram relies on
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 - threadIdx.x < n;
+         i0 += kEncodeUnroll * stride) {
+        float p[kEncodeUnroll][3];
+#pragma unroll
+        for (int u = 0; u < kEncodeUnroll; ++u) {
+            const int64_t i = i0 + u * stride;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) p[u][a] = i < n ? xyz[3 * i + a] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kEncodeUnroll; ++u) {
+            const int64_t i = i0 + u * stride;
+            if (i - threadIdx.x >= n) break;  // block-uniform: no wave of this step has a point
+            Vox v;
+            const bool ok = quantize3(p[u][0], p[u][1], p[u][2], o, scale, depth, v);
+            const K k = (K)enc3(v.x, v.y, v.z, depth, linear != 0);
+            if (i < n) {
+                bad |= !ok;
+                keys[i] = k;
+            }
+            if (passes && i < n) hist_add_coherent<RB>(s_h, k, passes);
+        }
     }
     if (bad) s_bad = 1;
     __syncthreads();

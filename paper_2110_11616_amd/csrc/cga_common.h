@@ -171,6 +171,48 @@ __device__ __forceinline__ T block_excl_max(T v, T lo, T *s_wave, T *total) {
     return wbase > exc ? wbase : exc;
 }
 
+// Decoupled look-back (Merrill & Garland 2016) run by one whole wave over a
+// window of 64 predecessors: lane l reads the status word of tile t - l, the
+// wave finds the nearest inclusive one, and one wave reduction combines every
+// value from there to tile t - 1; a walk over m unfinished predecessors costs
+// m / 64 round trips instead of m.  Status words carry a 2-bit flag in bits
+// 62-63 (0 = not yet published, 1 = aggregate, 2 = inclusive); tiles before
+// `first` count as an inclusive zero.  Every lane of the wave must call it;
+// every lane gets the result.  Combine is (sum of the low 62 bits).
+__device__ __forceinline__ uint64_t lookback_window(const uint64_t *status, int64_t tile,
+                                                    int64_t first, uint64_t *nearest_upto) {
+    const int lane = lane_id();
+    for (;;) {
+        const int64_t ti = tile - 1 - lane;
+        const uint64_t st = ti >= first ? ld_agent(&status[ti]) : (2ull << 62);
+        const uint64_t inc = __ballot((st >> 62) == 2);
+        const uint64_t pub = __ballot((st >> 62) != 0);
+        // lanes 0 .. f, f the nearest inclusive (every lane when there is none)
+        const uint64_t upto = inc ? ((inc & (~inc + 1)) << 1) - 1 : ~0ull;
+        if ((pub & upto) == upto) {
+            *nearest_upto = inc ? upto : 0;
+            return st;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__device__ __forceinline__ uint64_t lookback_sum62(const uint64_t *status, int64_t tile,
+                                                   int64_t first) {
+    const int lane = lane_id();
+    uint64_t acc = 0;
+    for (int64_t t = tile; ; t -= 64) {
+        uint64_t upto;
+        const uint64_t st = lookback_window(status, t, first, &upto);
+        const uint64_t use = upto ? upto : ~0ull;
+        unsigned long long v = ((use >> lane) & 1ull) ? (st & ((1ull << 62) - 1)) : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        acc += v;
+        if (upto) return acc;
+    }
+}
+
 // Dynamic tile id: tiles are numbered in the order their workgroups start,
 // so a tile only ever waits on tiles that are already running.
 __device__ __forceinline__ uint32_t next_tile(uint32_t *ctr, uint32_t *s_slot) {

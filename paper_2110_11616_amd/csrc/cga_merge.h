@@ -62,8 +62,21 @@ __device__ __forceinline__ void merge_tile(MergeShared<K> &sh, const K *__restri
     const bool extra = b1 < nb;  // first B element after the window, for provenance
     const int len = la + lb + (extra ? 1 : 0);
     K *s = sh.s;
-    for (int j = tid; j < len; j += kMergeBlock)
-        s[j] = j < la ? A[a0 + j] : B[b0 + (j - la)];
+    {
+        // every load of the window issued before the first LDS store
+        constexpr int kLoads = (kMergeTile + 1 + kMergeBlock - 1) / kMergeBlock;
+        K v[kLoads];
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const int j = u * kMergeBlock + tid;
+            v[u] = j < len ? (j < la ? A[a0 + j] : B[b0 + (j - la)]) : K(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const int j = u * kMergeBlock + tid;
+            if (j < len) s[j] = v[u];
+        }
+    }
     const bool prev_global = a0 > 0;
     const K prev_a_global = prev_global ? A[a0 - 1] : K(0);
     __syncthreads();
@@ -117,27 +130,19 @@ __device__ __forceinline__ void merge_tile(MergeShared<K> &sh, const K *__restri
     uint32_t tot;
     uint32_t ex = block_excl_sum<kMergeBlock>(cnt, sh.w, &tot);
 
-    if (tid == 0) {
+    if (tid < 64) {  // wave 0: publish, look back over earlier windows of this merge
         uint64_t pre = 0;
         if (tile == seg_first) {
-            st_agent(&status[tile], kMInc | (uint64_t)tot);
+            if (tid == 0) st_agent(&status[tile], kMInc | (uint64_t)tot);
         } else {
-            st_agent(&status[tile], kMAgg | (uint64_t)tot);
-            int64_t t = tile - 1;
-            for (;;) {
-                uint64_t st = ld_agent(&status[t]);
-                if ((st >> 62) == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                pre += st & kMVal;
-                if (st & kMInc) break;
-                --t;
-            }
-            st_agent(&status[tile], kMInc | (pre + tot));
+            if (tid == 0) st_agent(&status[tile], kMAgg | (uint64_t)tot);
+            pre = lookback_sum62(status, tile, seg_first);
+            if (tid == 0) st_agent(&status[tile], kMInc | (pre + tot));
         }
-        sh.prefix = (int64_t)pre;
-        if (d1 == total && n_out) *n_out = (int64_t)pre + tot;
+        if (tid == 0) {
+            sh.prefix = (int64_t)pre;
+            if (d1 == total && n_out) *n_out = (int64_t)pre + tot;
+        }
     }
     // stage survivors in LDS (the merge reads of s finished at the scan's barriers)
     uint32_t o = ex;

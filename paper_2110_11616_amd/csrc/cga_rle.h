@@ -54,9 +54,19 @@ __global__ __launch_bounds__(kRleBlock) void k_rle(const K *__restrict__ in, int
     const int64_t base = (int64_t)tile * kRleTile;
     if (base >= n) return;
 
-    for (int j = tid; j < kRleTile; j += kRleBlock) {
-        int64_t i = base + j;
-        SV(1 + j) = i < n ? (K)(in[i] >> shift) : K(0);
+    {
+        // every load of the tile issued before the first LDS store
+        K v[kRleItems];
+#pragma unroll
+        for (int it = 0; it < kRleItems; ++it) {
+            const int64_t i = base + it * kRleBlock + tid;
+            v[it] = i < n ? in[i] : K(0);
+        }
+#pragma unroll
+        for (int it = 0; it < kRleItems; ++it) {
+            const int j = it * kRleBlock + tid;
+            SV(1 + j) = base + j < n ? (K)(v[it] >> shift) : K(0);
+        }
     }
     if (tid == 0) SV(0) = base > 0 ? (K)(in[base - 1] >> shift) : K(0);
     if (tid == 1) SV(kRleTile + 1) = base + kRleTile < n ? (K)(in[base + kRleTile] >> shift) : K(0);
@@ -79,32 +89,40 @@ __global__ __launch_bounds__(kRleBlock) void k_rle(const K *__restrict__ in, int
     uint32_t ex_c = block_excl_sum<kRleBlock>(hc, s_wc, &tot_c);
     int32_t ex_l = block_excl_max<kRleBlock>(hl, (int32_t)-1, s_wl, &tot_l);
 
-    if (tid == 0) {
+    if (tid < 64) {  // wave 0: publish, then look back 64 tiles per round trip
         uint32_t pc = 0;
         int32_t pl = -1;
         if (tile == 0) {
-            st_agent(&status[tile], rle_pack(kRleInc, tot_c, tot_l));
+            if (tid == 0) st_agent(&status[tile], rle_pack(kRleInc, tot_c, tot_l));
         } else {
-            st_agent(&status[tile], rle_pack(kRleAgg, tot_c, tot_l));
-            int64_t t = (int64_t)tile - 1;
-            for (;;) {
-                uint64_t st = ld_agent(&status[t]);
-                if ((st >> 62) == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+            if (tid == 0) st_agent(&status[tile], rle_pack(kRleAgg, tot_c, tot_l));
+            for (int64_t t = tile; ; t -= 64) {
+                uint64_t upto;
+                const uint64_t st = lookback_window(status, t, 0, &upto);
+                const bool use = ((upto ? upto : ~0ull) >> tid) & 1ull;
+                // tiles before the first (t - 1 - lane < 0) read as inclusive
+                // zeros: count 0, latest head -1
+                const bool real = t - 1 - tid >= 0;
+                uint32_t c = use && real ? rle_cnt(st) : 0u;
+                int32_t l = use && real ? rle_last(st) : -1;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    c += __shfl_xor(c, o, 64);
+                    const int32_t lo = __shfl_xor(l, o, 64);
+                    l = lo > l ? lo : l;
                 }
-                pc += rle_cnt(st);
-                int32_t l = rle_last(st);
+                pc += c;
                 pl = pl > l ? pl : l;
-                if (st & kRleInc) break;
-                --t;
+                if (upto) break;
             }
-            int32_t il = pl > tot_l ? pl : tot_l;
-            st_agent(&status[tile], rle_pack(kRleInc, pc + tot_c, il));
+            const int32_t il = pl > tot_l ? pl : tot_l;
+            if (tid == 0) st_agent(&status[tile], rle_pack(kRleInc, pc + tot_c, il));
         }
-        s_pc = pc;
-        s_pl = pl;
-        if (ENDS && tile == 0 && ends) ends[0] = 0;
+        if (tid == 0) {
+            s_pc = pc;
+            s_pl = pl;
+            if (ENDS && tile == 0 && ends) ends[0] = 0;
+        }
     }
     __syncthreads();
 
