@@ -12,8 +12,10 @@
 //   child in octant o exists.  Child o is then node first + popcount(mask
 //   below bit o): one 8-byte load per visited node, and no load at all for
 //   the voxels under a level-1 node, whose coordinates follow from the path.
-// A dense table maps every level-DT cell (DT = depth - 7, 2^21 cells) to its
-// node, so a search enters the tree near the bottom instead of at the root.
+// A dense table maps every level-DT cell (DT = depth - DL, 8^DL cells, DL up
+// to 7 and no more than about log8 of the key count, so that clearing it
+// costs no more than the keys themselves) to its node, so a search enters the
+// tree near the bottom instead of at the root.
 //
 // Queries: a team of 8 lanes answers one query.  Round 0 searches the
 // query's level-LA cell: lane t walks child t (in visiting order) of each of
@@ -61,9 +63,17 @@ __device__ __forceinline__ int64_t lower_bound_dev(const K *keys, int64_t n, K q
 }
 
 // ------------------------------------------------------------ octree build
-__host__ __device__ inline int dense_level(uint32_t depth) { return depth > 7 ? (int)depth - 7 : 0; }
-__host__ __device__ inline int64_t dense_cells(uint32_t depth) {
-    return dense_level(depth) > 0 ? (int64_t)1 << 21 : 0;
+// Levels the dense table spans for n keys: floor(log8 n), within [2, 7].
+inline int dense_levels(int64_t n) {
+    int dl = 2;
+    while (dl < 7 && ((int64_t)1 << (3 * (dl + 1))) <= n) ++dl;
+    return dl;
+}
+__host__ __device__ inline int dense_level(uint32_t depth, int dl) {
+    return (int)depth > dl ? (int)depth - dl : 0;
+}
+__host__ __device__ inline int64_t dense_cells(uint32_t depth, int dl) {
+    return dense_level(depth, dl) > 0 ? (int64_t)1 << (3 * dl) : 0;
 }
 
 // Highest level at which key i starts a new cell: key 0 starts every cell up
@@ -502,8 +512,8 @@ void k_knn_tree(
     const uint64_t *__restrict__ node, const uint32_t *__restrict__ dense,
     const int64_t *__restrict__ lvl, int64_t nodes_max, const float *__restrict__ q, int64_t nq,
     const uint64_t *__restrict__ order, float o0, float o1, float o2, float scale, uint32_t depth,
-    int k, int la, int64_t *__restrict__ idx_out, uint64_t *__restrict__ d2_out, uint32_t *err,
-    unsigned long long *work = nullptr) {
+    int dl, int k, int la, int64_t *__restrict__ idx_out, uint64_t *__restrict__ d2_out,
+    uint32_t *err, unsigned long long *work = nullptr) {
     uint32_t c_node = 0, c_dense = 0, c_vox = 0, c_step = 0;  // kCount only
     using Dist = typename LIST::Dist;
     extern __shared__ uint64_t s_word[];  // open node word per level, one column per thread
@@ -525,7 +535,7 @@ void k_knn_tree(
     const int64_t j = order ? (int64_t)(order[slot] >> kOrderBits) : slot;  // query (and output row)
     // an oversized tree (keys that are not a CGA of the grid) searches nothing
     const int64_t n = tree_total(lvl, depth, nodes_max) < 0 ? 0 : lvl[0];
-    const int dt = dense_level(depth);
+    const int dt = dense_level(depth, dl);
 
     const float o[3] = {o0, o1, o2};
     Vox qv;
@@ -578,7 +588,7 @@ void k_knn_tree(
         int L;
         int64_t nj;
         if (dt > 0 && l <= dt) {
-            const uint32_t v = dense[enc3(x >> dt, y >> dt, z >> dt, 7, false)];
+            const uint32_t v = dense[enc3(x >> dt, y >> dt, z >> dt, (uint32_t)dl, false)];
             if (kCount) ++c_dense;
             if (!v) return -1;
             nj = (int64_t)v - 1;
@@ -930,6 +940,7 @@ struct KnnLayout {
     uint8_t *oct;
     uint64_t *node;
     uint32_t *dense;
+    int dl;  // levels spanned by the dense table
     int64_t tiles, nodes;
     size_t bytes;
 };
@@ -953,7 +964,8 @@ static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth, int64_t nq_orde
     L.first = c.take<uint32_t>((size_t)L.nodes);
     L.oct = c.take<uint8_t>((size_t)L.nodes);
     L.node = c.take<uint64_t>((size_t)L.nodes);
-    L.dense = c.take<uint32_t>((size_t)dense_cells(depth) + 1);
+    L.dl = dense_levels(n);
+    L.dense = c.take<uint32_t>((size_t)dense_cells(depth, L.dl) + 1);
     L.bytes = c.size();
     return L;
 }
@@ -964,12 +976,12 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
                        bool emit = false, uint8_t *occ = nullptr, int64_t occ_cap = 0,
                        int64_t *counts = nullptr) {
     CGA_PROF(label, s);
-    const int dt = dense_level(depth);
+    const int dt = dense_level(depth, L.dl);
     k_tree_count<K><<<(unsigned)L.tiles, 256, 0, s>>>(keys, n, d_n, depth, L.tiles, L.cnt, L.dense,
-                                                      dense_cells(depth), &L.ctl->err);
+                                                      dense_cells(depth, L.dl), &L.ctl->err);
     k_tree_scan<<<depth, 1024, 0, s>>>(L.cnt, L.tiles, n, d_n, L.lvl);
     k_tree_build<K><<<(unsigned)L.tiles, 256, 0, s>>>(keys, n, d_n, depth, dt, L.tiles, L.cnt, L.lvl,
-                                                      L.first, L.oct, L.dense, dense_cells(depth),
+                                                      L.first, L.oct, L.dense, dense_cells(depth, L.dl),
                                                       L.nodes);
     int64_t blocks = (L.nodes + 255) / 256;
     blocks = blocks < 4096 ? blocks : 4096;
@@ -987,11 +999,11 @@ static void knn_launch(const cga_grid *g, const KnnLayout &L, const float *q, in
     if (g->depth <= kPackedDepth)
         k_knn_tree<KT, PackedList<KT>, kCount><<<blocks, kKnnBlock, lds, s>>>(
             L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
-            g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err, work);
+            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, work);
     else
         k_knn_tree<KT, WideList<KT>, kCount><<<blocks, kKnnBlock, lds, s>>>(
             L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
-            g->scale, g->depth, k, knn_la(g->depth), idx, d2, &L.ctl->err, work);
+            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, work);
 }
 
 template <bool kCount>
