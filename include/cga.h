@@ -283,10 +283,12 @@ int cga_knn_count(const cga_grid *grid, const void *d_keys, int64_t n, const int
  * d_u nullable.  d_values (u uint32) receives each voxel's channel-wise
  * average of its points' values, rounded half up, floor((2 sum + count) /
  * (2 count)) -- the averaging of colours in a grid box that Section III-B's
- * downsampling applies.  Workspace: cga_voxel_values_workspace_bytes(u).
+ * downsampling applies.  The points' keys and values are radix-sorted
+ * together so that each voxel's points form one run, summed without atomics.
+ * Workspace: cga_voxel_values_workspace_bytes(grid, n).  n below 2^30.
  * Errors: CGA_ENONFINITE (device) for a non-finite point; CGA_EMISMATCH
  * (device) when a point's voxel is not among the keys or a key has no point. */
-size_t cga_voxel_values_workspace_bytes(int64_t u);
+size_t cga_voxel_values_workspace_bytes(const cga_grid *grid, int64_t n);
 int cga_voxel_values(const cga_grid *grid, const float *d_xyz, int64_t n, const uint32_t *d_attr,
                      const void *d_keys, int64_t u, const int64_t *d_u, uint32_t *d_values,
                      void *d_ws, size_t ws_bytes, cga_stream stream);

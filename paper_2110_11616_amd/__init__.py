@@ -124,7 +124,7 @@ _sig("cga_batch_graph_destroy", ctypes.c_int, _P)
 _sig("cga_autotune_workspace_bytes", _SZ, ctypes.c_uint32, _I64)
 _sig("cga_autotune_sort", ctypes.c_int, _P, ctypes.c_uint32, ctypes.c_uint32, _I64, _P, _SZ, _TP,
      ctypes.POINTER(ctypes.c_float), _P)
-_sig("cga_voxel_values_workspace_bytes", _SZ, _I64)
+_sig("cga_voxel_values_workspace_bytes", _SZ, _GP, _I64)
 _sig("cga_voxel_values", ctypes.c_int, _GP, _P, _I64, _P, _P, _I64, _P, _P, _P, _SZ, _P)
 _sig("cga_merge_values_workspace_bytes", _SZ)
 _sig("cga_merge_values", ctypes.c_int, _GP, _P, _P, _I64, _P, _P, _P, _I64, _P, _P, _I64, _P,
@@ -479,7 +479,7 @@ def cga_voxel_values(xyz: torch.Tensor, attr: torch.Tensor, keys: torch.Tensor, 
     u = keys.shape[0] if u is None else int(u)
     g = grid_struct(grid)
     vals = out if out is not None else torch.empty(max(u, 1), dtype=torch.int32, device=keys.device)
-    wsb = _ws("values", lib.cga_voxel_values_workspace_bytes(u), ws)
+    wsb = _ws("values", lib.cga_voxel_values_workspace_bytes(ctypes.byref(g), n), ws)
     _check(lib.cga_voxel_values(ctypes.byref(g), _ptr(xyz), n, _ptr(attr), _ptr(keys), u, _ptr(d_u),
                                 _ptr(vals), _ptr(wsb), wsb.numel(), _stream(stream)),
            "cga_voxel_values")

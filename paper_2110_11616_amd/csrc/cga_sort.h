@@ -6,9 +6,15 @@
 // digit order and scatters it.  Stable, so passes compose.
 #pragma once
 
+#include <type_traits>
+
 #include "cga_common.h"
 
 namespace cga {
+
+// No payload: the keys alone are sorted.  A payload type V (uint32_t) moves
+// with its key through every pass (a key-value sort).
+struct NoVal {};
 
 constexpr int kSortBlock = 256;
 constexpr int kMaxPasses = 16;  // 64 bits at 4 bits per digit
@@ -116,12 +122,14 @@ __global__ __launch_bounds__(kSortBlock) void k_hist_scan(uint32_t *hist) {
 // --------------------------------------------------------- onesweep pass
 // One LSD pass on digit bits [shift, shift + RB).  `look` holds one status
 // word per (tile, digit) and must be zero on entry; each tile also zeroes its
-// own slots of `look_next`, the status array of the following pass.
-template <typename K, int RB, int ITEMS>
+// own slots of `look_next`, the status array of the following pass.  With a
+// payload type V, vin[i] travels with in[i] to the same output slot.
+template <typename K, int RB, int ITEMS, typename V = NoVal>
 __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     const K *__restrict__ in, K *__restrict__ out, int64_t n_host, const int64_t *d_n, int shift,
     const uint32_t *__restrict__ digit_base, uint32_t *look, uint32_t *look_next,
-    uint32_t *tile_ctr) {
+    uint32_t *tile_ctr, const V *__restrict__ vin = nullptr, V *__restrict__ vout = nullptr) {
+    constexpr bool kHasVal = !std::is_same<V, NoVal>::value;
     constexpr int BLOCK = kSortBlock;
     constexpr int RADIX = 1 << RB;
     constexpr int WAVES = BLOCK / 64;
@@ -134,6 +142,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     __shared__ int64_t s_glob[RADIX];          // global position of LDS slot 0 per digit
     __shared__ uint32_t s_w[WAVES];
     __shared__ K s_keys[TILE];
+    __shared__ V s_vals[kHasVal ? TILE : 1];
 
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     for (int i = tid; i < WAVES * RADIX; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
@@ -147,12 +156,14 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     // Load wave-striped: wave w owns [w*64*ITEMS, (w+1)*64*ITEMS), item i of
     // lane l is element i*64 + l, so (wave, item, lane) order is input order.
     K keys[ITEMS];
+    V vals[kHasVal ? ITEMS : 1];
     uint32_t dig[ITEMS];
     const int64_t wbase = base + (int64_t)wave * 64 * ITEMS + lane;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         int64_t idx = wbase + i * 64;
         keys[i] = idx < n ? in[idx] : ~K(0);  // padding sorts last, never written
+        if constexpr (kHasVal) vals[i] = idx < n ? vin[idx] : V(0);
         dig[i] = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
     }
 
@@ -246,6 +257,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     for (int i = 0; i < ITEMS; ++i) {
         uint32_t pos = s_boff[dig[i]] + s_wcnt[wave][dig[i]] + rank[i];
         s_keys[pos] = keys[i];
+        if constexpr (kHasVal) s_vals[pos] = vals[i];
     }
     __syncthreads();
 
@@ -256,7 +268,10 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
         K k = s_keys[j];
         uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1);
         int64_t g = s_glob[d] + j;
-        if (g >= 0 && g < n) out[g] = k;
+        if (g >= 0 && g < n) {
+            out[g] = k;
+            if constexpr (kHasVal) vout[g] = s_vals[j];
+        }
     }
 }
 
@@ -368,6 +383,43 @@ inline void sort_launch(const SortWs &w, const K *in, K *out, K *alt0, K *alt1, 
         case 10: sort_launch_rb<K, 10>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
         case 11: sort_launch_rb<K, 11>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
         default: sort_launch_rb<K, 8>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+    }
+}
+
+// Key-value sort (payload uint32_t) with 8-bit digits and 4096-key tiles:
+// the same passes as sort_launch, the payload following its key; `w` carved
+// with radix_bits 8 and items 16.  Buffer chain as in sort_launch_rb, for the
+// keys (in, out, alt0, alt1) and the values (vin, vout, valt0, valt1).
+template <typename K>
+inline void sort_launch_kv(const SortWs &w, const K *in, K *out, K *alt0, K *alt1,
+                           const uint32_t *vin, uint32_t *vout, uint32_t *valt0, uint32_t *valt1,
+                           int64_t n_host, const int64_t *d_n, bool have_hist,
+                           uint32_t *tile_ctr, hipStream_t s) {
+    constexpr int RB = 8, ITEMS = 16;
+    if (w.passes == 0) return;
+    if (!have_hist) {
+        int64_t blocks = (n_host + kSortBlock * 16 - 1) / (kSortBlock * 16);
+        blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+        CGA_PROF("histogram", s);
+        k_histogram<K, RB><<<(unsigned)blocks, kSortBlock, hist_lds_bytes(w.passes, RB), s>>>(
+            in, n_host, d_n, w.passes, w.hist);
+    }
+    {
+        CGA_PROF("hist_scan", s);
+        k_hist_scan<RB><<<(unsigned)w.passes, kSortBlock, 0, s>>>(w.hist);
+    }
+    const K *src = in;
+    const uint32_t *vsrc = vin;
+    for (int p = 0; p < w.passes; ++p) {
+        const bool last = p == w.passes - 1, even = ((w.passes - 1 - p) & 1) != 0;
+        K *dst = last ? out : (even ? alt0 : alt1);
+        uint32_t *vdst = last ? vout : (even ? valt0 : valt1);
+        CGA_PROF("onesweep_kv", s);
+        k_onesweep<K, RB, ITEMS, uint32_t><<<(unsigned)w.tiles, kSortBlock, 0, s>>>(
+            src, dst, n_host, d_n, p * RB, w.hist + (size_t)p * 256, w.look[p & 1],
+            w.look[(p + 1) & 1], tile_ctr + p, vsrc, vdst);
+        src = dst;
+        vsrc = vdst;
     }
 }
 

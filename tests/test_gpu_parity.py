@@ -588,6 +588,33 @@ def test_values_runs(gpu, w_c1):
         assert np.array_equal(u64(k), want_k) and _u32(v).tolist() == want_v.tolist()
 
 
+@pytest.mark.parametrize("depth", [10, 12])
+def test_values_tile_runs(gpu, depth):
+    """Voxels whose points span whole 4096-point tiles of the sorted order:
+    one voxel of 20,000 points (five tiles and more), runs ending exactly on
+    a tile edge and one point past it, many short runs, the points shuffled;
+    then a key with no point of the cloud (CGA_EMISMATCH)."""
+    g = Grid((0.0, 0.0, 0.0), float(2 ** depth), depth, M)
+    rng = np.random.default_rng(517 + depth)
+    centres = rng.uniform(0.02, 0.98, (3000, 3)).astype(np.float32)
+    lens = np.concatenate([[4096, 4097, 1, 20_000, 4095, 8192], rng.integers(1, 40, 2994)])
+    pts = np.repeat(centres, lens, axis=0)
+    perm = rng.permutation(len(pts))
+    pts = pts[perm]
+    attr = rng.integers(0, 2 ** 32, len(pts), dtype=np.uint64).astype(np.uint32)
+    k, _ = gpu.cga_build(dev(pts), g)
+    v = gpu.cga_voxel_values(dev(pts), dev(attr.view(np.int32)), k, g)
+    want_k, want_v = oracle.voxel_values(pts, attr, g)
+    assert np.array_equal(u64(k), want_k) and np.array_equal(_u32(v), want_v)
+    # the same keys with one extra key no point falls in
+    extra = np.array([[0.999, 0.999, 0.0005]], np.float32)
+    k2, _ = gpu.cga_build(dev(np.concatenate([pts, extra])), g)
+    assert k2.numel() == k.numel() + 1
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_voxel_values(dev(pts), dev(attr.view(np.int32)), k2, g)
+    assert e.value.status == gpu.EMISMATCH
+
+
 def test_knn_linear_unsupported(gpu, w_c1):
     g = w_c1["grid"].with_mode(L)
     k, _ = gpu.cga_build(dev(w_c1["a"]), g)
