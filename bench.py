@@ -822,7 +822,8 @@ def c4_batched(cga, device, reps):
     one replay of the captured graph; the sort's digit width and tile size
     come from the autotuner run on the same number of keys.  Roofline: the
     method's bytes for every frame's build (quantize + encode, the autotuned
-    number of sort passes over the composite keys, run-length compaction)
+    number of sort passes over the key bits the frame-segmented sort covers,
+    run-length compaction)
     and every pair's merge, over the replay time."""
     import numpy as np
     import torch
@@ -835,8 +836,7 @@ def c4_batched(cga, device, reps):
     g = d["grid"]
     n, F = len(xyz), len(off) - 1
     gen_s = time.perf_counter() - t0
-    fb = int(np.ceil(np.log2(F)))
-    key_bits = 3 * g.depth + fb
+    key_bits = cga.cga_batch_sort_bits(g, F)  # the bits the (frame-segmented) sort passes cover
     rb, items, tune_ms = cga.cga_autotune_sort(key_bytes=8, key_bits=key_bits, n=n)
     graph = cga.BatchGraph(xyz, off, g)
     graph.launch()

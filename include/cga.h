@@ -421,9 +421,12 @@ int cga_mlp_loss_grad(const float *d_params, const float *d_x, const float *d_t,
  *       d_keys[d_key_off[f] .. d_key_off[f+1]);
  *   d_merged (capacity 2n): pair f's union starts at d_merged_off[f]
  *       (nframes - 1 int64) and holds d_merged_cnt[f] keys.
- * Implementation: composite keys (frame << 3*depth | key) in one radix sort,
- * one run-length pass, per-frame offsets by binary search, then one
- * persistent merge launch over a window queue spanning all pairs.  Every size
+ * Implementation: composite keys (frame << 3*depth | key), a radix sort
+ * segmented by frame (each frame's keys sorted within the frame's range by
+ * the 3*depth key bits alone; above 4096 frames one sort of the composite
+ * keys, frame bits included), one run-length pass, per-frame offsets by
+ * binary search, then one persistent merge launch over a window queue
+ * spanning all pairs.  Every size
  * after the input stays on the device, so the call can be captured in a
  * graph: cga_batch_graph_create records it once (on a private stream) into
  * an executable graph that cga_batch_graph_launch replays on any stream,
@@ -431,6 +434,12 @@ int cga_mlp_loss_grad(const float *d_params, const float *d_x, const float *d_t,
  * nframes in [1, 65536]; n < 2^30.  tune NULL = autotuned (see below) or
  * default digit width and tile size; results never depend on it. */
 size_t cga_batch_workspace_bytes(const cga_grid *grid, int nframes, int64_t n);
+/* Key bits the batched sort's passes cover for nframes frames on this grid
+ * (3*depth when segmented, else 3*depth + ceil(log2(nframes))): the
+ * key_bits under which cga_autotune_sort records a choice that
+ * cga_batch_build_merge and cga_batch_graph_create then use.  0 when the grid
+ * or nframes is invalid. */
+int cga_batch_sort_bits(const cga_grid *grid, int nframes);
 int cga_batch_build_merge(const cga_grid *grid, const float *d_xyz, const int64_t *d_off,
                           int nframes, int64_t n, void *d_keys, uint32_t *d_counts,
                           int64_t *d_key_off, void *d_merged, int64_t *d_merged_off,

@@ -115,6 +115,7 @@ _sig("cga_index_lookup", ctypes.c_int, _P, _P, _I64, _P, _I64, _P, _P, _P, _P, _
 _sig("cga_index_stats", ctypes.c_int, _P, _P, _P, _P)
 _sig("cga_mlp_loss_grad", ctypes.c_int, _P, _P, _P, _I64, _P, _P, _P)
 _sig("cga_batch_workspace_bytes", _SZ, _GP, ctypes.c_int, _I64)
+_sig("cga_batch_sort_bits", ctypes.c_int, _GP, ctypes.c_int)
 _sig("cga_batch_build_merge", ctypes.c_int, _GP, _P, _P, ctypes.c_int, _I64, _P, _P, _P, _P, _P, _P,
      _TP, _P, _SZ, _P)
 _sig("cga_batch_graph_create", ctypes.c_int, _GP, _P, _P, ctypes.c_int, _I64, _P, _P, _P, _P, _P,
@@ -643,6 +644,12 @@ def _batch_args(grid, xyz, off, out, tune, wsb):
     return (ctypes.byref(g), _ptr(xyz), _ptr(off), nf, xyz.shape[0], _ptr(out.keys), _ptr(out.counts),
             _ptr(out.key_off), _ptr(out.merged), _ptr(out.merged_off), _ptr(out.merged_cnt),
             tune_struct(tune), _ptr(wsb), wsb.numel()), g
+
+
+def cga_batch_sort_bits(grid, nframes: int) -> int:
+    """Key bits the batched sort's passes cover (the autotuner's key_bits)."""
+    g = grid_struct(grid)
+    return int(lib.cga_batch_sort_bits(ctypes.byref(g), nframes))
 
 
 def cga_batch_build_merge(xyz: torch.Tensor, off: torch.Tensor, grid, *, out=None, tune=None,

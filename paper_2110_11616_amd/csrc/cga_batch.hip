@@ -3,8 +3,9 @@
 // captured once in a hipGraph and replayed:
 //   1. quantize + encode every point as the composite key (frame << 3d | key)
 //      with the digit histograms of the sort on the side;
-//   2. one LSD radix sort of the composite keys (frames become contiguous
-//      segments, each sorted);
+//   2. an LSD radix sort segmented by frame: each frame's keys sorted on
+//      their own, in place of the frame's range, by the 3 * depth key bits
+//      only (with very many frames, one sort of the composite keys);
 //   3. run-length compaction -> unique composite keys + point counts;
 //   4. per-frame offsets (binary search of each frame's first key) and the
 //      frame bits stripped off;
@@ -107,41 +108,57 @@ __device__ __forceinline__ uint32_t frame_of(const int64_t *off, int F, int64_t 
     return (uint32_t)lo;
 }
 
+// Block b encodes the points [b * chunk, (b + 1) * chunk), frame by frame,
+// and adds the digits of every sort pass to LDS counters that it flushes at
+// each frame's end: into hist[p][f][digit] for a segmented sort (seg), else
+// into the one histogram hist[p][digit] of the composite keys.
 template <int RB>
 __global__ __launch_bounds__(256) void k_batch_encode(const float *__restrict__ xyz,
                                                       const int64_t *__restrict__ off, int F,
-                                                      int64_t n, float o0, float o1, float o2,
-                                                      float scale, uint32_t depth, int linear,
-                                                      uint64_t *__restrict__ keys, int passes,
-                                                      uint32_t *hist, uint32_t *err) {
+                                                      int64_t n, int64_t chunk, float o0, float o1,
+                                                      float o2, float scale, uint32_t depth,
+                                                      int linear, uint64_t *__restrict__ keys,
+                                                      int passes, int seg, uint32_t *hist,
+                                                      uint32_t *err) {
     constexpr uint32_t RADIX = 1u << RB;
     extern __shared__ uint32_t s_h[];
     __shared__ int s_bad;
-    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += blockDim.x) s_h[i] = 0;
+    const uint32_t nh = (uint32_t)passes * RADIX;
+    for (uint32_t i = threadIdx.x; i < nh; i += blockDim.x) s_h[i] = 0;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     const float o[3] = {o0, o1, o2};
     const int shift = 3 * (int)depth;
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        Vox v;
-        bad |= !quantize3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], o, scale, depth, v);
-        // a frame's points are consecutive, so the wave's first active lane
-        // finds its frame and the others only confirm it
-        const uint64_t act = __ballot(1);
-        const int leader = __ffsll((unsigned long long)act) - 1;
-        uint32_t f0 = 0;
-        if (lane_id() == leader) f0 = frame_of(off, F, i);
-        f0 = __shfl(f0, leader, 64);
-        const uint32_t fr = off[f0] <= i && i < off[f0 + 1] ? f0 : frame_of(off, F, i);
-        const uint64_t k = ((uint64_t)fr << shift) | enc3(v.x, v.y, v.z, depth, linear != 0);
-        keys[i] = k;
-        hist_add_coherent<RB>(s_h, k, passes);
+    int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = c0 + chunk < n ? c0 + chunk : n;
+    uint32_t f = c0 < c1 ? frame_of(off, F, c0) : (uint32_t)F;
+    while (c0 < c1) {
+        const int64_t fe = off[f + 1], e = fe < c1 ? fe : c1;
+        for (int64_t i = c0 + threadIdx.x; i < e; i += blockDim.x) {
+            Vox v;
+            bad |= !quantize3(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], o, scale, depth, v);
+            const uint64_t k = ((uint64_t)f << shift) | enc3(v.x, v.y, v.z, depth, linear != 0);
+            keys[i] = k;
+            hist_add_coherent<RB>(s_h, k, passes);
+        }
+        __syncthreads();
+        if (e > c0) {
+            for (uint32_t j = threadIdx.x; j < nh; j += blockDim.x) {
+                const uint32_t c = s_h[j];
+                if (c) {
+                    const uint32_t p = j / RADIX, d = j % RADIX;
+                    atomicAdd(&hist[seg ? ((size_t)p * F + f) * RADIX + d : j], c);
+                    s_h[j] = 0;
+                }
+            }
+        }
+        __syncthreads();
+        c0 = e;
+        ++f;
     }
     if (bad) s_bad = 1;
     __syncthreads();
-    hist_flush<RB>(s_h, hist, passes);
     if (threadIdx.x == 0 && s_bad) set_err(err, ERR_NONFINITE);
 }
 
@@ -279,6 +296,7 @@ struct BatchLayout {
     int64_t *merge_part;
     int64_t merge_tiles_bound;
     int frame_bits;
+    bool seg;  // each frame sorted on its own by its 3 * depth key bits
     size_t bytes;
 };
 
@@ -288,12 +306,26 @@ static int frame_bits_of(int F) {
     return b;
 }
 
+// Up to this many frames the sort is segmented by frame: the frames are
+// already in order, so only the 3 * depth key bits take passes, not the
+// frame bits above them.  Beyond it (many small frames: many part-filled
+// tiles, large per-frame histograms) one sort of the composite keys.
+constexpr int kSegMaxFrames = 4096;
+
+static bool batch_segmented(int F) { return F <= kSegMaxFrames; }
+
+// Key bits the sort passes cover (and the autotuner is asked about).
+static int batch_sort_bits(const cga_grid *g, int F) {
+    return 3 * (int)g->depth + (batch_segmented(F) ? 0 : frame_bits_of(F));
+}
+
 static BatchLayout batch_layout(void *ws, const cga_grid *g, int F, int64_t n, const SortCfg &cfg) {
     BatchLayout L;
     Carve c(ws);
     L.frame_bits = frame_bits_of(F);
+    L.seg = batch_segmented(F);
     L.ctl = c.take<Control>(1);
-    sort_carve(c, L.sort, n, 3 * (int)g->depth + L.frame_bits, cfg);
+    sort_carve(c, L.sort, n, batch_sort_bits(g, F), cfg, L.seg ? F : 0);
     L.rle_status = c.take<uint64_t>((size_t)rle_tiles(n));
     L.buf_a = c.take<uint64_t>((size_t)(n > 0 ? n : 1));
     L.buf_b = c.take<uint64_t>((size_t)(n > 0 ? n : 1));
@@ -321,28 +353,30 @@ static int persistent_groups() {
 
 template <int RB>
 static void batch_encode_launch(const cga_grid *g, const float *xyz, const int64_t *off, int F,
-                                int64_t n, uint64_t *keys, int passes, uint32_t *hist,
+                                int64_t n, uint64_t *keys, int passes, bool seg, uint32_t *hist,
                                 uint32_t *err, hipStream_t s) {
     int64_t blocks = (n + 256 * 8 - 1) / (256 * 8);
     blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+    int64_t chunk = (n + blocks - 1) / blocks;
+    chunk = (chunk + 255) / 256 * 256;
     CGA_PROF("batch_encode", s);
     k_batch_encode<RB><<<(unsigned)blocks, 256, hist_lds_bytes(passes, RB), s>>>(
-        xyz, off, F, n, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth,
-        g->key_mode == CGA_KEY_LINEAR, keys, passes, hist, err);
+        xyz, off, F, n, chunk, g->origin[0], g->origin[1], g->origin[2], g->scale, g->depth,
+        g->key_mode == CGA_KEY_LINEAR, keys, passes, seg ? 1 : 0, hist, err);
 }
 
 static void batch_encode_dispatch(int rb, const cga_grid *g, const float *xyz, const int64_t *off,
-                                  int F, int64_t n, uint64_t *keys, int passes, uint32_t *hist,
-                                  uint32_t *err, hipStream_t s) {
+                                  int F, int64_t n, uint64_t *keys, int passes, bool seg,
+                                  uint32_t *hist, uint32_t *err, hipStream_t s) {
     switch (rb) {
-        case 4: batch_encode_launch<4>(g, xyz, off, F, n, keys, passes, hist, err, s); break;
-        case 5: batch_encode_launch<5>(g, xyz, off, F, n, keys, passes, hist, err, s); break;
-        case 6: batch_encode_launch<6>(g, xyz, off, F, n, keys, passes, hist, err, s); break;
-        case 7: batch_encode_launch<7>(g, xyz, off, F, n, keys, passes, hist, err, s); break;
-        case 9: batch_encode_launch<9>(g, xyz, off, F, n, keys, passes, hist, err, s); break;
-        case 10: batch_encode_launch<10>(g, xyz, off, F, n, keys, passes, hist, err, s); break;
-        case 11: batch_encode_launch<11>(g, xyz, off, F, n, keys, passes, hist, err, s); break;
-        default: batch_encode_launch<8>(g, xyz, off, F, n, keys, passes, hist, err, s); break;
+        case 4: batch_encode_launch<4>(g, xyz, off, F, n, keys, passes, seg, hist, err, s); break;
+        case 5: batch_encode_launch<5>(g, xyz, off, F, n, keys, passes, seg, hist, err, s); break;
+        case 6: batch_encode_launch<6>(g, xyz, off, F, n, keys, passes, seg, hist, err, s); break;
+        case 7: batch_encode_launch<7>(g, xyz, off, F, n, keys, passes, seg, hist, err, s); break;
+        case 9: batch_encode_launch<9>(g, xyz, off, F, n, keys, passes, seg, hist, err, s); break;
+        case 10: batch_encode_launch<10>(g, xyz, off, F, n, keys, passes, seg, hist, err, s); break;
+        case 11: batch_encode_launch<11>(g, xyz, off, F, n, keys, passes, seg, hist, err, s); break;
+        default: batch_encode_launch<8>(g, xyz, off, F, n, keys, passes, seg, hist, err, s); break;
     }
 }
 
@@ -390,10 +424,14 @@ static int batch_enqueue(const BatchArgs &a, hipStream_t s) {
     int64_t *d_u = &L.ctl->count;
     if (n > 0) {
         batch_encode_dispatch(L.sort.radix_bits, &a.g, a.xyz, a.off, a.F, n, L.buf_a, L.sort.passes,
-                              L.sort.hist, &L.ctl->err, s);
+                              L.seg, L.sort.hist, &L.ctl->err, s);
         uint64_t *fin = (L.sort.passes & 1) ? L.buf_b : L.buf_a;
         uint64_t *other = (L.sort.passes & 1) ? L.buf_a : L.buf_b;
-        sort_launch<uint64_t>(L.sort, L.buf_a, fin, other, fin, n, nullptr, true, L.ctl->tile_ctr, s);
+        if (L.seg)
+            sort_launch_seg(L.sort, L.buf_a, fin, other, fin, a.off, L.ctl->tile_ctr, s);
+        else
+            sort_launch<uint64_t>(L.sort, L.buf_a, fin, other, fin, n, nullptr, true,
+                                  L.ctl->tile_ctr, s);
         // unique composite keys go to the buffer the sort did not end in
         {
             CGA_PROF("rle", s);
@@ -505,6 +543,11 @@ size_t cga_batch_workspace_bytes(const cga_grid *g, int nframes, int64_t n) {
     return m;
 }
 
+int cga_batch_sort_bits(const cga_grid *g, int nframes) {
+    if (!grid_valid(g) || nframes < 1 || nframes > 65536) return 0;
+    return batch_sort_bits(g, nframes);
+}
+
 int cga_batch_build_merge(const cga_grid *g, const float *d_xyz, const int64_t *d_off, int nframes,
                           int64_t n, void *d_keys, uint32_t *d_counts, int64_t *d_key_off,
                           void *d_merged, int64_t *d_merged_off, int64_t *d_merged_cnt,
@@ -513,7 +556,7 @@ int cga_batch_build_merge(const cga_grid *g, const float *d_xyz, const int64_t *
                            d_merged_cnt, d_ws));
     BatchArgs a{*g, d_xyz, d_off, nframes, n, d_keys, d_counts, d_key_off, d_merged, d_merged_off,
                 d_merged_cnt, d_ws, ws_bytes, SortCfg()};
-    CGA_TRY(resolve_cfg(tune, 8, 3 * (int)g->depth + frame_bits_of(nframes), n, &a.cfg));
+    CGA_TRY(resolve_cfg(tune, 8, batch_sort_bits(g, nframes), n, &a.cfg));
     return batch_run(a, (hipStream_t)stream);
 }
 
@@ -528,7 +571,7 @@ int cga_batch_graph_create(const cga_grid *g, const float *d_xyz, const int64_t 
                            d_merged_cnt, d_ws));
     BatchArgs a{*g, d_xyz, d_off, nframes, n, d_keys, d_counts, d_key_off, d_merged, d_merged_off,
                 d_merged_cnt, d_ws, ws_bytes, SortCfg()};
-    CGA_TRY(resolve_cfg(tune, 8, 3 * (int)g->depth + frame_bits_of(nframes), n, &a.cfg));
+    CGA_TRY(resolve_cfg(tune, 8, batch_sort_bits(g, nframes), n, &a.cfg));
     if (ws_bytes < batch_layout(nullptr, g, nframes, n, a.cfg).bytes) return CGA_EWORKSPACE;
     persistent_groups();  // query the device before capture
     hipStream_t cs;

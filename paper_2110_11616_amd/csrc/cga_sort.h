@@ -95,12 +95,18 @@ __global__ __launch_bounds__(kSortBlock) void k_histogram(const K *__restrict__ 
 }
 
 // Exclusive scan of each pass's histogram in place (one block per pass).
+// Segmented (nseg > 0): hist[p][f][digit] per pass and segment, one block
+// per (pass, segment), and each scan starts at the segment's first index
+// seg_off[f], so it gives every digit's first output slot directly.
 template <int RB>
-__global__ __launch_bounds__(kSortBlock) void k_hist_scan(uint32_t *hist) {
+__global__ __launch_bounds__(kSortBlock) void k_hist_scan(uint32_t *hist,
+                                                          const int64_t *seg_off = nullptr,
+                                                          int nseg = 0) {
     constexpr int RADIX = 1 << RB;
     constexpr int DPT = RADIX > kSortBlock ? RADIX / kSortBlock : 1;
     __shared__ uint32_t s_w[kSortBlock / 64];
     uint32_t *h = hist + (size_t)blockIdx.x * RADIX;
+    const uint32_t start = nseg > 0 ? (uint32_t)seg_off[blockIdx.x % nseg] : 0u;
     uint32_t v[DPT], sum = 0;
     const int t = threadIdx.x;
 #pragma unroll
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(kSortBlock) void k_hist_scan(uint32_t *hist) {
         sum += v[j];
     }
     uint32_t tot;
-    uint32_t ex = block_excl_sum<kSortBlock>(sum, s_w, &tot);
+    uint32_t ex = start + block_excl_sum<kSortBlock>(sum, s_w, &tot);
 #pragma unroll
     for (int j = 0; j < DPT; ++j) {
         int d = t * DPT + j;
@@ -119,16 +125,46 @@ __global__ __launch_bounds__(kSortBlock) void k_hist_scan(uint32_t *hist) {
     }
 }
 
+// Segments of consecutive keys, seg_off[0..nseg] (seg_off[nseg] = n), each
+// cut into its own tiles of `tile` keys: seg_tiles[f] = first tile of
+// segment f, seg_tiles[nseg] = the number of tiles.  One block of BLOCK.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_seg_tiles(const int64_t *__restrict__ seg_off, int nseg,
+                                                     int64_t tile, int64_t *__restrict__ seg_tiles) {
+    __shared__ int64_t s_w[BLOCK / 64];
+    int64_t carry = 0;
+    for (int f0 = 0; f0 < nseg; f0 += BLOCK) {
+        const int f = f0 + (int)threadIdx.x;
+        const int64_t len = f < nseg ? seg_off[f + 1] - seg_off[f] : 0;
+        const int64_t t = (len + tile - 1) / tile;
+        int64_t tot;
+        const int64_t ex = block_excl_sum<BLOCK>(t, s_w, &tot);
+        if (f < nseg) seg_tiles[f] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) seg_tiles[nseg] = carry;
+}
+
 // --------------------------------------------------------- onesweep pass
 // One LSD pass on digit bits [shift, shift + RB).  `look` holds one status
 // word per (tile, digit) and must be zero on entry; each tile also zeroes its
 // own slots of `look_next`, the status array of the following pass.  With a
 // payload type V, vin[i] travels with in[i] to the same output slot.
-template <typename K, int RB, int ITEMS, typename V = NoVal>
+//
+// SEG: a segmented pass.  The keys are nseg segments [seg_off[f],
+// seg_off[f + 1]), each sorted on its own within its own range; tiles never
+// straddle a segment (seg_tiles from k_seg_tiles), digit_base holds
+// per-segment digit starts (k_hist_scan with segments), and the look-back of
+// a tile stops at its segment's first tile, which publishes an inclusive
+// count at once.  Segments already ordered by a key prefix (frames of a
+// batch) then need no passes over that prefix.
+template <typename K, int RB, int ITEMS, typename V = NoVal, bool SEG = false>
 __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     const K *__restrict__ in, K *__restrict__ out, int64_t n_host, const int64_t *d_n, int shift,
     const uint32_t *__restrict__ digit_base, uint32_t *look, uint32_t *look_next,
-    uint32_t *tile_ctr, const V *__restrict__ vin = nullptr, V *__restrict__ vout = nullptr) {
+    uint32_t *tile_ctr, const V *__restrict__ vin = nullptr, V *__restrict__ vout = nullptr,
+    const int64_t *__restrict__ seg_off = nullptr, const int64_t *__restrict__ seg_tiles = nullptr,
+    int nseg = 0) {
     constexpr bool kHasVal = !std::is_same<V, NoVal>::value;
     constexpr int BLOCK = kSortBlock;
     constexpr int RADIX = 1 << RB;
@@ -147,9 +183,25 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     for (int i = tid; i < WAVES * RADIX; i += BLOCK) (&s_wcnt[0][0])[i] = 0;
     const uint32_t tile = next_tile(tile_ctr, &s_tile);
-    const int64_t n = dev_count(n_host, d_n);
-    const int64_t base = (int64_t)tile * TILE;
-    if (base >= n) return;  // uniform across the block
+    int64_t base, n;     // this tile's first key; one past the last key of its range
+    uint32_t first = 0;  // first tile of the range the look-back may not leave
+    if constexpr (SEG) {
+        if ((int64_t)tile >= seg_tiles[nseg]) return;  // uniform across the block
+        int lo = 0, len = nseg;  // last segment whose first tile is <= tile
+        while (len > 1) {
+            const int half = len >> 1;
+            lo = seg_tiles[lo + half] <= (int64_t)tile ? lo + half : lo;
+            len -= half;
+        }
+        first = (uint32_t)seg_tiles[lo];
+        base = seg_off[lo] + (int64_t)(tile - first) * TILE;
+        n = seg_off[lo + 1];
+        digit_base += (size_t)lo * RADIX;
+    } else {
+        n = dev_count(n_host, d_n);
+        base = (int64_t)tile * TILE;
+        if (base >= n) return;  // uniform across the block
+    }
 
     for (int d = tid; d < RADIX; d += BLOCK) look_next[(size_t)tile * RADIX + d] = 0;
 
@@ -201,7 +253,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
                 s += c;
             }
             // publish this tile's digit count for the tiles after it
-            st_agent(&look[(size_t)tile * RADIX + d], (tile == 0 ? kFlagInc : kFlagAgg) | s);
+            st_agent(&look[(size_t)tile * RADIX + d], (tile == first ? kFlagInc : kFlagAgg) | s);
         }
         cnt[j] = s;
         tsum += s;
@@ -217,10 +269,12 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
         if (d < RADIX) {
             s_boff[d] = ex;
             uint32_t before = 0;
-            if (tile > 0) {
+            if (tile > first) {
                 // kLookWindow predecessors per round trip: their loads are
                 // independent, so a walk over aggregates costs one latency
-                // per window, not per tile
+                // per window, not per tile (the walk ends at the range's
+                // first tile, inclusive from the start, before it could
+                // count a tile of another segment)
                 int64_t t = (int64_t)tile - 1;
                 for (;;) {
                     uint32_t st[kLookWindow];
@@ -277,19 +331,26 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
 
 // ------------------------------------------------------------------ host
 struct SortWs {
-    uint32_t *hist = nullptr;   // passes * RADIX
+    uint32_t *hist = nullptr;   // passes * RADIX (segmented: passes * nseg * RADIX)
     uint32_t *look[2] = {nullptr, nullptr};
     int passes = 0, radix_bits = 8, items = 16;
     int64_t tiles = 0;
+    int nseg = 0;
+    int64_t *seg_tiles = nullptr;  // segmented: nseg + 1 tile starts
 };
 
-inline void sort_carve(Carve &c, SortWs &w, int64_t n, int key_bits, const SortCfg &cfg) {
+// nseg > 0: a segmented sort of nseg segments (histograms per pass and
+// segment, up to nseg more tiles, the segment tile table).
+inline void sort_carve(Carve &c, SortWs &w, int64_t n, int key_bits, const SortCfg &cfg,
+                       int nseg = 0) {
     w.radix_bits = cfg.radix_bits;
     w.items = cfg.items;
     w.passes = sort_passes(key_bits, cfg.radix_bits);
-    w.tiles = sort_tiles(n, cfg.items);
+    w.tiles = sort_tiles(n, cfg.items) + nseg;
+    w.nseg = nseg;
     const size_t radix = (size_t)1 << cfg.radix_bits;
-    w.hist = c.take<uint32_t>((size_t)kMaxPasses * radix);
+    w.seg_tiles = nseg > 0 ? c.take<int64_t>((size_t)nseg + 1) : nullptr;
+    w.hist = c.take<uint32_t>((size_t)(nseg > 0 ? w.passes * nseg : kMaxPasses) * radix);
     w.look[0] = c.take<uint32_t>((size_t)w.tiles * radix);
     w.look[1] = c.take<uint32_t>((size_t)w.tiles * radix);
 }
@@ -383,6 +444,62 @@ inline void sort_launch(const SortWs &w, const K *in, K *out, K *alt0, K *alt1, 
         case 10: sort_launch_rb<K, 10>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
         case 11: sort_launch_rb<K, 11>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
         default: sort_launch_rb<K, 8>(w, in, out, alt0, alt1, n_host, d_n, have_hist, tile_ctr, s); break;
+    }
+}
+
+template <int RB, int ITEMS>
+inline void onesweep_seg_launch(const SortWs &w, const uint64_t *src, uint64_t *dst,
+                                const int64_t *seg_off, int pass, uint32_t *tile_ctr,
+                                hipStream_t s) {
+    const size_t radix = (size_t)1 << RB;
+    CGA_PROF("onesweep", s);
+    k_onesweep<uint64_t, RB, ITEMS, NoVal, true><<<(unsigned)w.tiles, kSortBlock, 0, s>>>(
+        src, dst, 0, nullptr, pass * RB, w.hist + (size_t)pass * w.nseg * radix, w.look[pass & 1],
+        w.look[(pass + 1) & 1], tile_ctr + pass, nullptr, nullptr, seg_off, w.seg_tiles, w.nseg);
+}
+
+template <int RB>
+inline void sort_launch_seg_rb(const SortWs &w, const uint64_t *in, uint64_t *out, uint64_t *alt0,
+                               uint64_t *alt1, const int64_t *seg_off, uint32_t *tile_ctr,
+                               hipStream_t s) {
+    {
+        CGA_PROF("hist_scan", s);
+        k_seg_tiles<1024><<<1, 1024, 0, s>>>(seg_off, w.nseg, (int64_t)kSortBlock * w.items, w.seg_tiles);
+        k_hist_scan<RB><<<(unsigned)(w.passes * w.nseg), kSortBlock, 0, s>>>(w.hist, seg_off,
+                                                                             w.nseg);
+    }
+    const uint64_t *src = in;
+    for (int p = 0; p < w.passes; ++p) {
+        uint64_t *dst = p == w.passes - 1 ? out : (((w.passes - 1 - p) & 1) ? alt0 : alt1);
+        switch (w.items) {
+            case 8: onesweep_seg_launch<RB, 8>(w, src, dst, seg_off, p, tile_ctr, s); break;
+            case 12: onesweep_seg_launch<RB, 12>(w, src, dst, seg_off, p, tile_ctr, s); break;
+            case 24: onesweep_seg_launch<RB, 24>(w, src, dst, seg_off, p, tile_ctr, s); break;
+            case 32: onesweep_seg_launch<RB, 32>(w, src, dst, seg_off, p, tile_ctr, s); break;
+            default: onesweep_seg_launch<RB, 16>(w, src, dst, seg_off, p, tile_ctr, s); break;
+        }
+        src = dst;
+    }
+}
+
+// Segmented sort of 64-bit keys (`w` carved with nseg segments): every
+// segment [seg_off[f], seg_off[f + 1]) sorted on its own by the low
+// passes * radix_bits bits, in place within its range; the histograms
+// hist[p][f][digit] already accumulated (the batched encode does that).
+// Buffer chain, zeroed state and tile counters as in sort_launch.
+inline void sort_launch_seg(const SortWs &w, const uint64_t *in, uint64_t *out, uint64_t *alt0,
+                            uint64_t *alt1, const int64_t *seg_off, uint32_t *tile_ctr,
+                            hipStream_t s) {
+    if (w.passes == 0 || w.nseg < 1) return;
+    switch (w.radix_bits) {
+        case 4: sort_launch_seg_rb<4>(w, in, out, alt0, alt1, seg_off, tile_ctr, s); break;
+        case 5: sort_launch_seg_rb<5>(w, in, out, alt0, alt1, seg_off, tile_ctr, s); break;
+        case 6: sort_launch_seg_rb<6>(w, in, out, alt0, alt1, seg_off, tile_ctr, s); break;
+        case 7: sort_launch_seg_rb<7>(w, in, out, alt0, alt1, seg_off, tile_ctr, s); break;
+        case 9: sort_launch_seg_rb<9>(w, in, out, alt0, alt1, seg_off, tile_ctr, s); break;
+        case 10: sort_launch_seg_rb<10>(w, in, out, alt0, alt1, seg_off, tile_ctr, s); break;
+        case 11: sort_launch_seg_rb<11>(w, in, out, alt0, alt1, seg_off, tile_ctr, s); break;
+        default: sort_launch_seg_rb<8>(w, in, out, alt0, alt1, seg_off, tile_ctr, s); break;
     }
 }
 

@@ -70,6 +70,22 @@ def test_key_widths_and_workspace_queries(lib):
     assert lib.cga_merge_workspace_bytes(ctypes.byref(grid(12)), 10, 10) >= 256
 
 
+def test_batch_sort_bits(lib):
+    """The batched sort covers the 3 * depth key bits when it is segmented
+    by frame (up to 4096 frames), the frame bits too beyond that."""
+    f = lib.cga_batch_sort_bits
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    g = grid(12)
+    assert f(ctypes.byref(g), 1) == 36
+    assert f(ctypes.byref(g), 256) == 36
+    assert f(ctypes.byref(g), 4096) == 36
+    assert f(ctypes.byref(g), 4097) == 36 + 13
+    assert f(ctypes.byref(g), 65536) == 36 + 16
+    assert f(ctypes.byref(g), 0) == 0 and f(ctypes.byref(g), 65537) == 0
+    assert f(ctypes.byref(grid(0)), 4) == 0
+
+
 class IndexParams(ctypes.Structure):
     _fields_ = [("n_leaves", ctypes.c_uint32), ("leaf_kind", ctypes.c_uint32),
                 ("epochs", ctypes.c_uint32), ("lr", ctypes.c_float),

@@ -82,6 +82,38 @@ def test_batch_single_and_tiny(gpu):
         _check(gpu, dict(xyz=xyz, off=off, grid=g), out)
 
 
+def test_batch_segment_tile_edges(gpu):
+    """Frames of exactly one tile, one tile and one key, two tiles, with
+    empty frames between, under a fixed 4096-key tile (the frame-segmented
+    sort): every frame sorted within its own range."""
+    g = gen.Grid((0.0, 0.0, 0.0), 1.0, 10, gen.KEY_MORTON)
+    rng = np.random.default_rng(11)
+    sizes = [4096, 0, 4097, 8192, 1, 0, 0, 8191, 12289, 2]
+    xyz = rng.integers(0, 1024, (sum(sizes), 3)).astype(np.float32)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    for tune in ((8, 16), (7, 16), (9, 32)):
+        say("segmented batch sort, tune", tune)
+        out = gpu.cga_batch_build_merge(dev(xyz), dev(off), g, tune=tune)
+        _check(gpu, dict(xyz=xyz, off=off, grid=g), out)
+
+
+def test_batch_many_frames_composite_sort(gpu):
+    """Beyond 4096 frames the batch sorts the composite keys (frame bits
+    included) in one sort: 4100 frames of 0 to 40 points, and 4096 frames
+    (segmented) of the same points, both against the oracle."""
+    g = gen.Grid((0.0, 0.0, 0.0), 1.0, 8, gen.KEY_MORTON)
+    rng = np.random.default_rng(12)
+    for nf in (4100, 4096):
+        assert gpu.cga_batch_sort_bits(g, nf) == 24 + (13 if nf > 4096 else 0)
+        sizes = rng.integers(0, 41, nf)
+        sizes[rng.choice(nf, nf // 10, replace=False)] = 0
+        xyz = rng.integers(0, 256, (int(sizes.sum()), 3)).astype(np.float32)
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        say("batch of", nf, "frames,", len(xyz), "points")
+        out = gpu.cga_batch_build_merge(dev(xyz), dev(off), g)
+        _check(gpu, dict(xyz=xyz, off=off, grid=g), out)
+
+
 def test_graph_replays_match_eager(gpu, frames):
     xyz, off, g = dev(frames["xyz"]), dev(frames["off"]), frames["grid"]
     ref = gpu.cga_batch_build_merge(xyz, off, g)
