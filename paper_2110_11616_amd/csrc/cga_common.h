@@ -90,6 +90,23 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
+// Lanes of the wave whose value v has the same low `bits` bits as this
+// lane's: per bit, the ballot of the lanes that have it set, flipped where
+// this lane has it clear (x ^ 0 or x ^ ~0, the bit's sign extension), and
+// any flipped-in difference rules a lane out.
+template <int BITS>
+__device__ __forceinline__ uint64_t match_low_bits(uint32_t v) {
+    uint32_t diff_lo = 0, diff_hi = 0;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const int32_t neg = __builtin_amdgcn_sbfe((int32_t)v, b, 1);  // 0 or -1
+        const uint64_t bal = __ballot(neg != 0);
+        diff_lo |= (uint32_t)bal ^ (uint32_t)neg;
+        diff_hi |= (uint32_t)(bal >> 32) ^ (uint32_t)neg;
+    }
+    return ~(((uint64_t)diff_hi << 32) | diff_lo);
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     return (uint64_t(1) << lane_id()) - 1;  // lane 0 -> 0
 }

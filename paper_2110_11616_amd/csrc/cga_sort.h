@@ -209,14 +209,15 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     // lane l is element i*64 + l, so (wave, item, lane) order is input order.
     K keys[ITEMS];
     V vals[kHasVal ? ITEMS : 1];
-    uint32_t dig[ITEMS];
+    // a key's digit is recomputed where needed (two instructions) rather
+    // than held: registers, not ALU, bound how many tiles a CU keeps in flight
+    auto digit = [&](K k) { return (uint32_t)(k >> shift) & (RADIX - 1); };
     const int64_t wbase = base + (int64_t)wave * 64 * ITEMS + lane;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         int64_t idx = wbase + i * 64;
         keys[i] = idx < n ? in[idx] : ~K(0);  // padding sorts last, never written
         if constexpr (kHasVal) vals[i] = idx < n ? vin[idx] : V(0);
-        dig[i] = (uint32_t)(keys[i] >> shift) & (RADIX - 1);
     }
 
     // Wave-level multisplit: lanes sharing a digit, found with RB ballots.
@@ -224,17 +225,12 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        uint64_t m = ~0ull;
-#pragma unroll
-        for (int b = 0; b < RB; ++b) {
-            bool bit = (dig[i] >> b) & 1u;
-            uint64_t bal = ballot64(bit);
-            m &= bit ? bal : ~bal;
-        }
-        uint32_t before = s_wcnt[wave][dig[i]];
+        const uint32_t di = digit(keys[i]);
+        const uint64_t m = match_low_bits<RB>(di);
+        uint32_t before = s_wcnt[wave][di];
         uint32_t pre = (uint32_t)__popcll(m & lt);
         rank[i] = before + pre;
-        if (pre == 0) s_wcnt[wave][dig[i]] = before + (uint32_t)__popcll(m);
+        if (pre == 0) s_wcnt[wave][di] = before + (uint32_t)__popcll(m);
     }
     __syncthreads();
 
@@ -309,19 +305,32 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(
     // Stage the tile in LDS in (digit, input order) order.
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        uint32_t pos = s_boff[dig[i]] + s_wcnt[wave][dig[i]] + rank[i];
+        const uint32_t di = digit(keys[i]);
+        uint32_t pos = s_boff[di] + s_wcnt[wave][di] + rank[i];
         s_keys[pos] = keys[i];
         if constexpr (kHasVal) s_vals[pos] = vals[i];
     }
     __syncthreads();
 
     // Scatter: consecutive threads write consecutive slots of one bucket.
+    // A full tile holds no padding, so every slot is written: straight-line
+    // code whose LDS reads the compiler can issue ahead of the stores.
+    if (base + TILE <= n) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int j = i * BLOCK + tid;
+            const K k = s_keys[j];
+            const int64_t g = s_glob[digit(k)] + j;
+            out[g] = k;
+            if constexpr (kHasVal) vout[g] = s_vals[j];
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         int j = i * BLOCK + tid;
         K k = s_keys[j];
-        uint32_t d = (uint32_t)(k >> shift) & (RADIX - 1);
-        int64_t g = s_glob[d] + j;
+        int64_t g = s_glob[digit(k)] + j;
         if (g >= 0 && g < n) {
             out[g] = k;
             if constexpr (kHasVal) vout[g] = s_vals[j];
