@@ -255,14 +255,36 @@ __global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, 
     }
 }
 
-// Pass 4: one thread per node: child mask from the children's octants, and
-// the packed node word.  With emit set, the masks are also the octree's
-// occupancy codes, written to occ (nullable) root first, level by level,
-// cells in key order (level L starts after the codes of levels depth .. L + 1),
-// and counts (nullable) gets the cells per level.
+// Node word: child mask in bits 0-7, first child index in bits 8-38, and in
+// bits 40-63 the bounding box of the node's voxels, per axis a (x, y, z) a
+// 4-bit low and high bound at bits 40 + 8a and 44 + 8a, in units of 1/16 of
+// the cell (of a voxel below level 4): voxel offsets [lo << s, ((hi + 1) << s)
+// - 1] within the cell, s = max(level - 4, 0), rounded outwards.  On a
+// surface a cell's voxels fill a thin slab of it, so distances to the box
+// bound the distances to the voxels far more tightly than the cell's do.
+constexpr uint64_t kNodeFirstMask = 0x7FFFFFFFull;
+constexpr int kNodeBoxShift = 40;
+__host__ __device__ __forceinline__ int64_t node_first(uint64_t w) {
+    return (int64_t)((w >> 8) & kNodeFirstMask);
+}
+__device__ __forceinline__ int box_unit_shift(int level) { return level > 4 ? level - 4 : 0; }
+__device__ __forceinline__ void node_box(uint64_t w, int a, int level, uint32_t &lo, uint32_t &hi) {
+    const int s = box_unit_shift(level);
+    const uint32_t f = (uint32_t)(w >> (kNodeBoxShift + 8 * a));
+    lo = (f & 15u) << s;
+    hi = ((((f >> 4) & 15u) + 1u) << s) - 1u;
+}
+
+// Pass 4, one launch per level from the voxels up (a level's boxes are the
+// union of its children's): one thread per node of level lev, the child mask
+// from the children's octants, the box, and the packed node word.  With emit
+// set, the masks are also the octree's occupancy codes, written to occ
+// (nullable) root first, level by level, cells in key order (level L starts
+// after the codes of levels depth .. L + 1), and counts (nullable) gets the
+// cells per level.
 template <typename K>
 __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, uint32_t depth,
-                                                   const int64_t *__restrict__ lvl,
+                                                   uint32_t lev, const int64_t *__restrict__ lvl,
                                                    const uint32_t *__restrict__ first,
                                                    const uint8_t *__restrict__ oct,
                                                    uint64_t *__restrict__ node, int64_t nodes_max,
@@ -282,23 +304,39 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
     }
     __syncthreads();
     const int64_t total = s_base[depth + 1];
-    if (emit && blockIdx.x == 0) {
+    if (emit && lev == 1 && blockIdx.x == 0) {
         if (counts && threadIdx.x <= depth) counts[threadIdx.x] = s_n[threadIdx.x];
         if (threadIdx.x == 0 && occ && total > occ_cap) set_err(err, ERR_CAPACITY);
     }
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
-        uint32_t L = 1;
-        while (L < depth && t >= s_base[L + 1]) ++L;
-        const int64_t j = t - s_base[L];
+    if (total == 0) return;  // block-uniform: no keys, or an oversized tree
+    const uint32_t L = lev;
+    const int ps = box_unit_shift((int)L);
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < s_n[L]; j += (int64_t)gridDim.x * 256) {
+        const int64_t t = s_base[L] + j;
         const int64_t f0 = first[t];
         int64_t f1 = j + 1 < s_n[L] ? (int64_t)first[t + 1] : s_n[L - 1];
         if (f1 > f0 + 8) f1 = f0 + 8;  // eight children at most (unique keys)
         uint32_t mask = 0;
+        uint32_t lo[3] = {~0u, ~0u, ~0u}, hi[3] = {0u, 0u, 0u};
         for (int64_t c = f0; c < f1; ++c) {
             const uint32_t o = L == 1 ? (uint32_t)((uint64_t)keys[c] & 7) : oct[s_base[L - 1] + c];
             mask |= 1u << o;
+            const uint64_t cw = L == 1 ? 0ull : node[s_base[L - 1] + c];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                // the child's cell sits at offset bit(o, a) * 2^(L - 1) of this cell
+                const uint32_t off = ((o >> (2 - a)) & 1u) << (L - 1);
+                uint32_t clo = 0, chi = 0;
+                if (L > 1) node_box(cw, a, (int)L - 1, clo, chi);
+                lo[a] = min(lo[a], off + clo);
+                hi[a] = max(hi[a], off + chi);
+            }
         }
-        node[t] = ((uint64_t)f0 << 8) | mask;
+        uint64_t box = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            box |= (uint64_t)(((lo[a] >> ps) & 15u) | (((hi[a] >> ps) & 15u) << 4)) << (8 * a);
+        node[t] = (box << kNodeBoxShift) | ((uint64_t)f0 << 8) | mask;
         if (emit && occ) {
             const int64_t o = total - s_base[L + 1] + j;  // codes of levels above L come first
             if (o < occ_cap) occ[o] = (uint8_t)mask;
@@ -603,7 +641,7 @@ void k_knn_tree(
             --L;
             const uint32_t oc = (((x >> L) & 1u) << 2) | (((y >> L) & 1u) << 1) | ((z >> L) & 1u);
             if (!((w >> oc) & 1u)) return -1;
-            nj = (int64_t)(w >> 8) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
+            nj = node_first(w) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
         }
         return nj;
     };
@@ -695,19 +733,24 @@ void k_knn_tree(
                 const int cl = l - 1;
                 qol = qo(cl);
                 // gaps to the low half [0, h) and the high half [h, 2h) of the
-                // node along an axis, from the query's signed offset t (every
-                // coordinate is below 2^21): max(-t, t - (h - 1), 0) and
-                // max(h - t, t - (2h - 1), 0)
+                // node along an axis, each cut to the node's voxel box
+                // [blo, bhi], from the query's signed offset t (every
+                // coordinate is below 2^21): max(a - t, t - b, 0) over the
+                // cut interval [a, b] (an empty cut has no child to visit)
                 const int32_t h = 1 << cl;
-                auto gaps = [&](uint32_t q, uint32_t c0, Dist &lo2, Dist &hi2) __attribute__((always_inline)) {
+                auto gaps = [&](int a, uint32_t q, uint32_t c0, Dist &lo2, Dist &hi2) __attribute__((always_inline)) {
+                    uint32_t blo, bhi;
+                    node_box(w, a, l, blo, bhi);
                     const int32_t t = (int32_t)(q - c0);
-                    const int32_t gl = max(max(-t, t - (h - 1)), 0), gh = max(max(h - t, t - (2 * h - 1)), 0);
+                    const int32_t la_ = (int32_t)blo, lb = min((int32_t)bhi, h - 1);
+                    const int32_t ha = max((int32_t)blo, h), hb = min((int32_t)bhi, 2 * h - 1);
+                    const int32_t gl = max(max(la_ - t, t - lb), 0), gh = max(max(ha - t, t - hb), 0);
                     lo2 = (Dist)gl * (Dist)gl;
                     hi2 = (Dist)gh * (Dist)gh;
                 };
-                gaps(qv.x, x0, gxl, gxh);
-                gaps(qv.y, y0, gyl, gyh);
-                gaps(qv.z, z0, gzl, gzh);
+                gaps(0, qv.x, x0, gxl, gxh);
+                gaps(1, qv.y, y0, gyl, gyh);
+                gaps(2, qv.z, z0, gzl, gzh);
                 touch = skip && cl == sk_l;
                 bnd = to_dist(bound_now());
                 // children already beyond the bound never take a step
@@ -737,7 +780,7 @@ void k_knn_tree(
                     const uint32_t cx = ((uint32_t)sc & 0x1FFFFFu) | (((qs >> 2) & 1u) << l0);
                     const uint32_t cy = ((uint32_t)(sc >> 21) & 0x1FFFFFu) | (((qs >> 1) & 1u) << l0);
                     const uint32_t cz = ((uint32_t)(sc >> 42) & 0x1FFFFFu) | ((qs & 1u) << l0);
-                    const int32_t ci = (int32_t)(sw >> 8) + __popc((uint32_t)sw & 0xFFu & ((1u << qs) - 1u));
+                    const int32_t ci = (int32_t)node_first(sw) + __popc((uint32_t)sw & 0xFFu & ((1u << qs) - 1u));
                     const Dist bd = box_dist(cx, cy, cz, l0);
                     if (bd <= bound_now() && !skipped(cx, cy, cz, l0)) {
                         if (l0 == 0) {
@@ -770,7 +813,7 @@ void k_knn_tree(
                     const uint32_t cx = x0 | (((oc >> 2) & 1u) << cl), cy = y0 | (((oc >> 1) & 1u) << cl),
                                    cz = z0 | ((oc & 1u) << cl);
                     if (bd <= bnd && !(touch && skipped(cx, cy, cz, cl))) {
-                        const int32_t ci = (int32_t)(w >> 8) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
+                        const int32_t ci = (int32_t)node_first(w) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
                         if (cl == 0) {
                             offer(bd, ci);
                             bnd = kth < (uint64_t)bnd ? to_dist(kth) : bnd;
@@ -983,10 +1026,16 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
     k_tree_build<K><<<(unsigned)L.tiles, 256, 0, s>>>(keys, n, d_n, depth, dt, L.tiles, L.cnt, L.lvl,
                                                       L.first, L.oct, L.dense, dense_cells(depth, L.dl),
                                                       L.nodes);
-    int64_t blocks = (L.nodes + 255) / 256;
-    blocks = blocks < 4096 ? blocks : 4096;
-    k_tree_mask<K><<<(unsigned)blocks, 256, 0, s>>>(keys, depth, L.lvl, L.first, L.oct, L.node,
-                                                    L.nodes, emit, occ, occ_cap, counts, &L.ctl->err);
+    for (uint32_t lev = 1; lev <= depth; ++lev) {
+        // level lev holds at most min(n, 8^(depth - lev)) nodes
+        const uint32_t e = 3 * (depth - lev);
+        const int64_t cap = e >= 62 ? INT64_MAX : (int64_t)1 << e;
+        int64_t blocks = ((n < cap ? n : cap) + 255) / 256;
+        blocks = blocks < 1 ? 1 : (blocks < 4096 ? blocks : 4096);
+        k_tree_mask<K><<<(unsigned)blocks, 256, 0, s>>>(keys, depth, lev, L.lvl, L.first, L.oct,
+                                                        L.node, L.nodes, emit, occ, occ_cap, counts,
+                                                        &L.ctl->err);
+    }
 }
 
 template <int KT, bool kCount = false>
