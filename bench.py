@@ -1036,7 +1036,8 @@ def main():
     # counter run of the same kernel sources
     work = knn_work(cga, pipe)
     progress(f"k-NN work per query: {work}")
-    knn_bytes_q = 12 + 16 * pipe.k + 8 * work["node_loads"] + 4 * work["dense_loads"]
+    # a node visit reads the node's two words (mask and first child; oriented box)
+    knn_bytes_q = 12 + 16 * pipe.k + 16 * work["node_loads"] + 4 * work["dense_loads"]
     knn = {"queries": nq, "k": pipe.k, "stage_ms": round(st[2], 4),
            "queries_per_s": nq / (st[2] * 1e-3),
            "work_per_query": {k: round(v, 2) for k, v in work.items()},

@@ -4,14 +4,21 @@
 // In Morton order every octree cell is a contiguous run of keys, so the array
 // already is a pointer-free octree; searching it directly costs a binary
 // search for every cell visited.  Each call therefore first derives the
-// explicit octree of the array, level by level from the voxels up, in four
-// passes over the keys:
+// explicit octree of the array, level by level from the voxels up (node
+// counts, a scan, node indexes, then per level the node words, and the
+// oriented boxes of the lower levels from their voxels):
 //   level-L node j (L = 1..depth) is the j-th distinct prefix key >> 3L;
-//   its 64-bit word is first << 8 | mask, where first indexes its first child
-//   at level L - 1 (a key index at L = 1) and bit o of mask says whether the
-//   child in octant o exists.  Child o is then node first + popcount(mask
-//   below bit o): one 8-byte load per visited node, and no load at all for
+//   its first 64-bit word holds first and mask, where first indexes its
+//   first child at level L - 1 (a key index at L = 1) and bit o of mask says
+//   whether the child in octant o exists, plus the axis-aligned box of its
+//   voxels; its second word an oriented box of its voxels (a slab along
+//   their least-variance direction).  Child o is node first + popcount(mask
+//   below bit o): one 16-byte load per visited node, and no load at all for
 //   the voxels under a level-1 node, whose coordinates follow from the path.
+//   The boxes bound the distance from a query to a node's voxels: a child
+//   whose axis-aligned box, cut to its parent's, lies beyond the k-th
+//   distance is never loaded, and a loaded node whose oriented box does
+//   opens no child.
 // A dense table maps every level-DT cell (DT = depth - DL, 8^DL cells, DL up
 // to 7 and no more than about log8 of the key count, so that clearing it
 // costs no more than the keys themselves) to its node, so a search enters the
@@ -188,6 +195,7 @@ __global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, 
                                                     int64_t tiles, const uint32_t *__restrict__ cnt,
                                                     const int64_t *__restrict__ lvl,
                                                     uint32_t *__restrict__ first,
+                                                    uint32_t *__restrict__ kfirst,
                                                     uint8_t *__restrict__ oct,
                                                     uint32_t *__restrict__ dense, int64_t ncells,
                                                     int64_t nodes_max) {
@@ -246,6 +254,7 @@ __global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, 
                 const int64_t j = (int64_t)before + mbcnt64(b);
                 const int64_t t = s_base[L] + j;
                 first[t] = (uint32_t)child;
+                kfirst[t] = (uint32_t)i;
                 oct[t] = (uint8_t)(((uint64_t)keys[i] >> (3 * L)) & 7);
                 const uint64_t dc = (uint64_t)keys[i] >> (3 * dt);
                 if (L == dt && dc < (uint64_t)ncells) dense[dc] = (uint32_t)j + 1;
@@ -263,6 +272,8 @@ __global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, 
 // surface a cell's voxels fill a thin slab of it, so distances to the box
 // bound the distances to the voxels far more tightly than the cell's do.
 constexpr uint64_t kNodeFirstMask = 0x7FFFFFFFull;
+constexpr int kScanLevels = 9;  // levels whose oriented boxes are fitted to the voxels
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 constexpr int kNodeBoxShift = 40;
 __host__ __device__ __forceinline__ int64_t node_first(uint64_t w) {
     return (int64_t)((w >> 8) & kNodeFirstMask);
@@ -273,6 +284,107 @@ __device__ __forceinline__ void node_box(uint64_t w, int a, int level, uint32_t 
     const uint32_t f = (uint32_t)(w >> (kNodeBoxShift + 8 * a));
     lo = (f & 15u) << s;
     hi = ((((f >> 4) & 15u) + 1u) << s) - 1u;
+}
+
+// Second word of a node: an oriented box holding the node's voxels.  Its
+// axes are n, the direction in which the voxel positions vary least (on a
+// surface, its normal), stored octahedrally in 7 + 7 bits, and e1, e2, which
+// complete the decoded n to an orthonormal frame; per axis an 8-bit signed
+// range [lo, hi] of the voxels' offsets from the cell centre along it, in
+// units of 1/128 of the cell, rounded outwards.  A far query sees a surface
+// cell's voxels in a slab a few voxels thick along n, while its axis-aligned
+// box can be as deep as the cell: the distance to the oriented box bounds the
+// distance to the voxels far more tightly.  (Bits: u 0-6, v 7-13, then lo,
+// hi of n at 14 and 22, of e1 at 30 and 38, of e2 at 46 and 54.)
+struct Frame {
+    float a[3][3];  // rows n, e1, e2
+};
+
+__device__ __forceinline__ float sgnf(float v) { return v >= 0.f ? 1.f : -1.f; }
+
+__device__ __forceinline__ uint32_t oct_encode(float x, float y, float z) {
+    float l1 = fabsf(x) + fabsf(y) + fabsf(z);
+    if (!(l1 > 0.f)) {
+        x = 0.f;
+        y = 0.f;
+        z = 1.f;
+        l1 = 1.f;
+    }
+    float px = x / l1, py = y / l1;
+    if (z < 0.f) {
+        const float tx = (1.f - fabsf(py)) * sgnf(px), ty = (1.f - fabsf(px)) * sgnf(py);
+        px = tx;
+        py = ty;
+    }
+    const int u = min(max((int)rintf((px * 0.5f + 0.5f) * 127.f), 0), 127);
+    const int v = min(max((int)rintf((py * 0.5f + 0.5f) * 127.f), 0), 127);
+    return (uint32_t)u | ((uint32_t)v << 7);
+}
+
+__device__ __forceinline__ Frame frame_decode(uint32_t code) {
+    float px = (float)(code & 127u) * (2.f / 127.f) - 1.f;
+    float py = (float)((code >> 7) & 127u) * (2.f / 127.f) - 1.f;
+    const float pz = 1.f - fabsf(px) - fabsf(py);
+    if (pz < 0.f) {
+        const float tx = (1.f - fabsf(py)) * sgnf(px), ty = (1.f - fabsf(px)) * sgnf(py);
+        px = tx;
+        py = ty;
+    }
+    Frame f;
+    const float r = rsqrtf(px * px + py * py + pz * pz);
+    const float n0 = px * r, n1 = py * r, n2 = pz * r;
+    // e1 = n x (the unit axis along which n is smallest), normalised
+    const float ax = fabsf(n0), ay = fabsf(n1), az = fabsf(n2);
+    float c0, c1, c2;
+    if (ax <= ay && ax <= az) {  // axis x
+        c0 = 0.f;
+        c1 = n2;
+        c2 = -n1;
+    } else if (ay <= az) {  // axis y
+        c0 = -n2;
+        c1 = 0.f;
+        c2 = n0;
+    } else {  // axis z
+        c0 = n1;
+        c1 = -n0;
+        c2 = 0.f;
+    }
+    const float rc = rsqrtf(c0 * c0 + c1 * c1 + c2 * c2);
+    c0 *= rc;
+    c1 *= rc;
+    c2 *= rc;
+    f.a[0][0] = n0;
+    f.a[0][1] = n1;
+    f.a[0][2] = n2;
+    f.a[1][0] = c0;
+    f.a[1][1] = c1;
+    f.a[1][2] = c2;
+    f.a[2][0] = n1 * c2 - n2 * c1;
+    f.a[2][1] = n2 * c0 - n0 * c2;
+    f.a[2][2] = n0 * c1 - n1 * c0;
+    return f;
+}
+
+__device__ __forceinline__ int obb_lo(uint64_t w, int k) { return (int)(int8_t)(uint8_t)(w >> (14 + 16 * k)); }
+__device__ __forceinline__ int obb_hi(uint64_t w, int k) { return (int)(int8_t)(uint8_t)(w >> (22 + 16 * k)); }
+
+// Squared distance from the offset dq (query minus the centre of a level-l
+// cell) to the cell's oriented box w, less safety margins that cover the
+// rounding of the projections and of the frame, so that it never exceeds
+// the squared distance to any voxel of the cell.
+__device__ __forceinline__ float obb_dist2(uint64_t w, int l, float dq0, float dq1, float dq2) {
+    const Frame f = frame_decode((uint32_t)w & 0x3FFFu);
+    const float cell = (float)(1u << l), u = cell * (1.f / 128.f);
+    const float margin = (fabsf(dq0) + fabsf(dq1) + fabsf(dq2)) * (1.f / 262144.f) + cell * (1.f / 1024.f);
+    float d2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float t = f.a[k][0] * dq0 + f.a[k][1] * dq1 + f.a[k][2] * dq2;
+        const float lo = (float)obb_lo(w, k) * u, hi = (float)obb_hi(w, k) * u;
+        const float g = fmaxf(fmaxf(lo - t, t - hi), 0.f) - margin;
+        d2 += g > 0.f ? g * g : 0.f;
+    }
+    return d2 * (1.f - 1.f / 65536.f);
 }
 
 // Pass 4, one launch per level from the voxels up (a level's boxes are the
@@ -287,8 +399,9 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
                                                    uint32_t lev, const int64_t *__restrict__ lvl,
                                                    const uint32_t *__restrict__ first,
                                                    const uint8_t *__restrict__ oct,
-                                                   uint64_t *__restrict__ node, int64_t nodes_max,
-                                                   bool emit, uint8_t *__restrict__ occ,
+                                                   uint64_t *__restrict__ node, float *__restrict__ mom,
+                                                   int64_t nodes_max, bool emit,
+                                                   uint8_t *__restrict__ occ,
                                                    int64_t occ_cap, int64_t *__restrict__ counts,
                                                    uint32_t *err) {
     __shared__ int64_t s_n[kMaxDepth + 2], s_base[kMaxDepth + 2];
@@ -318,10 +431,15 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
         if (f1 > f0 + 8) f1 = f0 + 8;  // eight children at most (unique keys)
         uint32_t mask = 0;
         uint32_t lo[3] = {~0u, ~0u, ~0u}, hi[3] = {0u, 0u, 0u};
+        // moments of the voxel offsets from this cell's centre: count, sums,
+        // and the sums of products xx, yy, zz, xy, xz, yz
+        float mc = 0.f, ms[3] = {0.f, 0.f, 0.f}, mS[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        const float half = (float)(1u << L) * 0.5f;  // child centre = cell centre + off - 2^(L-2)
         for (int64_t c = f0; c < f1; ++c) {
             const uint32_t o = L == 1 ? (uint32_t)((uint64_t)keys[c] & 7) : oct[s_base[L - 1] + c];
             mask |= 1u << o;
-            const uint64_t cw = L == 1 ? 0ull : node[s_base[L - 1] + c];
+            const uint64_t cw = L == 1 ? 0ull : node[2 * (s_base[L - 1] + c)];
+            float dl[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 // the child's cell sits at offset bit(o, a) * 2^(L - 1) of this cell
@@ -330,16 +448,198 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
                 if (L > 1) node_box(cw, a, (int)L - 1, clo, chi);
                 lo[a] = min(lo[a], off + clo);
                 hi[a] = max(hi[a], off + chi);
+                dl[a] = (float)off - half * 0.5f;  // child centre minus this centre (voxel: -0.5 or 0.5)
+            }
+            if (L == 1) {
+                mc += 1.f;
+                ms[0] += dl[0];
+                ms[1] += dl[1];
+                ms[2] += dl[2];
+                mS[0] += dl[0] * dl[0];
+                mS[1] += dl[1] * dl[1];
+                mS[2] += dl[2] * dl[2];
+                mS[3] += dl[0] * dl[1];
+                mS[4] += dl[0] * dl[2];
+                mS[5] += dl[1] * dl[2];
+            } else {
+                const float *cm = mom + 10 * (s_base[L - 1] + c);
+                const float m = cm[0], s0 = cm[1], s1 = cm[2], s2 = cm[3];
+                mc += m;
+                ms[0] += s0 + m * dl[0];
+                ms[1] += s1 + m * dl[1];
+                ms[2] += s2 + m * dl[2];
+                mS[0] += cm[4] + 2.f * dl[0] * s0 + m * dl[0] * dl[0];
+                mS[1] += cm[5] + 2.f * dl[1] * s1 + m * dl[1] * dl[1];
+                mS[2] += cm[6] + 2.f * dl[2] * s2 + m * dl[2] * dl[2];
+                mS[3] += cm[7] + dl[0] * s1 + dl[1] * s0 + m * dl[0] * dl[1];
+                mS[4] += cm[8] + dl[0] * s2 + dl[2] * s0 + m * dl[0] * dl[2];
+                mS[5] += cm[9] + dl[1] * s2 + dl[2] * s1 + m * dl[1] * dl[2];
             }
         }
         uint64_t box = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             box |= (uint64_t)(((lo[a] >> ps) & 15u) | (((hi[a] >> ps) & 15u) << 4)) << (8 * a);
-        node[t] = (box << kNodeBoxShift) | ((uint64_t)f0 << 8) | mask;
+        float *pm = mom + 10 * t;
+        pm[0] = mc;
+        pm[1] = ms[0];
+        pm[2] = ms[1];
+        pm[3] = ms[2];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) pm[4 + e] = mS[e];
+        // least-variance direction: power iteration on tr(C) I - C, whose
+        // largest eigenvalue belongs to C's smallest
+        const float inv = 1.f / mc;
+        const float mu0 = ms[0] * inv, mu1 = ms[1] * inv, mu2 = ms[2] * inv;
+        const float cxx = mS[0] * inv - mu0 * mu0, cyy = mS[1] * inv - mu1 * mu1, czz = mS[2] * inv - mu2 * mu2;
+        const float cxy = mS[3] * inv - mu0 * mu1, cxz = mS[4] * inv - mu0 * mu2, cyz = mS[5] * inv - mu1 * mu2;
+        const float tr = cxx + cyy + czz;
+        float v0 = cxx <= cyy && cxx <= czz ? 1.f : 0.3f, v1 = cyy < cxx && cyy <= czz ? 1.f : 0.3f,
+              v2 = czz < cxx && czz < cyy ? 1.f : 0.3f;
+        for (int it = 0; it < 12; ++it) {
+            const float w0 = (tr - cxx) * v0 - cxy * v1 - cxz * v2;
+            const float w1 = -cxy * v0 + (tr - cyy) * v1 - cyz * v2;
+            const float w2 = -cxz * v0 - cyz * v1 + (tr - czz) * v2;
+            const float nn = w0 * w0 + w1 * w1 + w2 * w2;
+            if (!(nn > 1e-30f)) break;
+            const float r = rsqrtf(nn);
+            v0 = w0 * r;
+            v1 = w1 * r;
+            v2 = w2 * r;
+        }
+        const uint32_t code = oct_encode(v0, v1, v2);
+        const Frame f = frame_decode(code);
+        // ranges along the frame: up to level kScanLevels k_tree_ranges
+        // takes them from the voxels; above, from the corners of the
+        // children's oriented boxes
+        float tmin[3] = {3e38f, 3e38f, 3e38f}, tmax[3] = {-3e38f, -3e38f, -3e38f};
+        for (int64_t c = L <= (uint32_t)kScanLevels ? f1 : f0; c < f1; ++c) {
+            const uint32_t o = L == 1 ? (uint32_t)((uint64_t)keys[c] & 7) : oct[s_base[L - 1] + c];
+            float dl[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) dl[a] = (float)(((o >> (2 - a)) & 1u) << (L - 1)) - half * 0.5f;
+            if (L == 1) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const float tt = f.a[k][0] * dl[0] + f.a[k][1] * dl[1] + f.a[k][2] * dl[2];
+                    tmin[k] = fminf(tmin[k], tt);
+                    tmax[k] = fmaxf(tmax[k], tt);
+                }
+            } else {
+                const uint64_t cw2 = node[2 * (s_base[L - 1] + c) + 1];
+                const Frame fc = frame_decode((uint32_t)cw2 & 0x3FFFu);
+                const float uc = (float)(1u << (L - 1)) * (1.f / 128.f);
+                float r0[3], r1[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    r0[k] = (float)obb_lo(cw2, k) * uc;
+                    r1[k] = (float)obb_hi(cw2, k) * uc;
+                }
+#pragma unroll
+                for (int corner = 0; corner < 8; ++corner) {
+                    const float t0 = (corner & 1) ? r1[0] : r0[0], t1 = (corner & 2) ? r1[1] : r0[1],
+                                t2 = (corner & 4) ? r1[2] : r0[2];
+                    float pc[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) pc[a] = dl[a] + t0 * fc.a[0][a] + t1 * fc.a[1][a] + t2 * fc.a[2][a];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const float tt = f.a[k][0] * pc[0] + f.a[k][1] * pc[1] + f.a[k][2] * pc[2];
+                        tmin[k] = fminf(tmin[k], tt);
+                        tmax[k] = fmaxf(tmax[k], tt);
+                    }
+                }
+            }
+        }
+        uint64_t ob = code;
+        if (L > (uint32_t)kScanLevels) {
+            const float cell = (float)(1u << L), u = cell * (1.f / 128.f), slack = cell * (1.f / 1024.f);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                // never wider than the cell's own extent along the axis
+                const float sup = (fabsf(f.a[k][0]) + fabsf(f.a[k][1]) + fabsf(f.a[k][2])) * (cell - 1.f) * 0.5f;
+                const float a0 = fmaxf(tmin[k], -sup) - slack, a1 = fminf(tmax[k], sup) + slack;
+                const int q0 = max((int)floorf(a0 / u), -128), q1 = min((int)ceilf(a1 / u), 127);
+                ob |= (uint64_t)(uint8_t)(int8_t)q0 << (14 + 16 * k);
+                ob |= (uint64_t)(uint8_t)(int8_t)q1 << (22 + 16 * k);
+            }
+        }
+        node[2 * t] = (box << kNodeBoxShift) | ((uint64_t)f0 << 8) | mask;
+        node[2 * t + 1] = ob;
         if (emit && occ) {
             const int64_t o = total - s_base[L + 1] + j;  // codes of levels above L come first
             if (o < occ_cap) occ[o] = (uint8_t)mask;
+        }
+    }
+}
+
+// Pass 5 for levels up to kScanLevels, after pass 4 of the level: the
+// oriented box's ranges from the node's own voxels (its keys
+// [kfirst[t], kfirst[t + 1]) of the level, decoded), so that they are as
+// tight as the voxels allow.  A node is scanned by one thread below level
+// 4, by one wave from level 4 on.
+template <typename K, int LANES>
+__global__ __launch_bounds__(256) void k_tree_ranges(const K *__restrict__ keys, uint32_t depth,
+                                                     uint32_t lev, const int64_t *__restrict__ lvl,
+                                                     const uint32_t *__restrict__ kfirst,
+                                                     uint64_t *__restrict__ node, int64_t nodes_max) {
+    __shared__ int64_t s_n[kMaxDepth + 2], s_base[kMaxDepth + 2];
+    if (threadIdx.x == 0) {
+        s_n[0] = lvl[0];
+        int64_t b = 0;
+        for (uint32_t L = 1; L <= depth; ++L) {
+            s_n[L] = lvl[L];
+            s_base[L] = b;
+            b += lvl[L];
+        }
+        s_base[depth + 1] = b <= nodes_max ? b : 0;
+    }
+    __syncthreads();
+    if (s_base[depth + 1] == 0) return;  // block-uniform
+    const uint32_t L = lev;
+    const int sub = (int)(threadIdx.x % LANES);
+    const int64_t per_block = 256 / LANES;
+    const float cell = (float)(1u << L), u = cell * (1.f / 128.f), slack = cell * (1.f / 1024.f);
+    const float hc = (cell - 1.f) * 0.5f;
+    for (int64_t j = (int64_t)blockIdx.x * per_block + threadIdx.x / LANES; j < s_n[L];
+         j += (int64_t)gridDim.x * per_block) {
+        const int64_t t = s_base[L] + j;
+        const int64_t k0 = kfirst[t], k1 = j + 1 < s_n[L] ? (int64_t)kfirst[t + 1] : s_n[0];
+        const uint64_t w1 = node[2 * t + 1];
+        const Frame f = frame_decode((uint32_t)w1 & 0x3FFFu);
+        const Vox v0 = dec3((uint64_t)keys[k0], depth, false);
+        const float cx = (float)((v0.x >> L) << L) + hc, cy = (float)((v0.y >> L) << L) + hc,
+                    cz = (float)((v0.z >> L) << L) + hc;
+        float tmin[3] = {3e38f, 3e38f, 3e38f}, tmax[3] = {-3e38f, -3e38f, -3e38f};
+        for (int64_t i = k0 + sub; i < k1; i += LANES) {
+            const Vox v = dec3((uint64_t)keys[i], depth, false);
+            const float d0 = (float)v.x - cx, d1 = (float)v.y - cy, d2 = (float)v.z - cz;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float tt = f.a[k][0] * d0 + f.a[k][1] * d1 + f.a[k][2] * d2;
+                tmin[k] = fminf(tmin[k], tt);
+                tmax[k] = fmaxf(tmax[k], tt);
+            }
+        }
+        if (LANES > 1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int o = 1; o < LANES; o <<= 1) {
+                    tmin[k] = fminf(tmin[k], __shfl_xor(tmin[k], o, 64));
+                    tmax[k] = fmaxf(tmax[k], __shfl_xor(tmax[k], o, 64));
+                }
+        }
+        if (sub == 0) {
+            uint64_t ob = w1 & 0x3FFFull;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float a0 = tmin[k] - slack, a1 = tmax[k] + slack;
+                const int q0 = max((int)floorf(a0 / u), -128), q1 = min((int)ceilf(a1 / u), 127);
+                ob |= (uint64_t)(uint8_t)(int8_t)q0 << (14 + 16 * k);
+                ob |= (uint64_t)(uint8_t)(int8_t)q1 << (22 + 16 * k);
+            }
+            node[2 * t + 1] = ob;
         }
     }
 }
@@ -636,7 +936,7 @@ void k_knn_tree(
             L = (int)depth;
         }
         while (L > l) {
-            const uint64_t w = node[s_base[L] + nj];
+            const uint64_t w = node[2 * (s_base[L] + nj)];
             if (kCount) ++c_node;
             --L;
             const uint32_t oc = (((x >> L) & 1u) << 2) | (((y >> L) & 1u) << 1) | ((z >> L) & 1u);
@@ -699,7 +999,7 @@ void k_knn_tree(
                 if (d <= bound_now()) offer(d, (int32_t)cn);
             }
         } else {
-            s_sw[tid] = cn >= 0 ? node[s_base[ls] + cn] : 0ull;
+            s_sw[tid] = cn >= 0 ? node[2 * (s_base[ls] + cn)] : 0ull;
             if (kCount) c_node += cn >= 0 ? 1u : 0u;
             s_sc[tid] = (uint64_t)c[0] | ((uint64_t)c[1] << 21) | ((uint64_t)c[2] << 42);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -713,7 +1013,7 @@ void k_knn_tree(
             // depth-first walk of each subtree, nearest child first
             int l = l0;
             uint32_t x0 = 0, y0 = 0, z0 = 0;
-            uint64_t w = 0;
+            uint64_t w = 0, wo = 0;  // the open node's words: mask and first child; oriented box
             // Per open node: the query's octant one level down, the squared
             // gap to the low and the high child half on each axis (a child's
             // box distance is then three selects and two adds), whether its
@@ -729,7 +1029,7 @@ void k_knn_tree(
                 return b > (uint64_t)(Dist)~(Dist)0 ? (Dist)~(Dist)0 : (Dist)b;
             };
             uint32_t near = 0;  // children (by octant) within the bound at entry
-            auto enter = [&]() __attribute__((always_inline)) {
+            auto enter = [&](bool fresh) __attribute__((always_inline)) {
                 const int cl = l - 1;
                 qol = qo(cl);
                 // gaps to the low half [0, h) and the high half [h, 2h) of the
@@ -760,6 +1060,14 @@ void k_knn_tree(
                        (q1 + gzl <= bnd ? 0x04u : 0u) | (q1 + gzh <= bnd ? 0x08u : 0u) |
                        (q2 + gzl <= bnd ? 0x10u : 0u) | (q2 + gzh <= bnd ? 0x20u : 0u) |
                        (q3 + gzl <= bnd ? 0x40u : 0u) | (q3 + gzh <= bnd ? 0x80u : 0u);
+                // a node just loaded whose oriented box lies beyond the bound
+                // opens no child (rounded up, the bound only keeps more)
+                if (fresh && near) {
+                    const float hc = (float)((1u << l) - 1u) * 0.5f;
+                    const float lb2 = obb_dist2(wo, l, (float)qv.x - ((float)x0 + hc),
+                                                (float)qv.y - ((float)y0 + hc), (float)qv.z - ((float)z0 + hc));
+                    if (lb2 > (float)bnd * (1.f + 1.f / 1048576.f) + 1.f) near = 0;
+                }
             };
             uint32_t pm = 0;
             // One iteration: start this lane's next subtree, climb back to
@@ -786,7 +1094,9 @@ void k_knn_tree(
                         if (l0 == 0) {
                             offer(bd, ci);
                         } else {
-                            w = node[s_base[l0] + ci];
+                            const u64x2 pr = *(const u64x2 *)(node + 2 * (s_base[l0] + ci));
+                            w = pr.x;
+                            wo = pr.y;
                             if (kCount) ++c_node;
                             s_word[l0 * kKnnBlock + tid] = w;
                             x0 = cx;
@@ -818,7 +1128,9 @@ void k_knn_tree(
                             offer(bd, ci);
                             bnd = kth < (uint64_t)bnd ? to_dist(kth) : bnd;
                         } else {
-                            w = node[s_base[cl] + ci];
+                            const u64x2 pr = *(const u64x2 *)(node + 2 * (s_base[cl] + ci));
+                            w = pr.x;
+                            wo = pr.y;
                             if (kCount) ++c_node;
                             s_word[cl * kKnnBlock + tid] = w;
                             l = cl;
@@ -830,7 +1142,7 @@ void k_knn_tree(
                     }
                 }
                 if (moved) {
-                    enter();
+                    enter(!climbed);
                     const uint32_t done_slots = climbed ? (2u << near_order(done_oc ^ qol)) - 1u : 0u;
                     pm = slot_mask((uint32_t)w & near, qol) & ~done_slots;
                 }
@@ -982,6 +1294,8 @@ struct KnnLayout {
     uint32_t *first;
     uint8_t *oct;
     uint64_t *node;
+    float *mom;        // build-time moments of each node's voxels
+    uint32_t *kfirst;  // each node's first key
     uint32_t *dense;
     int dl;  // levels spanned by the dense table
     int64_t tiles, nodes;
@@ -1006,7 +1320,9 @@ static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth, int64_t nq_orde
     L.cnt = c.take<uint32_t>((size_t)L.tiles * depth);
     L.first = c.take<uint32_t>((size_t)L.nodes);
     L.oct = c.take<uint8_t>((size_t)L.nodes);
-    L.node = c.take<uint64_t>((size_t)L.nodes);
+    L.node = c.take<uint64_t>(2 * (size_t)L.nodes);  // two words per node
+    L.mom = c.take<float>(10 * (size_t)L.nodes);
+    L.kfirst = c.take<uint32_t>((size_t)L.nodes);
     L.dl = dense_levels(n);
     L.dense = c.take<uint32_t>((size_t)dense_cells(depth, L.dl) + 1);
     L.bytes = c.size();
@@ -1024,8 +1340,8 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
                                                       dense_cells(depth, L.dl), &L.ctl->err);
     k_tree_scan<<<depth, 1024, 0, s>>>(L.cnt, L.tiles, n, d_n, L.lvl);
     k_tree_build<K><<<(unsigned)L.tiles, 256, 0, s>>>(keys, n, d_n, depth, dt, L.tiles, L.cnt, L.lvl,
-                                                      L.first, L.oct, L.dense, dense_cells(depth, L.dl),
-                                                      L.nodes);
+                                                      L.first, L.kfirst, L.oct, L.dense,
+                                                      dense_cells(depth, L.dl), L.nodes);
     for (uint32_t lev = 1; lev <= depth; ++lev) {
         // level lev holds at most min(n, 8^(depth - lev)) nodes
         const uint32_t e = 3 * (depth - lev);
@@ -1033,8 +1349,19 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
         int64_t blocks = ((n < cap ? n : cap) + 255) / 256;
         blocks = blocks < 1 ? 1 : (blocks < 4096 ? blocks : 4096);
         k_tree_mask<K><<<(unsigned)blocks, 256, 0, s>>>(keys, depth, lev, L.lvl, L.first, L.oct,
-                                                        L.node, L.nodes, emit, occ, occ_cap, counts,
-                                                        &L.ctl->err);
+                                                        L.node, L.mom, L.nodes, emit, occ, occ_cap,
+                                                        counts, &L.ctl->err);
+        if ((int)lev <= kScanLevels) {
+            if (lev < 4) {
+                k_tree_ranges<K, 1><<<(unsigned)blocks, 256, 0, s>>>(keys, depth, lev, L.lvl,
+                                                                     L.kfirst, L.node, L.nodes);
+            } else {
+                int64_t wb = ((n < cap ? n : cap) + 3) / 4;  // four nodes per block
+                wb = wb < 1 ? 1 : (wb < 16384 ? wb : 16384);
+                k_tree_ranges<K, 64><<<(unsigned)wb, 256, 0, s>>>(keys, depth, lev, L.lvl, L.kfirst,
+                                                                  L.node, L.nodes);
+            }
+        }
     }
 }
 
