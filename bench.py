@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--sort-tune", default="", metavar="RB,ITEMS,RB2,ITEMS2",
                     help="use these sort settings for the builds (RB, ITEMS) and projections "
                          "(RB2, ITEMS2) instead of running the autotuner (profiling runs)")
-    ap.add_argument("--only", default="", choices=["", "build_merge", "step", "knn"],
+    ap.add_argument("--only", default="", choices=["", "build_merge", "step", "knn", "c4"],
                     help="time only this part (for external profilers)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES between two device buffers 5 times (a plain copy "
@@ -856,6 +856,27 @@ def c4_batched(cga, device, reps):
         b.record()
     torch.cuda.synchronize()
     ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    # per-kernel times of the same work launched eagerly (HIP events around
+    # each launch; the graph itself cannot carry them)
+    labels = ["batch_encode", "hist_scan", "onesweep", "rle", "batch_offsets", "batch_pairs",
+              "batch_merge"]
+    cga.cga_prof_reset()
+    cga.cga_prof_enable(labels)
+    for _ in range(2):
+        cga.cga_batch_build_merge(xyz, off, g, tune=(rb, items))
+    torch.cuda.synchronize()
+    cga.cga_prof_disable()
+    kern = {}
+    for lb in labels:
+        kms, kn = cga.cga_prof_read(lb)
+        if kn:
+            kern[lb] = {"ms_per_run": round(kms / 2, 4), "launches_per_run": kn // 2}
+    if "onesweep" in kern and kern["onesweep"]["launches_per_run"]:
+        us = kern["onesweep"]["ms_per_run"] * 1e3 / kern["onesweep"]["launches_per_run"]
+        kern["onesweep"]["avg_launch_us"] = round(us, 1)
+        kern["onesweep"]["gbs_per_pass"] = round(16 * n / (us * 1e-6) / 1e9, 1)
+        kern["onesweep"]["algorithmic_bytes_per_pass"] = 16 * n
+        kern["onesweep"]["traffic"] = load_traffic("onesweep", "c4")
     key_off = graph.out.key_off.cpu().numpy()
     uf = np.diff(key_off)
     u = int(key_off[-1])
@@ -870,7 +891,7 @@ def c4_batched(cga, device, reps):
     return {"frames": F, "points": n, "unique_total": u, "merged_total": merged,
             "gen_s": round(gen_s, 1), "autotune": {"radix_bits": rb, "tile_items": items,
                                                    "sort_passes": P, "sort_ms": round(tune_ms, 3)},
-            "graph_ms": round(ms, 3), "points_per_s": n / (ms * 1e-3),
+            "graph_ms": round(ms, 3), "points_per_s": n / (ms * 1e-3), "kernels_eager": kern,
             "roofline": {"bound": "hbm", "kernel": "whole graph", "achieved": round(gbs, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                          "algorithmic_bytes": total, "build_bytes": build_bytes,
@@ -891,6 +912,11 @@ def main():
 
     import paper_2110_11616_amd as cga
     device = torch.device("cuda:0")
+    if args.only == "c4":
+        # the 256-frame batched graph alone, replayed `steps` times
+        c4 = c4_batched(cga, device, args.steps)
+        progress(f"c4 only: graph {c4['graph_ms']} ms, onesweep {c4['kernels_eager'].get('onesweep')}")
+        return
     wl_label, drops = WORKLOADS[args.workload]
     progress(f"generating workload {args.workload}")
     d = make_workload(args.workload)
