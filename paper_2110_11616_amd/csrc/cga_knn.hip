@@ -101,12 +101,27 @@ __device__ __forceinline__ int64_t key_count(int64_t n_host, const int64_t *d_n)
     return n < n_host ? n : n_host;
 }
 
-// Total node count of all levels, or -1 when it exceeds the arrays (a key
-// array that is not a CGA of the grid can have more cells than the bound).
-__device__ __forceinline__ int64_t tree_total(const int64_t *lvl, uint32_t depth, int64_t nodes_max) {
-    int64_t t = 0;
-    for (uint32_t L = 1; L <= depth; ++L) t += lvl[L];
-    return t <= nodes_max ? t : -1;
+// The level table: lvl[L] = nodes at level L (lvl[0] = keys), lvl[kLvlBase +
+// L] = first node of level L in the concatenated arrays (L = 1 .. depth + 1,
+// the last being the total), and lvl[kLvlTotal] = the total, or -1 when it
+// exceeds the arrays (a key array that is not a CGA of the grid can have
+// more cells than the bound).
+constexpr int kLvlBase = kMaxDepth + 2;
+constexpr int kLvlTotal = 2 * kMaxDepth + 4;
+constexpr int kLvlWords = 2 * kMaxDepth + 6;
+
+__device__ __forceinline__ int64_t tree_total(const int64_t *lvl) { return lvl[kLvlTotal]; }
+
+// The node bases and the total, from the level sizes (one thread).
+__global__ void k_tree_bases(int64_t *__restrict__ lvl, uint32_t depth, int64_t nodes_max) {
+    if (threadIdx.x != 0) return;
+    int64_t b = 0;
+    for (uint32_t L = 1; L <= depth; ++L) {
+        lvl[kLvlBase + L] = b;
+        b += lvl[L];
+    }
+    lvl[kLvlBase + depth + 1] = b;
+    lvl[kLvlTotal] = b <= nodes_max ? b : -1;
 }
 
 __device__ __forceinline__ uint32_t mbcnt64(uint64_t m) {
@@ -203,16 +218,10 @@ __global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, 
     __shared__ int64_t s_base[kMaxDepth + 2];
     __shared__ uint32_t s_off[kMaxDepth + 1];
     __shared__ int s_max[4];
-    if (tree_total(lvl, depth, nodes_max) < 0) return;  // block-uniform
+    if (tree_total(lvl) < 0) return;  // block-uniform
     const int64_t n = key_count(n_host, d_n);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0) {
-        int64_t b = 0;
-        for (uint32_t L = 1; L <= depth + 1; ++L) {
-            s_base[L] = b;
-            if (L <= depth) b += lvl[L];
-        }
-    }
+    if (threadIdx.x >= 1 && threadIdx.x <= depth + 1) s_base[threadIdx.x] = lvl[kLvlBase + threadIdx.x];
     if (threadIdx.x >= 1 && threadIdx.x <= depth)
         s_off[threadIdx.x] = cnt[(int64_t)(threadIdx.x - 1) * tiles + blockIdx.x];
     int h[kTreeRows];
@@ -272,7 +281,7 @@ __global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, 
 // surface a cell's voxels fill a thin slab of it, so distances to the box
 // bound the distances to the voxels far more tightly than the cell's do.
 constexpr uint64_t kNodeFirstMask = 0x7FFFFFFFull;
-constexpr int kScanLevels = 9;  // levels whose oriented boxes are fitted to the voxels
+constexpr int kScanLevels = 6;  // levels whose oriented boxes are fitted to the voxels
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 constexpr int kNodeBoxShift = 40;
 __host__ __device__ __forceinline__ int64_t node_first(uint64_t w) {
@@ -405,18 +414,12 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
                                                    int64_t occ_cap, int64_t *__restrict__ counts,
                                                    uint32_t *err) {
     __shared__ int64_t s_n[kMaxDepth + 2], s_base[kMaxDepth + 2];
-    if (threadIdx.x == 0) {
-        s_n[0] = lvl[0];
-        int64_t b = 0;
-        for (uint32_t L = 1; L <= depth; ++L) {
-            s_n[L] = lvl[L];
-            s_base[L] = b;
-            b += lvl[L];
-        }
-        s_base[depth + 1] = b <= nodes_max ? b : 0;  // nothing to do for an oversized tree
+    if (threadIdx.x <= depth + 1) {
+        s_n[threadIdx.x] = lvl[threadIdx.x];
+        s_base[threadIdx.x] = lvl[kLvlBase + threadIdx.x];
     }
     __syncthreads();
-    const int64_t total = s_base[depth + 1];
+    const int64_t total = tree_total(lvl) > 0 ? tree_total(lvl) : 0;  // 0: nothing to do
     if (emit && lev == 1 && blockIdx.x == 0) {
         if (counts && threadIdx.x <= depth) counts[threadIdx.x] = s_n[threadIdx.x];
         if (threadIdx.x == 0 && occ && total > occ_cap) set_err(err, ERR_CAPACITY);
@@ -509,11 +512,12 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
         }
         const uint32_t code = oct_encode(v0, v1, v2);
         const Frame f = frame_decode(code);
-        // ranges along the frame: up to level kScanLevels k_tree_ranges
-        // takes them from the voxels; above, from the corners of the
-        // children's oriented boxes
+        // ranges along the frame: at level 1 from the voxels (the
+        // children), at levels 2 .. kScanLevels from the voxels by
+        // k_tree_ranges, above from the corners of the children's boxes
+        const bool own = L == 1 || L > (uint32_t)kScanLevels;
         float tmin[3] = {3e38f, 3e38f, 3e38f}, tmax[3] = {-3e38f, -3e38f, -3e38f};
-        for (int64_t c = L <= (uint32_t)kScanLevels ? f1 : f0; c < f1; ++c) {
+        for (int64_t c = own ? f0 : f1; c < f1; ++c) {
             const uint32_t o = L == 1 ? (uint32_t)((uint64_t)keys[c] & 7) : oct[s_base[L - 1] + c];
             float dl[3];
 #pragma unroll
@@ -552,7 +556,7 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
             }
         }
         uint64_t ob = code;
-        if (L > (uint32_t)kScanLevels) {
+        if (own) {
             const float cell = (float)(1u << L), u = cell * (1.f / 128.f), slack = cell * (1.f / 1024.f);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -573,46 +577,33 @@ __global__ __launch_bounds__(256) void k_tree_mask(const K *__restrict__ keys, u
     }
 }
 
-// Pass 5 for levels up to kScanLevels, after pass 4 of the level: the
+// Pass 5 for levels 2 .. kScanLevels, after pass 4 of the level: the
 // oriented box's ranges from the node's own voxels (its keys
 // [kfirst[t], kfirst[t + 1]) of the level, decoded), so that they are as
-// tight as the voxels allow.  A node is scanned by one thread below level
-// 4, by one wave from level 4 on.
-template <typename K, int LANES>
-__global__ __launch_bounds__(256) void k_tree_ranges(const K *__restrict__ keys, uint32_t depth,
-                                                     uint32_t lev, const int64_t *__restrict__ lvl,
-                                                     const uint32_t *__restrict__ kfirst,
-                                                     uint64_t *__restrict__ node, int64_t nodes_max) {
-    __shared__ int64_t s_n[kMaxDepth + 2], s_base[kMaxDepth + 2];
-    if (threadIdx.x == 0) {
-        s_n[0] = lvl[0];
-        int64_t b = 0;
-        for (uint32_t L = 1; L <= depth; ++L) {
-            s_n[L] = lvl[L];
-            s_base[L] = b;
-            b += lvl[L];
+// tight as the voxels allow.  Above kScanLevels the children hold enough
+// voxels for well-defined normals, and their box corners bound the parent's
+// ranges closely enough.
+//
+// Voxel offsets of keys [k0, k1) from the cell centre (cx, cy, cz),
+// projected on the frame's axes: their least and greatest, over the keys
+// i = k0 + sub, k0 + sub + step, ... (four loads in flight per round: a big
+// node's scan is bound by load latency, not by the projections).
+template <typename K>
+__device__ __forceinline__ void frame_extent(const K *__restrict__ keys, int64_t k0, int64_t k1,
+                                             int sub, int step, uint32_t depth, const Frame &f,
+                                             float cx, float cy, float cz, float tmin[3],
+                                             float tmax[3]) {
+    constexpr int kIn = 4;
+    for (int64_t i0 = k0 + sub; i0 < k1; i0 += (int64_t)step * kIn) {
+        K kk[kIn];
+#pragma unroll
+        for (int m = 0; m < kIn; ++m) {
+            const int64_t i = i0 + (int64_t)m * step;
+            kk[m] = keys[i < k1 ? i : k0];  // repeating the first key changes no range
         }
-        s_base[depth + 1] = b <= nodes_max ? b : 0;
-    }
-    __syncthreads();
-    if (s_base[depth + 1] == 0) return;  // block-uniform
-    const uint32_t L = lev;
-    const int sub = (int)(threadIdx.x % LANES);
-    const int64_t per_block = 256 / LANES;
-    const float cell = (float)(1u << L), u = cell * (1.f / 128.f), slack = cell * (1.f / 1024.f);
-    const float hc = (cell - 1.f) * 0.5f;
-    for (int64_t j = (int64_t)blockIdx.x * per_block + threadIdx.x / LANES; j < s_n[L];
-         j += (int64_t)gridDim.x * per_block) {
-        const int64_t t = s_base[L] + j;
-        const int64_t k0 = kfirst[t], k1 = j + 1 < s_n[L] ? (int64_t)kfirst[t + 1] : s_n[0];
-        const uint64_t w1 = node[2 * t + 1];
-        const Frame f = frame_decode((uint32_t)w1 & 0x3FFFu);
-        const Vox v0 = dec3((uint64_t)keys[k0], depth, false);
-        const float cx = (float)((v0.x >> L) << L) + hc, cy = (float)((v0.y >> L) << L) + hc,
-                    cz = (float)((v0.z >> L) << L) + hc;
-        float tmin[3] = {3e38f, 3e38f, 3e38f}, tmax[3] = {-3e38f, -3e38f, -3e38f};
-        for (int64_t i = k0 + sub; i < k1; i += LANES) {
-            const Vox v = dec3((uint64_t)keys[i], depth, false);
+#pragma unroll
+        for (int m = 0; m < kIn; ++m) {
+            const Vox v = dec3((uint64_t)kk[m], depth, false);
             const float d0 = (float)v.x - cx, d1 = (float)v.y - cy, d2 = (float)v.z - cz;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -621,11 +612,51 @@ __global__ __launch_bounds__(256) void k_tree_ranges(const K *__restrict__ keys,
                 tmax[k] = fmaxf(tmax[k], tt);
             }
         }
-        if (LANES > 1) {
+    }
+}
+
+// Two launches per level: BIG = false, a thread per node of at most
+// kSmallNode keys; BIG = true, a wave per larger node (its lanes stride
+// over the keys).  Sparse levels (a few voxels per cell) and dense ones (a
+// LiDAR ground plane) both keep their lanes busy; each launch skips the
+// other's nodes after reading their key range.
+constexpr int64_t kSmallNode = 16;
+
+template <typename K, bool BIG>
+__global__ __launch_bounds__(256) void k_tree_ranges(const K *__restrict__ keys, uint32_t depth,
+                                                     uint32_t lev, const int64_t *__restrict__ lvl,
+                                                     const uint32_t *__restrict__ kfirst,
+                                                     uint64_t *__restrict__ node) {
+    constexpr int LANES = BIG ? 64 : 1;
+    __shared__ int64_t s_n[kMaxDepth + 2], s_base[kMaxDepth + 2];
+    if (threadIdx.x <= depth + 1) {
+        s_n[threadIdx.x] = lvl[threadIdx.x];
+        s_base[threadIdx.x] = lvl[kLvlBase + threadIdx.x];
+    }
+    __syncthreads();
+    if (tree_total(lvl) <= 0) return;  // block-uniform: no keys, or an oversized tree
+    const uint32_t L = lev;
+    const int sub = (int)(threadIdx.x % LANES);
+    const int64_t per_block = 256 / LANES;
+    const float cell = (float)(1u << L), u = cell * (1.f / 128.f), slack = cell * (1.f / 1024.f);
+    const float hc = (cell - 1.f) * 0.5f;
+    const int64_t nl = s_n[L];
+    for (int64_t j = (int64_t)blockIdx.x * per_block + threadIdx.x / LANES; j < nl;
+         j += (int64_t)gridDim.x * per_block) {
+        const int64_t t = s_base[L] + j;
+        const int64_t k0 = kfirst[t], k1 = j + 1 < nl ? (int64_t)kfirst[t + 1] : s_n[0];
+        if ((k1 - k0 > kSmallNode) != BIG) continue;  // uniform over the node's lanes
+        const uint64_t w1 = node[2 * t + 1];
+        const Frame f = frame_decode((uint32_t)w1 & 0x3FFFu);
+        const Vox v0 = dec3((uint64_t)keys[k0], depth, false);
+        float tmin[3] = {3e38f, 3e38f, 3e38f}, tmax[3] = {-3e38f, -3e38f, -3e38f};
+        frame_extent(keys, k0, k1, sub, LANES, depth, f, (float)((v0.x >> L) << L) + hc,
+                     (float)((v0.y >> L) << L) + hc, (float)((v0.z >> L) << L) + hc, tmin, tmax);
+        if (BIG) {
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int o = 1; o < LANES; o <<= 1) {
+                for (int o = 1; o < 64; o <<= 1) {
                     tmin[k] = fminf(tmin[k], __shfl_xor(tmin[k], o, 64));
                     tmax[k] = fmaxf(tmax[k], __shfl_xor(tmax[k], o, 64));
                 }
@@ -859,20 +890,14 @@ void k_knn_tree(
     __shared__ uint64_t s_sw[kKnnBlock], s_sc[kKnnBlock];  // start cells of the round: word, corner
     __shared__ int64_t s_base[kMaxDepth + 1];
     const int tid = threadIdx.x, team = tid / kTeam, tl = tid % kTeam;
-    if (tid == 0) {
-        int64_t b = 0;
-        for (uint32_t L = 1; L <= depth; ++L) {
-            s_base[L] = b;
-            b += lvl[L];
-        }
-    }
+    if (tid >= 1 && tid <= depth) s_base[tid] = lvl[kLvlBase + tid];
     if (tl == 0) s_bound[team] = LIST::kNone;
     __syncthreads();  // the only block-wide barrier; teams run independently after it
     const int64_t slot = (int64_t)blockIdx.x * kTeamsPerBlock + team;
     if (slot >= nq) return;
     const int64_t j = order ? (int64_t)(order[slot] >> kOrderBits) : slot;  // query (and output row)
     // an oversized tree (keys that are not a CGA of the grid) searches nothing
-    const int64_t n = tree_total(lvl, depth, nodes_max) < 0 ? 0 : lvl[0];
+    const int64_t n = tree_total(lvl) < 0 ? 0 : lvl[0];
     const int dt = dense_level(depth, dl);
 
     const float o[3] = {o0, o1, o2};
@@ -1316,7 +1341,7 @@ static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth, int64_t nq_orde
         L.oa = c.take<uint64_t>((size_t)nq_order);
         L.ob = c.take<uint64_t>((size_t)nq_order);
     }
-    L.lvl = c.take<int64_t>(kMaxDepth + 2);
+    L.lvl = c.take<int64_t>(kLvlWords);
     L.cnt = c.take<uint32_t>((size_t)L.tiles * depth);
     L.first = c.take<uint32_t>((size_t)L.nodes);
     L.oct = c.take<uint8_t>((size_t)L.nodes);
@@ -1339,6 +1364,7 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
     k_tree_count<K><<<(unsigned)L.tiles, 256, 0, s>>>(keys, n, d_n, depth, L.tiles, L.cnt, L.dense,
                                                       dense_cells(depth, L.dl), &L.ctl->err);
     k_tree_scan<<<depth, 1024, 0, s>>>(L.cnt, L.tiles, n, d_n, L.lvl);
+    k_tree_bases<<<1, 64, 0, s>>>(L.lvl, depth, L.nodes);
     k_tree_build<K><<<(unsigned)L.tiles, 256, 0, s>>>(keys, n, d_n, depth, dt, L.tiles, L.cnt, L.lvl,
                                                       L.first, L.kfirst, L.oct, L.dense,
                                                       dense_cells(depth, L.dl), L.nodes);
@@ -1346,21 +1372,22 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
         // level lev holds at most min(n, 8^(depth - lev)) nodes
         const uint32_t e = 3 * (depth - lev);
         const int64_t cap = e >= 62 ? INT64_MAX : (int64_t)1 << e;
+        // latency-bound passes (a thread per node walks its children):
+        // many blocks in flight; their set-up is two parallel loads
         int64_t blocks = ((n < cap ? n : cap) + 255) / 256;
         blocks = blocks < 1 ? 1 : (blocks < 4096 ? blocks : 4096);
         k_tree_mask<K><<<(unsigned)blocks, 256, 0, s>>>(keys, depth, lev, L.lvl, L.first, L.oct,
                                                         L.node, L.mom, L.nodes, emit, occ, occ_cap,
                                                         counts, &L.ctl->err);
-        if ((int)lev <= kScanLevels) {
-            if (lev < 4) {
-                k_tree_ranges<K, 1><<<(unsigned)blocks, 256, 0, s>>>(keys, depth, lev, L.lvl,
-                                                                     L.kfirst, L.node, L.nodes);
-            } else {
-                int64_t wb = ((n < cap ? n : cap) + 3) / 4;  // four nodes per block
-                wb = wb < 1 ? 1 : (wb < 16384 ? wb : 16384);
-                k_tree_ranges<K, 64><<<(unsigned)wb, 256, 0, s>>>(keys, depth, lev, L.lvl, L.kfirst,
-                                                                  L.node, L.nodes);
-            }
+        if (lev >= 2 && (int)lev <= kScanLevels) {
+            const int64_t m = n < cap ? n : cap;
+            int64_t tb = (m + 255) / 256, wb = (m + 3) / 4;
+            tb = tb < 1 ? 1 : (tb < 4096 ? tb : 4096);
+            wb = wb < 1 ? 1 : (wb < 8192 ? wb : 8192);
+            k_tree_ranges<K, false><<<(unsigned)tb, 256, 0, s>>>(keys, depth, lev, L.lvl, L.kfirst,
+                                                                 L.node);
+            k_tree_ranges<K, true><<<(unsigned)wb, 256, 0, s>>>(keys, depth, lev, L.lvl, L.kfirst,
+                                                                L.node);
         }
     }
 }
