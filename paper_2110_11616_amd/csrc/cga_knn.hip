@@ -1086,8 +1086,12 @@ void k_knn_tree(
                        (q2 + gzl <= bnd ? 0x10u : 0u) | (q2 + gzh <= bnd ? 0x20u : 0u) |
                        (q3 + gzl <= bnd ? 0x40u : 0u) | (q3 + gzh <= bnd ? 0x80u : 0u);
                 // a node just loaded whose oriented box lies beyond the bound
-                // opens no child (rounded up, the bound only keeps more)
-                if (fresh && near) {
+                // opens no child (rounded up, the bound only keeps more);
+                // tested from the second round on, when the query's own
+                // cell did not hold its neighbours (a query near the voxels,
+                // whose first round mostly settles it, would pay for the
+                // test and rarely gain)
+                if (fresh && near && !round0) {
                     const float hc = (float)((1u << l) - 1u) * 0.5f;
                     const float lb2 = obb_dist2(wo, l, (float)qv.x - ((float)x0 + hc),
                                                 (float)qv.y - ((float)y0 + hc), (float)qv.z - ((float)z0 + hc));
