@@ -282,6 +282,7 @@ __global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, 
 // bound the distances to the voxels far more tightly than the cell's do.
 constexpr uint64_t kNodeFirstMask = 0x7FFFFFFFull;
 constexpr int kScanLevels = 6;  // levels whose oriented boxes are fitted to the voxels
+constexpr int kTreeBigCtr = 24;  // control-block counters of the big-node lists, one per level
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 constexpr int kNodeBoxShift = 40;
 __host__ __device__ __forceinline__ int64_t node_first(uint64_t w) {
@@ -615,18 +616,19 @@ __device__ __forceinline__ void frame_extent(const K *__restrict__ keys, int64_t
     }
 }
 
-// Two launches per level: BIG = false, a thread per node of at most
-// kSmallNode keys; BIG = true, a wave per larger node (its lanes stride
-// over the keys).  Sparse levels (a few voxels per cell) and dense ones (a
-// LiDAR ground plane) both keep their lanes busy; each launch skips the
-// other's nodes after reading their key range.
+// Two launches per level: BIG = false, a thread per node, which fits the
+// nodes of at most kSmallNode keys and lists the others (big, *n_big); BIG
+// = true, a wave per listed node (its lanes stride over the keys).  Sparse
+// levels (a few voxels per cell) and dense ones (a LiDAR ground plane) both
+// keep their lanes busy.
 constexpr int64_t kSmallNode = 16;
 
 template <typename K, bool BIG>
 __global__ __launch_bounds__(256) void k_tree_ranges(const K *__restrict__ keys, uint32_t depth,
                                                      uint32_t lev, const int64_t *__restrict__ lvl,
                                                      const uint32_t *__restrict__ kfirst,
-                                                     uint64_t *__restrict__ node) {
+                                                     uint64_t *__restrict__ node,
+                                                     uint32_t *__restrict__ big, uint32_t *n_big) {
     constexpr int LANES = BIG ? 64 : 1;
     __shared__ int64_t s_n[kMaxDepth + 2], s_base[kMaxDepth + 2];
     if (threadIdx.x <= depth + 1) {
@@ -640,12 +642,16 @@ __global__ __launch_bounds__(256) void k_tree_ranges(const K *__restrict__ keys,
     const int64_t per_block = 256 / LANES;
     const float cell = (float)(1u << L), u = cell * (1.f / 128.f), slack = cell * (1.f / 1024.f);
     const float hc = (cell - 1.f) * 0.5f;
-    const int64_t nl = s_n[L];
-    for (int64_t j = (int64_t)blockIdx.x * per_block + threadIdx.x / LANES; j < nl;
-         j += (int64_t)gridDim.x * per_block) {
+    const int64_t nl = BIG ? (int64_t)ld_agent(n_big) : s_n[L];
+    for (int64_t q = (int64_t)blockIdx.x * per_block + threadIdx.x / LANES; q < nl;
+         q += (int64_t)gridDim.x * per_block) {
+        const int64_t j = BIG ? (int64_t)big[q] : q;
         const int64_t t = s_base[L] + j;
-        const int64_t k0 = kfirst[t], k1 = j + 1 < nl ? (int64_t)kfirst[t + 1] : s_n[0];
-        if ((k1 - k0 > kSmallNode) != BIG) continue;  // uniform over the node's lanes
+        const int64_t k0 = kfirst[t], k1 = j + 1 < s_n[L] ? (int64_t)kfirst[t + 1] : s_n[0];
+        if (!BIG && k1 - k0 > kSmallNode) {
+            big[atomicAdd(n_big, 1u)] = (uint32_t)j;
+            continue;
+        }
         const uint64_t w1 = node[2 * t + 1];
         const Frame f = frame_decode((uint32_t)w1 & 0x3FFFu);
         const Vox v0 = dec3((uint64_t)keys[k0], depth, false);
@@ -1325,6 +1331,7 @@ struct KnnLayout {
     uint64_t *node;
     float *mom;        // build-time moments of each node's voxels
     uint32_t *kfirst;  // each node's first key
+    uint32_t *big;     // nodes of more than kSmallNode keys, one level at a time
     uint32_t *dense;
     int dl;  // levels spanned by the dense table
     int64_t tiles, nodes;
@@ -1352,6 +1359,7 @@ static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth, int64_t nq_orde
     L.node = c.take<uint64_t>(2 * (size_t)L.nodes);  // two words per node
     L.mom = c.take<float>(10 * (size_t)L.nodes);
     L.kfirst = c.take<uint32_t>((size_t)L.nodes);
+    L.big = c.take<uint32_t>((size_t)(n / kSmallNode + 1));
     L.dl = dense_levels(n);
     L.dense = c.take<uint32_t>((size_t)dense_cells(depth, L.dl) + 1);
     L.bytes = c.size();
@@ -1385,13 +1393,14 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
                                                         counts, &L.ctl->err);
         if (lev >= 2 && (int)lev <= kScanLevels) {
             const int64_t m = n < cap ? n : cap;
-            int64_t tb = (m + 255) / 256, wb = (m + 3) / 4;
+            int64_t tb = (m + 255) / 256, wb = (m / kSmallNode + 3) / 4;  // at most m / 16 big nodes
             tb = tb < 1 ? 1 : (tb < 4096 ? tb : 4096);
-            wb = wb < 1 ? 1 : (wb < 8192 ? wb : 8192);
+            wb = wb < 1 ? 1 : (wb < 2048 ? wb : 2048);
+            uint32_t *n_big = &L.ctl->tile_ctr[kTreeBigCtr + lev];
             k_tree_ranges<K, false><<<(unsigned)tb, 256, 0, s>>>(keys, depth, lev, L.lvl, L.kfirst,
-                                                                 L.node);
+                                                                 L.node, L.big, n_big);
             k_tree_ranges<K, true><<<(unsigned)wb, 256, 0, s>>>(keys, depth, lev, L.lvl, L.kfirst,
-                                                                L.node);
+                                                                L.node, L.big, n_big);
         }
     }
 }
