@@ -11,7 +11,7 @@
 namespace cga {
 
 constexpr int kMergeBlock = 256;
-constexpr int kMergeItems = 8;
+constexpr int kMergeItems = 16;
 constexpr int kMergeTile = kMergeBlock * kMergeItems;
 
 constexpr uint64_t kMAgg = 1ull << 62;
