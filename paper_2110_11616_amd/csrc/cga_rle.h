@@ -13,7 +13,7 @@
 namespace cga {
 
 constexpr int kRleBlock = 256;
-constexpr int kRleItems = 16;
+constexpr int kRleItems = 24;
 constexpr int kRleTile = kRleBlock * kRleItems;
 
 inline int64_t rle_tiles(int64_t n) { return n <= 0 ? 1 : (n + kRleTile - 1) / kRleTile; }
