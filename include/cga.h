@@ -253,8 +253,11 @@ int cga_project(const cga_grid *grid, const void *d_keys, int64_t n, const int64
  * CGA smallest in (squared voxel distance, key).  Outputs row-major nq x k:
  * d_idx (int64 position in the key array, -1 padding when fewer than k
  * voxels exist) and d_d2 (uint64 squared distance, UINT64_MAX padding).
- * k in [1, 32]; n (the host bound) below 2^31 (else CGA_EINVAL).  MORTON
- * grids only (LINEAR: CGA_EUNSUPPORTED).  From 2^18 queries on, the queries
+ * k in [1, 32]; n (the host bound) below 2^31 (else CGA_EINVAL).  On a
+ * LINEAR grid the keys are re-keyed to Morton order inside the call (a
+ * key-value sort carrying each key's position; the workspace grows by about
+ * 3 * (S + 4) bytes per key): d_idx then holds LINEAR positions, and ties
+ * go to the smaller LINEAR position.  From 2^18 queries on, the queries
  * are searched in the order of their Morton keys (results are unchanged;
  * the workspace then grows by about 24 bytes per query, so size it with the
  * same nq as the call).

@@ -283,6 +283,7 @@ __global__ __launch_bounds__(256) void k_tree_build(const K *__restrict__ keys, 
 constexpr uint64_t kNodeFirstMask = 0x7FFFFFFFull;
 constexpr int kScanLevels = 6;  // levels whose oriented boxes are fitted to the voxels
 constexpr int kTreeBigCtr = 24;  // control-block counters of the big-node lists, one per level
+constexpr int kLinearSortCtr = 8;  // tile counters of the LINEAR keys' re-key sort (up to 8 passes)
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 constexpr int kNodeBoxShift = 40;
 __host__ __device__ __forceinline__ int64_t node_first(uint64_t w) {
@@ -888,7 +889,7 @@ void k_knn_tree(
     const int64_t *__restrict__ lvl, int64_t nodes_max, const float *__restrict__ q, int64_t nq,
     const uint64_t *__restrict__ order, float o0, float o1, float o2, float scale, uint32_t depth,
     int dl, int k, int la, int64_t *__restrict__ idx_out, uint64_t *__restrict__ d2_out,
-    uint32_t *err, unsigned long long *work = nullptr) {
+    uint32_t *err, const uint32_t *__restrict__ perm = nullptr, unsigned long long *work = nullptr) {
     uint32_t c_node = 0, c_dense = 0, c_vox = 0, c_step = 0;  // kCount only
     using Dist = typename LIST::Dist;
     extern __shared__ uint64_t s_word[];  // open node word per level, one column per thread
@@ -932,9 +933,11 @@ void k_knn_tree(
                    gz = axis_gap(qv.z, z, z + e);
         return gx * gx + gy * gy + gz * gz;
     };
+    // a voxel's position: in the key array, or through perm in the caller's
+    // LINEAR array (then ties go to the smaller LINEAR position, as there)
     auto offer = [&](Dist d, int32_t i) __attribute__((always_inline)) {
         if (kCount) ++c_vox;
-        list.offer(d, i);
+        list.offer(d, perm ? (int32_t)perm[i] : i);
         kth = list.kth(k);
         if (kth < s_bound[team]) atomicMin(&s_bound[team], (unsigned long long)kth);
     };
@@ -1267,6 +1270,20 @@ void k_knn_tree(
     }
 }
 
+// LINEAR keys -> the Morton keys of the same voxels, with each key's position.
+template <typename K>
+__global__ __launch_bounds__(256) void k_linear_to_morton(const K *__restrict__ keys, int64_t n_host,
+                                                          const int64_t *d_n, uint32_t depth,
+                                                          K *__restrict__ mk, uint32_t *__restrict__ pos) {
+    const int64_t n = key_count(n_host, d_n);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Vox v = dec3((uint64_t)keys[i], depth, true);
+        mk[i] = (K)enc3(v.x, v.y, v.z, depth, false);
+        pos[i] = (uint32_t)i;
+    }
+}
+
 // Ordering code of every query: its index above the top kOrderBits of its
 // Morton key, with the digit histogram of the three 8-bit passes.
 __global__ __launch_bounds__(256) void k_knn_order(const float *__restrict__ q, int64_t nq, float o0,
@@ -1332,18 +1349,34 @@ struct KnnLayout {
     float *mom;        // build-time moments of each node's voxels
     uint32_t *kfirst;  // each node's first key
     uint32_t *big;     // nodes of more than kSmallNode keys, one level at a time
+    // LINEAR keys only: their Morton re-keys (in, alternate, sorted) with
+    // the key positions riding along, and the sort's workspace
+    SortWs msort;
+    void *mk[3] = {nullptr, nullptr, nullptr};
+    uint32_t *pos[3] = {nullptr, nullptr, nullptr};
+    const uint32_t *perm = nullptr;  // set per call: the sorted keys' LINEAR positions
     uint32_t *dense;
     int dl;  // levels spanned by the dense table
     int64_t tiles, nodes;
     size_t bytes;
 };
 
-static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth, int64_t nq_order = 0) {
+static KnnLayout knn_layout(void *ws, int64_t n, uint32_t depth, int64_t nq_order = 0,
+                            bool linear = false) {
     KnnLayout L;
     Carve c(ws);
     L.tiles = n > 0 ? (n + kTreeTile - 1) / kTreeTile : 1;
     L.nodes = tree_nodes_max(n, depth);
     L.ctl = c.take<Control>(1);
+    if (linear) {  // LINEAR keys: re-keyed to Morton and sorted with their positions
+        SortCfg cfg;
+        cfg.radix_bits = 8;
+        cfg.items = 16;
+        sort_carve(c, L.msort, n, 3 * (int)depth, cfg);
+        const size_t kb = wide_keys(depth) ? 8 : 4, m = (size_t)(n > 0 ? n : 1);
+        for (int b = 0; b < 3; ++b) L.mk[b] = c.take<uint8_t>(m * kb);
+        for (int b = 0; b < 3; ++b) L.pos[b] = c.take<uint32_t>(m);
+    }
     if (nq_order > 0) {
         SortCfg cfg;
         cfg.radix_bits = 8;
@@ -1415,11 +1448,11 @@ static void knn_launch(const cga_grid *g, const KnnLayout &L, const float *q, in
     if (g->depth <= kPackedDepth)
         k_knn_tree<KT, PackedList<KT>, kCount><<<blocks, kKnnBlock, lds, s>>>(
             L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
-            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, work);
+            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, L.perm, work);
     else
         k_knn_tree<KT, WideList<KT>, kCount><<<blocks, kKnnBlock, lds, s>>>(
             L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
-            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, work);
+            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, L.perm, work);
 }
 
 template <bool kCount>
@@ -1448,6 +1481,25 @@ __global__ __launch_bounds__(256) void k_binary_lookup(const uint64_t *__restric
     if (found) found[j] = (uint8_t)(r < n && keys[r] == v);
 }
 
+// LINEAR keys: their Morton re-keys sorted with the key positions (an 8-bit
+// key-value radix sort: mk[0] -> ... -> mk[2], pos likewise); the tree is
+// built over mk[2] and the search reports positions through pos[2].
+template <typename K>
+static void linear_rekey(KnnLayout &L, const K *keys, int64_t n, const int64_t *d_n,
+                         uint32_t depth, hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+    {
+        CGA_PROF("knn_rekey", s);
+        k_linear_to_morton<K><<<(unsigned)blocks, 256, 0, s>>>(keys, n, d_n, depth, (K *)L.mk[0],
+                                                                L.pos[0]);
+    }
+    sort_launch_kv<K>(L.msort, (const K *)L.mk[0], (K *)L.mk[2], (K *)L.mk[1], (K *)L.mk[2],
+                      L.pos[0], L.pos[2], L.pos[1], L.pos[2], n, d_n, false,
+                      &L.ctl->tile_ctr[kLinearSortCtr], s);
+    L.perm = L.pos[2];
+}
+
 }  // namespace cga
 
 using namespace cga;
@@ -1456,8 +1508,10 @@ extern "C" {
 
 size_t cga_knn_workspace_bytes(const cga_grid *g, int64_t n, int64_t nq) {
     if (!grid_valid(g) || n < 0 || nq < 0) return 0;
-    return knn_layout(nullptr, n, g->depth, knn_order(nq) ? nq : 0).bytes;
+    return knn_layout(nullptr, n, g->depth, knn_order(nq) ? nq : 0,
+                      g->key_mode == CGA_KEY_LINEAR).bytes;
 }
+
 
 static int knn_call(const cga_grid *g, const void *d_keys, int64_t n, const int64_t *d_n,
                     const float *d_q, int64_t nq, int k, int64_t *d_idx, uint64_t *d_d2, void *d_ws,
@@ -1466,14 +1520,14 @@ static int knn_call(const cga_grid *g, const void *d_keys, int64_t n, const int6
         return CGA_EINVAL;
     if (nq > 0 && (!d_q || !d_idx || !d_d2)) return CGA_EINVAL;
     if (n > 0 && !d_keys) return CGA_EINVAL;
-    if (g->key_mode != CGA_KEY_MORTON) return CGA_EUNSUPPORTED;
     if (nq >= ((int64_t)1 << (64 - kOrderBits))) return CGA_EUNSUPPORTED;
-    const bool ordered = knn_order(nq);
-    KnnLayout L = knn_layout(d_ws, n, g->depth, ordered ? nq : 0);
+    const bool ordered = knn_order(nq), linear = g->key_mode == CGA_KEY_LINEAR;
+    KnnLayout L = knn_layout(d_ws, n, g->depth, ordered ? nq : 0, linear);
     if (ws_bytes < L.bytes) return CGA_EWORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     CGA_TRY(launch_begin(L.ctl, ordered ? L.sort.hist : nullptr, ordered ? sort_zero_bytes(L.sort) : 0,
-                         nullptr, 0, nullptr, s));
+                         linear ? L.msort.hist : nullptr, linear ? sort_zero_bytes(L.msort) : 0,
+                         nullptr, s));
     if (nq > 0) {
         if (ordered) {
             int64_t blocks = (nq + 256 * 8 - 1) / (256 * 8);
@@ -1490,10 +1544,18 @@ static int knn_call(const cga_grid *g, const void *d_keys, int64_t n, const int6
         } else {
             L.ob = nullptr;
         }
+        const void *tk = d_keys;  // the keys the tree is built over (Morton order)
+        if (linear && n > 0) {
+            if (wide_keys(g->depth))
+                linear_rekey<uint64_t>(L, (const uint64_t *)d_keys, n, d_n, g->depth, s);
+            else
+                linear_rekey<uint32_t>(L, (const uint32_t *)d_keys, n, d_n, g->depth, s);
+            tk = L.mk[2];
+        }
         if (wide_keys(g->depth))
-            tree_build<uint64_t>(L, (const uint64_t *)d_keys, n, d_n, g->depth, s);
+            tree_build<uint64_t>(L, (const uint64_t *)tk, n, d_n, g->depth, s);
         else
-            tree_build<uint32_t>(L, (const uint32_t *)d_keys, n, d_n, g->depth, s);
+            tree_build<uint32_t>(L, (const uint32_t *)tk, n, d_n, g->depth, s);
         if (work) knn_dispatch<true>(g, L, d_q, nq, k, d_idx, d_d2, s, work);
         else knn_dispatch<false>(g, L, d_q, nq, k, d_idx, d_d2, s, nullptr);
         CGA_HIP(hipGetLastError());

@@ -615,12 +615,33 @@ def test_values_tile_runs(gpu, depth):
     assert e.value.status == gpu.EMISMATCH
 
 
-def test_knn_linear_unsupported(gpu, w_c1):
-    g = w_c1["grid"].with_mode(L)
-    k, _ = gpu.cga_build(dev(w_c1["a"]), g)
-    with pytest.raises(gpu.CgaError) as e:
-        gpu.cga_knn(k, dev(w_c1["q"]), g, 1)
-    assert e.value.status == gpu.EUNSUPPORTED
+@pytest.mark.parametrize("ordered", [False, True])
+def test_knn_linear(gpu, w_c1, w_c2s, monkeypatch, ordered):
+    """k-NN on LINEAR CGAs (re-keyed to Morton inside the call, positions
+    carried along): rows are LINEAR positions, ties broken by the smaller
+    LINEAR position, as the oracle does -- c1 (brute force), the c2 sweep,
+    a tiny grid full of ties, fewer voxels than k, depth 21."""
+    if ordered:
+        monkeypatch.setenv("CGA_KNN_ORDER", "1")
+    g1 = w_c1["grid"].with_mode(L)
+    k1, _ = gpu.cga_build(dev(w_c1["a"]), g1)
+    _check_knn(gpu, k1, w_c1["q"], g1, 1, tier="brute")
+    g2 = w_c2s["grid"].with_mode(L)
+    k2, _ = gpu.cga_build(dev(w_c2s["a"]), g2)
+    for k in (1, 8, 16):
+        say("knn linear c2s", k, "ordered" if ordered else "")
+        _check_knn(gpu, k2, w_c2s["q"], g2, k)
+    rng = np.random.default_rng(41)
+    g5 = Grid((0.0, 0.0, 0.0), 1.0, 5, L)
+    pts = rng.integers(0, 32, (300, 3)).astype(np.float32)
+    k5, _ = gpu.cga_build(dev(pts), g5)
+    q = np.concatenate([pts[:50], rng.integers(-3, 35, (500, 3)).astype(np.float32)])
+    for k in (1, 5, 13, 32):
+        _check_knn(gpu, k5, q, g5, k, tier="brute")
+    _check_knn(gpu, k5[:3], q[:40], g5, 8, tier="brute")
+    g21 = Grid((0.0, 0.0, 0.0), float(2 ** 21), 21, L)
+    k21, _ = gpu.cga_build(dev(rng.uniform(0, 1, (20_000, 3)).astype(np.float32)), g21)
+    _check_knn(gpu, k21, rng.uniform(0, 1, (700, 3)).astype(np.float32), g21, 4)
 
 
 # ------------------------------------------------------------------ lookup
