@@ -659,11 +659,13 @@ def test_binary_lookup(gpu):
 
 
 # ------------------------------------------------- device-resident pipeline
-def test_device_count_pipeline_and_repeat(gpu, w_c2s):
+@pytest.mark.parametrize("mode", [M, L])
+def test_device_count_pipeline_and_repeat(gpu, w_c2s, mode):
     """build -> merge -> project -> kNN with every size left on the device (no
-    host sync between calls) equals the synchronous path, twice in a row."""
+    host sync between calls) equals the synchronous path, twice in a row, on
+    both key orders (the LINEAR k-NN re-keys only the device count's keys)."""
     d = w_c2s
-    g = d["grid"]
+    g = d["grid"].with_mode(mode)
     a, b, q = dev(d["a"]), dev(d["b"]), dev(d["q"])
     ref_m, _ = gpu.cga_merge(gpu.cga_build(a, g)[0], gpu.cga_build(b, g)[0], g)
     ref_p, ref_c = gpu.cga_project(ref_m, g, 2)
