@@ -271,7 +271,7 @@ int cga_knn(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *
 /* The same search built with work counters, for measurement: identical
  * outputs, and d_work (device, 4 uint64, accumulated -- the caller zeroes
  * it) gains the search's node-record loads (16 B each), dense-table loads (4 B
- * each), voxels offered to the candidate lists and walk-loop steps, summed
+ * each), voxels offered to the candidate list and walk-loop steps, summed
  * over all queries and lanes.  The search is deterministic, so these are the
  * exact per-call work of cga_knn on the same input. */
 int cga_knn_count(const cga_grid *grid, const void *d_keys, int64_t n, const int64_t *d_n,

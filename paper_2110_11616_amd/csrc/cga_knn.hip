@@ -708,10 +708,28 @@ __device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
     return (uint32_t)r;
 }
 
-// Candidate lists, ascending in (squared distance, key index), kept in
-// registers: every array below is indexed only inside unrolled loops, and a
-// k-th entry is taken as a predicated maximum, never a variable index (which
-// would move the list to scratch memory).
+// Team lane shifts for the shared candidate lists: a 64-bit value from the
+// lane one below (DPP row shift; a team's lane 0 gets another team's value,
+// which the caller discards), and one lane's value sent to every lane.
+__device__ __forceinline__ uint32_t dpp_prev_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+}
+__device__ __forceinline__ uint64_t dpp_prev_u64(uint64_t x) {
+    return ((uint64_t)dpp_prev_u32((uint32_t)(x >> 32)) << 32) | dpp_prev_u32((uint32_t)x);
+}
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Candidate lists of one query, shared by its team of kTeam lanes: ascending
+// in (squared distance, key index) over the team, lane t holding positions
+// t*E .. t*E + E - 1 in registers (every array below is indexed only inside
+// unrolled loops).  A candidate offered by one lane is sent to the whole team
+// and inserted with one shift by one position: the team then prunes with the
+// k-th distance of every candidate it has found.  Insertions need every lane
+// of the team active.
 //
 // Up to depth 15 a squared voxel distance is below 2^32 - 1, so a candidate
 // packs into one word, distance above index, whose integer order is the
@@ -719,61 +737,47 @@ __device__ __forceinline__ uint32_t isqrt64(uint64_t v) {
 template <int KT>
 struct PackedList {
     using Dist = uint32_t;
+    static constexpr int E = KT >= kTeam ? KT / kTeam : 1;  // entries per lane
     static constexpr uint64_t kNone = ~0ull;  // bound meaning "no k-th candidate yet"
-    uint64_t e[KT];
+    struct Cand {
+        uint64_t v;
+    };
+    uint64_t e[E];
     __device__ __forceinline__ void clear() {
 #pragma unroll
-        for (int s = 0; s < KT; ++s) e[s] = ~0ull;
+        for (int s = 0; s < E; ++s) e[s] = ~0ull;
     }
-    __device__ __forceinline__ void offer(uint32_t d, int32_t i) {
-        const uint64_t v = ((uint64_t)d << 32) | (uint32_t)i;
-        if (v >= e[KT - 1]) return;
+    __device__ static __forceinline__ Cand make(uint32_t d, int32_t i) {
+        return Cand{((uint64_t)d << 32) | (uint32_t)i};
+    }
+    __device__ static __forceinline__ Cand bcast(Cand c, int src) { return Cand{shfl_u64(c.v, src)}; }
+    // insert c (the same on every lane of the team); tl = lane within the team
+    __device__ __forceinline__ void insert(Cand c, int tl) {
+        const uint64_t v = c.v;
+        const uint64_t p = dpp_prev_u64(e[E - 1]);
+        const uint64_t below = tl == 0 ? 0ull : p;  // position t*E - 1 (none for lane 0)
 #pragma unroll
-        for (int s = KT - 1; s > 0; --s) {
+        for (int s = E - 1; s > 0; --s) {
             const uint64_t lo = e[s - 1], cur = e[s];
             e[s] = v < lo ? lo : (v < cur ? v : cur);
         }
-        e[0] = v < e[0] ? v : e[0];
+        e[0] = v < below ? below : (v < e[0] ? v : e[0]);
     }
-    // k-th distance, or kNone while fewer than k candidates are held
-    __device__ __forceinline__ uint64_t kth(int k) const {
-        uint64_t m = e[KT - 1];
-        if (k != KT) {  // grid-uniform
-            m = e[0];
+    // the team's k-th distance, or kNone while it holds fewer than k; base =
+    // the team's lane 0
+    __device__ __forceinline__ uint64_t kth(int k, int base) const {
+        const int pos = k - 1, slot = pos % E;
+        uint32_t hi = (uint32_t)(e[0] >> 32);
 #pragma unroll
-            for (int s = 1; s < KT; ++s) {
-                const uint64_t v = s < k ? e[s] : 0;
-                m = v > m ? v : m;
-            }
-        }
-        return m == ~0ull ? kNone : (m >> 32);
+        for (int s = 1; s < E; ++s) hi = s == slot ? (uint32_t)(e[s] >> 32) : hi;
+        hi = (uint32_t)__shfl((int)hi, base + pos / E, 64);
+        return hi == 0xFFFFFFFFu ? kNone : hi;
     }
-    __device__ __forceinline__ void merge_step(int step) {
-        uint64_t p[KT];
-#pragma unroll
-        for (int s = 0; s < KT; ++s) {
-            const uint32_t lo = __shfl_xor((uint32_t)e[s], step, 64);
-            const uint32_t hi = __shfl_xor((uint32_t)(e[s] >> 32), step, 64);
-            p[s] = ((uint64_t)hi << 32) | lo;
-        }
-#pragma unroll
-        for (int s = 0; s < KT; ++s) e[s] = p[KT - 1 - s] < e[s] ? p[KT - 1 - s] : e[s];
-#pragma unroll
-        for (int j = KT / 2; j > 0; j >>= 1) {
-#pragma unroll
-            for (int s = 0; s < KT; ++s) {
-                if ((s & j) == 0) {
-                    const uint64_t a = e[s], b = e[s + j];
-                    e[s] = a < b ? a : b;
-                    e[s + j] = a < b ? b : a;
-                }
-            }
-        }
-    }
+    // this lane's entry s (team position tl*E + s)
     __device__ __forceinline__ void out(int s, int64_t &idx, uint64_t &d2) const {
         uint64_t v = e[0];
 #pragma unroll
-        for (int t = 1; t < KT; ++t) v = t == s ? e[t] : v;
+        for (int t = 1; t < E; ++t) v = t == s ? e[t] : v;
         idx = v == ~0ull ? -1 : (int64_t)(uint32_t)v;
         d2 = v == ~0ull ? ~0ull : (v >> 32);
     }
@@ -784,23 +788,39 @@ struct PackedList {
 template <int KT>
 struct WideList {
     using Dist = uint64_t;
+    static constexpr int E = KT >= kTeam ? KT / kTeam : 1;
     static constexpr uint64_t kNone = ~0ull;
-    uint64_t d[KT];
-    int32_t i[KT];
+    struct Cand {
+        uint64_t d;
+        int32_t i;
+    };
+    uint64_t d[E];
+    int32_t i[E];
     __device__ static __forceinline__ bool less(uint64_t ad, int32_t ai, uint64_t bd, int32_t bi) {
         return ad < bd || (ad == bd && ai < bi);
     }
     __device__ __forceinline__ void clear() {
 #pragma unroll
-        for (int s = 0; s < KT; ++s) {
+        for (int s = 0; s < E; ++s) {
             d[s] = ~0ull;
             i[s] = 0x7FFFFFFF;
         }
     }
-    __device__ __forceinline__ void offer(uint64_t vd, int32_t vi) {
-        if (!less(vd, vi, d[KT - 1], i[KT - 1])) return;
+    __device__ static __forceinline__ Cand make(uint64_t vd, int32_t vi) { return Cand{vd, vi}; }
+    __device__ static __forceinline__ Cand bcast(Cand c, int src) {
+        return Cand{shfl_u64(c.d, src), __shfl(c.i, src, 64)};
+    }
+    __device__ __forceinline__ void insert(Cand c, int tl) {
+        const uint64_t vd = c.d;
+        const int32_t vi = c.i;
+        uint64_t bd = dpp_prev_u64(d[E - 1]);
+        int32_t bi = (int32_t)dpp_prev_u32((uint32_t)i[E - 1]);
+        if (tl == 0) {  // nothing below lane 0's first position
+            bd = 0;
+            bi = INT32_MIN;
+        }
 #pragma unroll
-        for (int s = KT - 1; s > 0; --s) {
+        for (int s = E - 1; s > 0; --s) {
             const bool sh = less(vd, vi, d[s - 1], i[s - 1]);
             const bool here = less(vd, vi, d[s], i[s]);
             const uint64_t nd = sh ? d[s - 1] : (here ? vd : d[s]);
@@ -808,59 +828,25 @@ struct WideList {
             d[s] = nd;
             i[s] = ni;
         }
-        const bool f = less(vd, vi, d[0], i[0]);
-        d[0] = f ? vd : d[0];
-        i[0] = f ? vi : i[0];
+        const bool sh = less(vd, vi, bd, bi);
+        const bool here = less(vd, vi, d[0], i[0]);
+        const uint64_t nd = sh ? bd : (here ? vd : d[0]);
+        const int32_t ni = sh ? bi : (here ? vi : i[0]);
+        d[0] = nd;
+        i[0] = ni;
     }
-    __device__ __forceinline__ uint64_t kth(int k) const {
-        uint64_t m = d[KT - 1];
-        if (k != KT) {  // grid-uniform
-            m = d[0];
+    __device__ __forceinline__ uint64_t kth(int k, int base) const {
+        const int pos = k - 1, slot = pos % E;
+        uint64_t m = d[0];
 #pragma unroll
-            for (int s = 1; s < KT; ++s) {
-                const uint64_t v = s < k ? d[s] : 0;
-                m = v > m ? v : m;
-            }
-        }
-        return m;
-    }
-    __device__ __forceinline__ void merge_step(int step) {
-        uint64_t pd[KT];
-        int32_t pi[KT];
-#pragma unroll
-        for (int s = 0; s < KT; ++s) {
-            const uint32_t lo = __shfl_xor((uint32_t)d[s], step, 64);
-            const uint32_t hi = __shfl_xor((uint32_t)(d[s] >> 32), step, 64);
-            pd[s] = ((uint64_t)hi << 32) | lo;
-            pi[s] = __shfl_xor(i[s], step, 64);
-        }
-#pragma unroll
-        for (int s = 0; s < KT; ++s) {
-            const bool t = less(pd[KT - 1 - s], pi[KT - 1 - s], d[s], i[s]);
-            d[s] = t ? pd[KT - 1 - s] : d[s];
-            i[s] = t ? pi[KT - 1 - s] : i[s];
-        }
-#pragma unroll
-        for (int j = KT / 2; j > 0; j >>= 1) {
-#pragma unroll
-            for (int s = 0; s < KT; ++s) {
-                if ((s & j) == 0) {
-                    const uint64_t ad = d[s], bd = d[s + j];
-                    const int32_t ai = i[s], bi = i[s + j];
-                    const bool t = less(bd, bi, ad, ai);
-                    d[s] = t ? bd : ad;
-                    i[s] = t ? bi : ai;
-                    d[s + j] = t ? ad : bd;
-                    i[s + j] = t ? ai : bi;
-                }
-            }
-        }
+        for (int s = 1; s < E; ++s) m = s == slot ? d[s] : m;
+        return shfl_u64(m, base + pos / E);
     }
     __device__ __forceinline__ void out(int s, int64_t &idx, uint64_t &d2) const {
         uint64_t vd = d[0];
         int32_t vi = i[0];
 #pragma unroll
-        for (int t = 1; t < KT; ++t) {
+        for (int t = 1; t < E; ++t) {
             vd = t == s ? d[t] : vd;
             vi = t == s ? i[t] : vi;
         }
@@ -893,12 +879,11 @@ void k_knn_tree(
     uint32_t c_node = 0, c_dense = 0, c_vox = 0, c_step = 0;  // kCount only
     using Dist = typename LIST::Dist;
     extern __shared__ uint64_t s_word[];  // open node word per level, one column per thread
-    __shared__ unsigned long long s_bound[kTeamsPerBlock];
     __shared__ uint64_t s_sw[kKnnBlock], s_sc[kKnnBlock];  // start cells of the round: word, corner
     __shared__ int64_t s_base[kMaxDepth + 1];
     const int tid = threadIdx.x, team = tid / kTeam, tl = tid % kTeam;
+    const int tw = (tid & 63) / kTeam, tbase = (tid & 63) - tl;  // team within the wave, its lane 0
     if (tid >= 1 && tid <= depth) s_base[tid] = lvl[kLvlBase + tid];
-    if (tl == 0) s_bound[team] = LIST::kNone;
     __syncthreads();  // the only block-wide barrier; teams run independently after it
     const int64_t slot = (int64_t)blockIdx.x * kTeamsPerBlock + team;
     if (slot >= nq) return;
@@ -920,7 +905,7 @@ void k_knn_tree(
     }
     LIST list;
     list.clear();
-    uint64_t kth = LIST::kNone;  // this lane's k-th distance
+    uint64_t kth = LIST::kNone;  // the team's k-th distance
 
     // the query's octant at level l is digit l of its Morton key
     const uint64_t qkey = enc3(qv.x, qv.y, qv.z, depth, false);
@@ -935,15 +920,28 @@ void k_knn_tree(
     };
     // a voxel's position: in the key array, or through perm in the caller's
     // LINEAR array (then ties go to the smaller LINEAR position, as there)
-    auto offer = [&](Dist d, int32_t i) __attribute__((always_inline)) {
+    using Cand = typename LIST::Cand;
+    auto cand = [&](Dist d, int32_t i) __attribute__((always_inline)) -> Cand {
         if (kCount) ++c_vox;
-        list.offer(d, perm ? (int32_t)perm[i] : i);
-        kth = list.kth(k);
-        if (kth < s_bound[team]) atomicMin(&s_bound[team], (unsigned long long)kth);
+        return LIST::make(d, perm ? (int32_t)perm[i] : i);
+    };
+    // Every lane of the team with a candidate (pend) inserts it into the
+    // team's list, one lane after another; the team's k-th distance follows.
+    // Called with every lane of the team active.
+    auto team_offer = [&](bool pend, Cand c) __attribute__((always_inline)) {
+        const uint64_t b = __ballot(pend);
+        if (!b) return;  // no lane of the wave has one
+        uint32_t tm = (uint32_t)(b >> (kTeam * tw)) & ((1u << kTeam) - 1u);
+        while (tm) {
+            const int src = __builtin_ctz(tm);
+            tm &= tm - 1;
+            list.insert(LIST::bcast(c, tbase + src), tl);
+        }
+        kth = list.kth(k, tbase);
     };
     // Region already searched (a box of level-sk_l cells, every earlier
-    // round's region inside it), skipped by later rounds so that lane 0 can
-    // carry the team's list forward without repeats.
+    // round's region inside it), skipped by later rounds so that the team's
+    // list, kept from round to round, never takes a voxel twice.
     bool skip = false;
     int sk_l = 0;
     uint32_t sk_x0 = 0, sk_x1 = 0, sk_y0 = 0, sk_y1 = 0, sk_z0 = 0, sk_z1 = 0;
@@ -1016,10 +1014,6 @@ void k_knn_tree(
             }
         }
         const int64_t cn = ok && !skipped(c[0], c[1], c[2], ls) ? find_node(c[0], c[1], c[2], ls) : -1;
-        auto bound_now = [&]() __attribute__((always_inline)) -> uint64_t {
-            const uint64_t b = s_bound[team];
-            return kth < b ? kth : b;
-        };
         // The start cells are shared out a child at a time: lane tl walks
         // child near_order(tl) ^ (query octant) of every start cell in turn,
         // so that the heaviest cell's work is spread over the whole team.
@@ -1028,10 +1022,16 @@ void k_knn_tree(
         uint32_t avail = 0;     // start cells that have this lane's child
         uint32_t qs = 0;
         if (ls == 0) {
+            bool pend = false;
+            Cand cv{};
             if (cn >= 0) {
                 const Dist d = box_dist(c[0], c[1], c[2], 0);
-                if (d <= bound_now()) offer(d, (int32_t)cn);
+                if (d <= kth) {
+                    pend = true;
+                    cv = cand(d, (int32_t)cn);
+                }
             }
+            team_offer(pend, cv);
         } else {
             s_sw[tid] = cn >= 0 ? node[2 * (s_base[ls] + cn)] : 0ull;
             if (kCount) c_node += cn >= 0 ? 1u : 0u;
@@ -1043,8 +1043,10 @@ void k_knn_tree(
 #pragma unroll
             for (int m = 0; m < kTeam; ++m) avail |= (uint32_t)((s_sw[team * kTeam + m] >> qs) & 1u) << m;
         }
-        if (avail) {
-            // depth-first walk of each subtree, nearest child first
+        if (ls != 0) {
+            // depth-first walk of each subtree, nearest child first (a lane
+            // whose walks are over stays in the loop for its team's
+            // insertions until every lane of the wave is done)
             int l = l0;
             uint32_t x0 = 0, y0 = 0, z0 = 0;
             uint64_t w = 0, wo = 0;  // the open node's words: mask and first child; oriented box
@@ -1086,7 +1088,7 @@ void k_knn_tree(
                 gaps(1, qv.y, y0, gyl, gyh);
                 gaps(2, qv.z, z0, gzl, gzh);
                 touch = skip && cl == sk_l;
-                bnd = to_dist(bound_now());
+                bnd = to_dist(kth);
                 // children already beyond the bound never take a step
                 const Dist xl = gxl, xh = gxh;
                 const Dist q0 = xl + gyl, q1 = xl + gyh, q2 = xh + gyl, q3 = xh + gyh;
@@ -1108,18 +1110,24 @@ void k_knn_tree(
                 }
             };
             uint32_t pm = 0;
+            bool fin = false;
             // One iteration: start this lane's next subtree, climb back to
             // the parent (its slots up to the one just finished are done), or
             // take the next child -- prune it, offer it (a voxel), or descend
-            // into it.  Starting, climbing and descending share one node-entry
-            // tail, so a wave whose lanes take different paths runs it once.
+            // into it; then the team inserts what its lanes offered.
+            // Starting, climbing and descending share one node-entry tail, so
+            // a wave whose lanes take different paths runs it once.
             for (;;) {
-                if (kCount) ++c_step;
+                bool pend = false;
+                Cand cv{};
                 const bool up = pm == 0;
                 bool moved = false, climbed = false;
                 uint32_t done_oc = 0;
-                if (up && l == l0) {
-                    if (!avail) break;
+                if (fin) {
+                } else if (up && l == l0 && !avail) {
+                    fin = true;
+                } else if (up && l == l0) {
+                    if (kCount) ++c_step;
                     const int m = __builtin_ctz(avail);
                     avail &= avail - 1;
                     const uint64_t sw = s_sw[team * kTeam + m], sc = s_sc[team * kTeam + m];
@@ -1128,9 +1136,10 @@ void k_knn_tree(
                     const uint32_t cz = ((uint32_t)(sc >> 42) & 0x1FFFFFu) | ((qs & 1u) << l0);
                     const int32_t ci = (int32_t)node_first(sw) + __popc((uint32_t)sw & 0xFFu & ((1u << qs) - 1u));
                     const Dist bd = box_dist(cx, cy, cz, l0);
-                    if (bd <= bound_now() && !skipped(cx, cy, cz, l0)) {
+                    if (bd <= kth && !skipped(cx, cy, cz, l0)) {
                         if (l0 == 0) {
-                            offer(bd, ci);
+                            pend = true;
+                            cv = cand(bd, ci);
                         } else {
                             const u64x2 pr = *(const u64x2 *)(node + 2 * (s_base[l0] + ci));
                             w = pr.x;
@@ -1144,6 +1153,7 @@ void k_knn_tree(
                         }
                     }
                 } else if (up) {
+                    if (kCount) ++c_step;
                     done_oc = (((x0 >> l) & 1u) << 2) | (((y0 >> l) & 1u) << 1) | ((z0 >> l) & 1u);
                     ++l;
                     const uint32_t clr = ~((1u << l) - 1u);
@@ -1153,6 +1163,7 @@ void k_knn_tree(
                     w = s_word[l * kKnnBlock + tid];
                     moved = climbed = true;
                 } else {
+                    if (kCount) ++c_step;
                     const uint32_t sl = __builtin_ctz(pm);
                     pm &= pm - 1;
                     const uint32_t oc = near_order(sl) ^ qol;
@@ -1163,8 +1174,8 @@ void k_knn_tree(
                     if (bd <= bnd && !(touch && skipped(cx, cy, cz, cl))) {
                         const int32_t ci = (int32_t)node_first(w) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
                         if (cl == 0) {
-                            offer(bd, ci);
-                            bnd = kth < (uint64_t)bnd ? to_dist(kth) : bnd;
+                            pend = true;
+                            cv = cand(bd, ci);
                         } else {
                             const u64x2 pr = *(const u64x2 *)(node + 2 * (s_base[cl] + ci));
                             w = pr.x;
@@ -1184,11 +1195,11 @@ void k_knn_tree(
                     const uint32_t done_slots = climbed ? (2u << near_order(done_oc ^ qol)) - 1u : 0u;
                     pm = slot_mask((uint32_t)w & near, qol) & ~done_slots;
                 }
+                team_offer(pend, cv);
+                bnd = kth < (uint64_t)bnd ? to_dist(kth) : bnd;
+                if (!__ballot(!fin)) break;
             }
         }
-#pragma unroll
-        for (int step = 1; step < kTeam; step <<= 1) list.merge_step(step);
-        kth = list.kth(k);
         // Exact once every voxel within the k-th distance lies in the region
         // searched so far: the pruning only ever used k-th distances of real
         // candidates, so no voxel of that ball inside the region was missed.
@@ -1226,12 +1237,6 @@ void k_knn_tree(
             sk_z1 = ((uint64_t)qv.z + r < top ? qv.z + r : top) >> ls;
         }
         const uint64_t bound = kth;
-        if (tl != 0) {  // lane 0 carries the team's list into the next round
-            list.clear();
-            kth = LIST::kNone;
-        } else {
-            s_bound[team] = bound;
-        }
         // next cube: the k-th distance ball, or a grown cube while fewer than
         // k candidates are known (from round 0 at least one level-la cell
         // wide, so that the next region contains the la cell)
@@ -1244,13 +1249,14 @@ void k_knn_tree(
         round0 = false;
     }
 #pragma unroll
-    for (int s = 0; s < KT; ++s) {
-        if (s < k && (s % kTeam) == tl) {
+    for (int s = 0; s < LIST::E; ++s) {
+        const int pos = tl * LIST::E + s;
+        if (pos < k) {
             int64_t idx;
             uint64_t d2;
             list.out(s, idx, d2);
-            idx_out[j * k + s] = idx;
-            d2_out[j * k + s] = d2;
+            idx_out[j * k + pos] = idx;
+            d2_out[j * k + pos] = d2;
         }
     }
     if (kCount) {  // the team's sums, one atomic per counter per query
