@@ -1111,22 +1111,77 @@ void k_knn_tree(
             };
             uint32_t pm = 0;
             bool fin = false;
-            // One iteration: start this lane's next subtree, climb back to
-            // the parent (its slots up to the one just finished are done), or
-            // take the next child -- prune it, offer it (a voxel), or descend
-            // into it; then the team inserts what its lanes offered.
-            // Starting, climbing and descending share one node-entry tail, so
-            // a wave whose lanes take different paths runs it once.
+            // Work sharing within the team: lroot is the level this lane's
+            // walk climbs back to (l0, or the node it took over); bit L of
+            // open marks an ancestor at level L on its path that has children
+            // left after the one walked, bit L of given one whose remaining
+            // children another lane took over.
+            int lroot = l0;
+            uint32_t open = 0, given = 0;
+            // One iteration: take over work, start this lane's next subtree,
+            // climb back to the parent (its slots up to the one just finished
+            // are done), or take the next child -- prune it, offer it (a
+            // voxel), or descend into it; then the team inserts what its
+            // lanes offered.  Taking over, starting, climbing and descending
+            // share one node-entry tail, so a wave whose lanes take different
+            // paths runs it once.
             for (;;) {
+                // A lane without work left takes the remaining children of the
+                // shallowest open ancestor of a lane that has one (the k-th
+                // idle lane of the team pairs with its k-th such lane).  A
+                // team's lanes move in step, so no atomics are needed.
+                bool recv = false;
+                int rsrc = 0;
+                uint32_t rx = 0, ry = 0, rz = 0;
+                int rl = 0;
+                {
+                    const bool idle = pm == 0 && l == lroot && !avail;
+                    const uint32_t ti = (uint32_t)(__ballot(idle) >> (kTeam * tw)) & 0xFFu;
+                    const uint32_t td = (uint32_t)(__ballot(open != 0) >> (kTeam * tw)) & 0xFFu;
+                    if (__ballot(ti != 0 && td != 0)) {
+                        const uint32_t below = (1u << tl) - 1u;
+                        const int np = min(__popc(ti), __popc(td));
+                        const int dl = open ? 31 - __builtin_clz(open) : 0;
+                        if (open && __popc(td & below) < np) {
+                            given |= 1u << dl;
+                            open &= ~(1u << dl);
+                        }
+                        const int ri = __popc(ti & below);
+                        uint32_t m = td;
+#pragma unroll
+                        for (int i = 0; i < kTeam - 1; ++i)
+                            if (i < ri) m &= m - 1u;
+                        rsrc = m ? __builtin_ctz(m) : tl;
+                        rl = __shfl(dl, tbase + rsrc, 64);
+                        rx = (uint32_t)__shfl((int)x0, tbase + rsrc, 64);
+                        ry = (uint32_t)__shfl((int)y0, tbase + rsrc, 64);
+                        rz = (uint32_t)__shfl((int)z0, tbase + rsrc, 64);
+                        recv = idle && ri < np;
+                    }
+                }
                 bool pend = false;
                 Cand cv{};
                 const bool up = pm == 0;
                 bool moved = false, climbed = false;
                 uint32_t done_oc = 0;
-                if (fin) {
-                } else if (up && l == l0 && !avail) {
+                if (recv) {
+                    // enter the ancestor as if climbing back into it from the
+                    // child the other lane is walking
+                    l = rl;
+                    lroot = rl;
+                    done_oc = (((rx >> (l - 1)) & 1u) << 2) | (((ry >> (l - 1)) & 1u) << 1) | ((rz >> (l - 1)) & 1u);
+                    const uint32_t clr = ~((1u << l) - 1u);
+                    x0 = rx & clr;
+                    y0 = ry & clr;
+                    z0 = rz & clr;
+                    w = s_word[l * kKnnBlock + (tid - tl + rsrc)];
+                    s_word[l * kKnnBlock + tid] = w;
+                    fin = false;
+                    moved = climbed = true;
+                } else if (fin) {
+                } else if (up && l == lroot && !avail) {
                     fin = true;
-                } else if (up && l == l0) {
+                } else if (up && l == lroot) {
                     if (kCount) ++c_step;
                     const int m = __builtin_ctz(avail);
                     avail &= avail - 1;
@@ -1156,6 +1211,7 @@ void k_knn_tree(
                     if (kCount) ++c_step;
                     done_oc = (((x0 >> l) & 1u) << 2) | (((y0 >> l) & 1u) << 1) | ((z0 >> l) & 1u);
                     ++l;
+                    open &= ~(1u << l);
                     const uint32_t clr = ~((1u << l) - 1u);
                     x0 &= clr;
                     y0 &= clr;
@@ -1182,6 +1238,7 @@ void k_knn_tree(
                             wo = pr.y;
                             if (kCount) ++c_node;
                             s_word[cl * kKnnBlock + tid] = w;
+                            if (pm) open |= 1u << l;
                             l = cl;
                             x0 = cx;
                             y0 = cy;
@@ -1194,6 +1251,10 @@ void k_knn_tree(
                     enter(!climbed);
                     const uint32_t done_slots = climbed ? (2u << near_order(done_oc ^ qol)) - 1u : 0u;
                     pm = slot_mask((uint32_t)w & near, qol) & ~done_slots;
+                    if (climbed && ((given >> l) & 1u)) {  // its remaining children went to another lane
+                        pm = 0;
+                        given &= ~(1u << l);
+                    }
                 }
                 team_offer(pend, cv);
                 bnd = kth < (uint64_t)bnd ? to_dist(kth) : bnd;
