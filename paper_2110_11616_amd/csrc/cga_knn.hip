@@ -37,6 +37,9 @@
 // (their children dealt out the same way), and repeats with the grown ball
 // until a round that started from a known bound covers it.
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "cga_common.h"
 #include "cga_sort.h"
@@ -44,7 +47,12 @@
 namespace cga {
 
 constexpr int kKnnBlock = 256;
-constexpr int kTeam = 8;
+#ifndef CGA_KNN_TEAM
+#define CGA_KNN_TEAM 8
+#endif
+constexpr int kTeam = CGA_KNN_TEAM;  // lanes per query
+constexpr int kCells = 8;            // start cells of a round, children of a node
+static_assert(kTeam >= kCells && kTeam <= 32 && (kTeam & (kTeam - 1)) == 0, "team size");
 constexpr int kTeamsPerBlock = kKnnBlock / kTeam;
 constexpr int kMaxDepth = 21;
 constexpr int kTreeRows = 4;                       // rows of 256 keys per build tile
@@ -284,6 +292,8 @@ constexpr uint64_t kNodeFirstMask = 0x7FFFFFFFull;
 constexpr int kScanLevels = 6;  // levels whose oriented boxes are fitted to the voxels
 constexpr int kTreeBigCtr = 24;  // control-block counters of the big-node lists, one per level
 constexpr int kLinearSortCtr = 8;  // tile counters of the LINEAR keys' re-key sort (up to 8 passes)
+constexpr int kKnnQueryCtr = 20;   // control-block counter of the search's query queue
+constexpr int64_t kKnnQueuePerTeam = 8;  // queries per team from which the search uses it
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 constexpr int kNodeBoxShift = 40;
 __host__ __device__ __forceinline__ int64_t node_first(uint64_t w) {
@@ -864,10 +874,17 @@ constexpr int knn_waves_per_eu() {
     return (KT <= 8 && sizeof(typename LIST::Dist) == 4) ? 5 : 1;
 }
 
-// One query per team of kTeam lanes.  LIST is PackedList (depth <= 15) or
-// WideList.  kCount (a measurement build, same results): every lane counts
-// its node-word loads, dense-table loads, voxels whose distance it took and
-// loop steps, summed into work[0..3].
+// One query at a time per team of kTeam lanes: each team's first query by
+// its place in the grid, the next ones from a counter (qctr, zero at launch;
+// without it, round-robin over the grid).  LIST is
+// PackedList (depth <= 15) or WideList.  The kernel is one loop whose every
+// trip moves each team one step in its own query: set up a query, set up a
+// round (its start cells), walk (one step per lane, with work handed from
+// busy lanes to idle ones), end a round, so that a team whose query or round
+// is over goes on with the next one instead of waiting for the other teams
+// of its wave.  kCount (a measurement build, same results): every lane
+// counts its node-word loads, dense-table loads, voxels whose distance it
+// took and walk steps, summed into work[0..3].
 template <int KT, class LIST, bool kCount = false>
 __global__ __launch_bounds__(kKnnBlock) __attribute__((amdgpu_waves_per_eu(knn_waves_per_eu<KT, LIST>())))
 void k_knn_tree(
@@ -875,89 +892,108 @@ void k_knn_tree(
     const int64_t *__restrict__ lvl, int64_t nodes_max, const float *__restrict__ q, int64_t nq,
     const uint64_t *__restrict__ order, float o0, float o1, float o2, float scale, uint32_t depth,
     int dl, int k, int la, int64_t *__restrict__ idx_out, uint64_t *__restrict__ d2_out,
-    uint32_t *err, const uint32_t *__restrict__ perm = nullptr, unsigned long long *work = nullptr) {
+    uint32_t *err, uint32_t *qctr, const uint32_t *__restrict__ perm = nullptr,
+    unsigned long long *work = nullptr) {
     uint32_t c_node = 0, c_dense = 0, c_vox = 0, c_step = 0;  // kCount only
     using Dist = typename LIST::Dist;
-    extern __shared__ uint64_t s_word[];  // open node word per level, one column per thread
+    using Cand = typename LIST::Cand;
+    // open node word per level 1 .. depth - 1 (the levels a walk opens),
+    // one column per thread
+    extern __shared__ uint64_t s_word[];
     __shared__ uint64_t s_sw[kKnnBlock], s_sc[kKnnBlock];  // start cells of the round: word, corner
     __shared__ int64_t s_base[kMaxDepth + 1];
     const int tid = threadIdx.x, team = tid / kTeam, tl = tid % kTeam;
     const int tw = (tid & 63) / kTeam, tbase = (tid & 63) - tl;  // team within the wave, its lane 0
+    const uint32_t tmask = (uint32_t)((1ull << kTeam) - 1ull);
     if (tid >= 1 && tid <= depth) s_base[tid] = lvl[kLvlBase + tid];
     __syncthreads();  // the only block-wide barrier; teams run independently after it
-    const int64_t slot = (int64_t)blockIdx.x * kTeamsPerBlock + team;
-    if (slot >= nq) return;
-    const int64_t j = order ? (int64_t)(order[slot] >> kOrderBits) : slot;  // query (and output row)
     // an oversized tree (keys that are not a CGA of the grid) searches nothing
     const int64_t n = tree_total(lvl) < 0 ? 0 : lvl[0];
     const int dt = dense_level(depth, dl);
-
     const float o[3] = {o0, o1, o2};
-    Vox qv;
-    const bool finite = quantize3(q[3 * j], q[3 * j + 1], q[3 * j + 2], o, scale, depth, qv);
-    if (!finite && tl == 0) set_err(err, ERR_NONFINITE);
-    if (!finite || n == 0) {
-        for (int s = tl; s < k; s += kTeam) {
-            idx_out[j * k + s] = -1;
-            d2_out[j * k + s] = ~0ull;
-        }
-        return;
-    }
+    const uint32_t top = (1u << depth) - 1;
+    const int64_t stride = (int64_t)gridDim.x * kTeamsPerBlock;
+
+    // ---- per query
+    int64_t slot = (int64_t)blockIdx.x * kTeamsPerBlock + team, j = 0;
+    uint32_t nxt = 0;  // lane 0: the team's next query from the counter, taken one query ahead
+    auto next_slot = [&]() __attribute__((always_inline)) -> int64_t {
+        return qctr ? stride + (int64_t)(uint32_t)__shfl((int)nxt, tbase, 64) : slot + stride;
+    };
+    Vox qv{0, 0, 0};
+    uint64_t qkey = 0;
     LIST list;
     list.clear();
     uint64_t kth = LIST::kNone;  // the team's k-th distance
-
-    // the query's octant at level l is digit l of its Morton key
-    const uint64_t qkey = enc3(qv.x, qv.y, qv.z, depth, false);
-    auto qo = [&](int l) __attribute__((always_inline)) -> uint32_t {
-        return (uint32_t)(qkey >> (3 * l)) & 7u;
-    };
-    auto box_dist = [&](uint32_t x, uint32_t y, uint32_t z, int l) __attribute__((always_inline)) -> Dist {
-        const uint32_t e = (1u << l) - 1;
-        const Dist gx = axis_gap(qv.x, x, x + e), gy = axis_gap(qv.y, y, y + e),
-                   gz = axis_gap(qv.z, z, z + e);
-        return gx * gx + gy * gy + gz * gz;
-    };
-    // a voxel's position: in the key array, or through perm in the caller's
-    // LINEAR array (then ties go to the smaller LINEAR position, as there)
-    using Cand = typename LIST::Cand;
-    auto cand = [&](Dist d, int32_t i) __attribute__((always_inline)) -> Cand {
-        if (kCount) ++c_vox;
-        return LIST::make(d, perm ? (int32_t)perm[i] : i);
-    };
-    // Every lane of the team with a candidate (pend) inserts it into the
-    // team's list, one lane after another; the team's k-th distance follows.
-    // Called with every lane of the team active.
-    auto team_offer = [&](bool pend, Cand c) __attribute__((always_inline)) {
-        const uint64_t b = __ballot(pend);
-        if (!b) return;  // no lane of the wave has one
-        uint32_t tm = (uint32_t)(b >> (kTeam * tw)) & ((1u << kTeam) - 1u);
-        while (tm) {
-            const int src = __builtin_ctz(tm);
-            tm &= tm - 1;
-            list.insert(LIST::bcast(c, tbase + src), tl);
-        }
-        kth = list.kth(k, tbase);
-    };
+    bool round0 = true;
+    uint32_t r = 0;
+    int ls = 0;
     // Region already searched (a box of level-sk_l cells, every earlier
     // round's region inside it), skipped by later rounds so that the team's
     // list, kept from round to round, never takes a voxel twice.
     bool skip = false;
     int sk_l = 0;
     uint32_t sk_x0 = 0, sk_x1 = 0, sk_y0 = 0, sk_y1 = 0, sk_z0 = 0, sk_z1 = 0;
-    auto skipped = [&](uint32_t x, uint32_t y, uint32_t z, int l) __attribute__((always_inline)) {
-        if (!skip || l > sk_l) return false;
+    // ---- per round: level of the walked subtrees, the start cells that
+    // have this lane's child, that child's octant
+    int l0 = 0;
+    uint32_t avail = 0, qs = 0;
+    // ---- per walk: depth-first, nearest child first.  The open node: its
+    // level, corner and words (mask and first child; oriented box); the
+    // query's octant one level down; the squared gap to the low and the high
+    // child half on each axis (a child's box distance is then three selects
+    // and two adds); whether its children are cells of the skipped level; the
+    // bound, refreshed from the team's at every node, in the distance type
+    // and saturated (every distance of a packed-list grid is below 2^32 - 1,
+    // so "<=" keeps its meaning); its children within the bound at entry; the
+    // slots still to visit.
+    int l = -1;
+    uint32_t x0 = 0, y0 = 0, z0 = 0;
+    uint64_t w = 0, wo = 0;
+    uint32_t qol = 0;
+    Dist gxl = 0, gxh = 0, gyl = 0, gyh = 0, gzl = 0, gzh = 0;
+    bool touch = false;
+    Dist bnd = 0;
+    uint32_t near = 0, pm = 0;
+    // Work sharing within the team: lroot is the level this lane's walk
+    // climbs back to (l0, or the node it took over); bit L of open marks an
+    // ancestor at level L on its path that has children left after the one
+    // walked, bit L of given one whose remaining children another lane took
+    // over.
+    int lroot = -1;
+    uint32_t open = 0, given = 0;
+    enum { kQuery, kRound, kWalk, kDone };
+    int phase = kQuery;
+
+    // the query's octant at level l is digit l of its Morton key
+    auto qo = [&](int lv) __attribute__((always_inline)) -> uint32_t {
+        return (uint32_t)(qkey >> (3 * lv)) & 7u;
+    };
+    auto box_dist = [&](uint32_t x, uint32_t y, uint32_t z, int lv) __attribute__((always_inline)) -> Dist {
+        const uint32_t e = (1u << lv) - 1;
+        const Dist gx = axis_gap(qv.x, x, x + e), gy = axis_gap(qv.y, y, y + e),
+                   gz = axis_gap(qv.z, z, z + e);
+        return gx * gx + gy * gy + gz * gz;
+    };
+    // a voxel's position: in the key array, or through perm in the caller's
+    // LINEAR array (then ties go to the smaller LINEAR position, as there)
+    auto cand = [&](Dist d, int32_t i) __attribute__((always_inline)) -> Cand {
+        if (kCount) ++c_vox;
+        return LIST::make(d, perm ? (int32_t)perm[i] : i);
+    };
+    auto skipped = [&](uint32_t x, uint32_t y, uint32_t z, int lv) __attribute__((always_inline)) {
+        if (!skip || lv > sk_l) return false;
         x >>= sk_l;
         y >>= sk_l;
         z >>= sk_l;
         return x >= sk_x0 && x <= sk_x1 && y >= sk_y0 && y <= sk_y1 && z >= sk_z0 && z <= sk_z1;
     };
-    // Node (index within its level) of the level-l cell with corner (x, y, z),
-    // or -1 if empty; at l = 0 the key index of the voxel.
-    auto find_node = [&](uint32_t x, uint32_t y, uint32_t z, int l) __attribute__((always_inline)) -> int64_t {
+    // Node (index within its level) of the level-lv cell with corner (x, y,
+    // z), or -1 if empty; at lv = 0 the key index of the voxel.
+    auto find_node = [&](uint32_t x, uint32_t y, uint32_t z, int lv) __attribute__((always_inline)) -> int64_t {
         int L;
         int64_t nj;
-        if (dt > 0 && l <= dt) {
+        if (dt > 0 && lv <= dt) {
             const uint32_t v = dense[enc3(x >> dt, y >> dt, z >> dt, (uint32_t)dl, false)];
             if (kCount) ++c_dense;
             if (!v) return -1;
@@ -967,368 +1003,389 @@ void k_knn_tree(
             nj = 0;  // the root
             L = (int)depth;
         }
-        while (L > l) {
-            const uint64_t w = node[2 * (s_base[L] + nj)];
+        while (L > lv) {
+            const uint64_t nw = node[2 * (s_base[L] + nj)];
             if (kCount) ++c_node;
             --L;
             const uint32_t oc = (((x >> L) & 1u) << 2) | (((y >> L) & 1u) << 1) | ((z >> L) & 1u);
-            if (!((w >> oc) & 1u)) return -1;
-            nj = node_first(w) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
+            if (!((nw >> oc) & 1u)) return -1;
+            nj = node_first(nw) + __popc((uint32_t)nw & 0xFFu & ((1u << oc) - 1u));
         }
         return nj;
     };
+    auto to_dist = [](uint64_t b) __attribute__((always_inline)) -> Dist {
+        return b > (uint64_t)(Dist)~(Dist)0 ? (Dist)~(Dist)0 : (Dist)b;
+    };
+    // Entering the open node (level l, corner x0, words w, wo): its child
+    // gaps, the bound and the children within it.
+    auto enter = [&](bool fresh) __attribute__((always_inline)) {
+        const int cl = l - 1;
+        qol = qo(cl);
+        // gaps to the low half [0, h) and the high half [h, 2h) of the node
+        // along an axis, each cut to the node's voxel box [blo, bhi], from
+        // the query's signed offset t (every coordinate is below 2^21):
+        // max(a - t, t - b, 0) over the cut interval [a, b] (an empty cut has
+        // no child to visit)
+        const int32_t h = 1 << cl;
+        auto gaps = [&](int a, uint32_t qc, uint32_t c0, Dist &lo2, Dist &hi2) __attribute__((always_inline)) {
+            uint32_t blo, bhi;
+            node_box(w, a, l, blo, bhi);
+            const int32_t t = (int32_t)(qc - c0);
+            const int32_t la_ = (int32_t)blo, lb = min((int32_t)bhi, h - 1);
+            const int32_t ha = max((int32_t)blo, h), hb = min((int32_t)bhi, 2 * h - 1);
+            const int32_t gl = max(max(la_ - t, t - lb), 0), gh = max(max(ha - t, t - hb), 0);
+            lo2 = (Dist)gl * (Dist)gl;
+            hi2 = (Dist)gh * (Dist)gh;
+        };
+        gaps(0, qv.x, x0, gxl, gxh);
+        gaps(1, qv.y, y0, gyl, gyh);
+        gaps(2, qv.z, z0, gzl, gzh);
+        touch = skip && cl == sk_l;
+        bnd = to_dist(kth);
+        // children already beyond the bound never take a step
+        const Dist xl = gxl, xh = gxh;
+        const Dist q0 = xl + gyl, q1 = xl + gyh, q2 = xh + gyl, q3 = xh + gyh;
+        near = (q0 + gzl <= bnd ? 0x01u : 0u) | (q0 + gzh <= bnd ? 0x02u : 0u) |
+               (q1 + gzl <= bnd ? 0x04u : 0u) | (q1 + gzh <= bnd ? 0x08u : 0u) |
+               (q2 + gzl <= bnd ? 0x10u : 0u) | (q2 + gzh <= bnd ? 0x20u : 0u) |
+               (q3 + gzl <= bnd ? 0x40u : 0u) | (q3 + gzh <= bnd ? 0x80u : 0u);
+        // a node just loaded whose oriented box lies beyond the bound opens
+        // no child (rounded up, the bound only keeps more); tested from the
+        // second round on, when the query's own cell did not hold its
+        // neighbours (a query near the voxels, whose first round mostly
+        // settles it, would pay for the test and rarely gain)
+        if (fresh && near && !round0) {
+            const float hc = (float)((1u << l) - 1u) * 0.5f;
+            const float lb2 = obb_dist2(wo, l, (float)qv.x - ((float)x0 + hc),
+                                        (float)qv.y - ((float)y0 + hc), (float)qv.z - ((float)z0 + hc));
+            if (lb2 > (float)bnd * (1.f + 1.f / 1048576.f) + 1.f) near = 0;
+        }
+    };
 
-    const uint32_t top = (1u << depth) - 1;
-    bool round0 = true;
-    uint32_t r = 0;
-    int ls = la - 1;
     for (;;) {
-        // this lane's start cell: round 0 = one child of the query's level-la
-        // cell; later rounds = one of the level-ls cells covering the cube
-        // [q - r, q + r] (the query's own cell and, per axis where the cube
-        // crosses a cell border, the neighbour)
-        uint32_t c[3];
-        bool ok = true;
-        {
-            const uint32_t c3[3] = {qv.x, qv.y, qv.z};
-            if (round0) {
-                const uint32_t oc = near_order((uint32_t)tl) ^ qo(la - 1);
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    c[a] = ((c3[a] >> la) << la) | (((oc >> (2 - a)) & 1u) << (la - 1));
+        bool pend = false;  // this lane's voxel for the team's list, if any
+        Cand cv{};
+        // ---- next query of the team
+        if (phase == kQuery) {
+            if (slot >= nq) {
+                phase = kDone;
             } else {
-                const uint32_t m = near_order((uint32_t)tl);
+                if (qctr && tl == 0) nxt = atomicAdd(qctr, 1u);
+                j = order ? (int64_t)(order[slot] >> kOrderBits) : slot;  // query (and output row)
+                const bool finite = quantize3(q[3 * j], q[3 * j + 1], q[3 * j + 2], o, scale, depth, qv);
+                if (!finite && tl == 0) set_err(err, ERR_NONFINITE);
+                if (!finite || n == 0) {
+                    for (int s = tl; s < k; s += kTeam) {
+                        idx_out[j * k + s] = -1;
+                        d2_out[j * k + s] = ~0ull;
+                    }
+                    slot = next_slot();
+                } else {
+                    qkey = enc3(qv.x, qv.y, qv.z, depth, false);
+                    list.clear();
+                    kth = LIST::kNone;
+                    skip = false;
+                    round0 = true;
+                    r = 0;
+                    ls = la - 1;
+                    phase = kRound;
+                }
+            }
+        }
+        // ---- next round: this lane's start cell (round 0: one child of the
+        // query's level-la cell; later rounds: one of the level-ls cells
+        // covering the cube [q - r, q + r], the query's own cell and, per
+        // axis where the cube crosses a cell border, the neighbour)
+        if (phase == kRound) {
+            uint32_t c[3];
+            bool ok = tl < kCells;  // the team's lanes beyond the eight cells start idle
+            {
+                const uint32_t c3[3] = {qv.x, qv.y, qv.z};
+                if (round0) {
+                    const uint32_t oc = near_order((uint32_t)tl & 7u) ^ qo(la - 1);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        c[a] = ((c3[a] >> la) << la) | (((oc >> (2 - a)) & 1u) << (la - 1));
+                } else {
+                    const uint32_t m = near_order((uint32_t)tl & 7u);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const uint32_t lo = c3[a] > r ? c3[a] - r : 0;
+                        const uint32_t hi = (uint64_t)c3[a] + r < top ? c3[a] + r : top;
+                        const uint32_t own = c3[a] >> ls, clo = lo >> ls, chi = hi >> ls;
+                        if ((m >> (2 - a)) & 1u) {
+                            const uint32_t other = own == clo ? chi : clo;
+                            ok = ok && other != own;
+                            c[a] = other << ls;
+                        } else {
+                            c[a] = own << ls;
+                        }
+                    }
+                }
+            }
+            const int64_t cn = ok && !skipped(c[0], c[1], c[2], ls) ? find_node(c[0], c[1], c[2], ls) : -1;
+            // The start cells are shared out a child at a time: lane tl walks
+            // child near_order(tl) ^ (query octant) of every start cell in
+            // turn, so that the heaviest cell's work is spread over the team.
+            // Start cells at level 0 are voxels: each is offered by its lane.
+            l0 = ls - 1;
+            avail = 0;
+            if (ls == 0) {
+                if (cn >= 0) {
+                    const Dist d = box_dist(c[0], c[1], c[2], 0);
+                    if (d <= kth) {
+                        pend = true;
+                        cv = cand(d, (int32_t)cn);
+                    }
+                }
+            } else {
+                s_sw[tid] = cn >= 0 ? node[2 * (s_base[ls] + cn)] : 0ull;
+                if (kCount) c_node += cn >= 0 ? 1u : 0u;
+                s_sc[tid] = (uint64_t)c[0] | ((uint64_t)c[1] << 21) | ((uint64_t)c[2] << 42);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                qs = near_order((uint32_t)tl & 7u) ^ qo(l0);
+#pragma unroll
+                for (int m = 0; m < kCells; ++m) avail |= (uint32_t)((s_sw[team * kTeam + m] >> qs) & 1u) << m;
+                if (tl >= kCells) avail = 0;
+            }
+            l = l0;
+            lroot = l0;
+            pm = 0;
+            open = 0;
+            given = 0;
+            phase = kWalk;
+        }
+        // ---- one walk step: take over work, start this lane's next subtree,
+        // climb back to the parent (its slots up to the one just finished are
+        // done), or take the next child -- prune it, offer it (a voxel), or
+        // descend into it.  Taking over, starting, climbing and descending
+        // share one node-entry tail, so a wave whose lanes take different
+        // paths runs it once.
+        if (phase == kWalk) {
+            // A lane without work left takes the remaining children of the
+            // shallowest open ancestor of a lane that has one (the k-th idle
+            // lane of the team pairs with its k-th such lane).  A team's lanes
+            // move in step, so no atomics are needed.
+            bool recv = false;
+            int rsrc = 0, rl = 0;
+            uint32_t rx = 0, ry = 0, rz = 0;
+            {
+                const bool idle = pm == 0 && l == lroot && !avail;
+                const uint32_t ti = (uint32_t)(__ballot(idle) >> (kTeam * tw)) & tmask;
+                const uint32_t td = (uint32_t)(__ballot(open != 0) >> (kTeam * tw)) & tmask;
+                if (__ballot(ti != 0 && td != 0)) {
+                    const uint32_t below = (1u << tl) - 1u;
+                    const int np = min(__popc(ti), __popc(td));
+                    const int gl = open ? 31 - __builtin_clz(open) : 0;
+                    if (open && __popc(td & below) < np) {
+                        given |= 1u << gl;
+                        open &= ~(1u << gl);
+                    }
+                    const int ri = __popc(ti & below);
+                    uint32_t m = td;
+#pragma unroll
+                    for (int i = 0; i < kTeam - 1; ++i)
+                        if (i < ri) m &= m - 1u;
+                    rsrc = m ? __builtin_ctz(m) : tl;
+                    rl = __shfl(gl, tbase + rsrc, 64);
+                    rx = (uint32_t)__shfl((int)x0, tbase + rsrc, 64);
+                    ry = (uint32_t)__shfl((int)y0, tbase + rsrc, 64);
+                    rz = (uint32_t)__shfl((int)z0, tbase + rsrc, 64);
+                    recv = idle && ri < np;
+                }
+            }
+            const bool up = pm == 0;
+            bool moved = false, climbed = false;
+            uint32_t done_oc = 0;
+            if (recv) {
+                // enter the ancestor as if climbing back into it from the
+                // child the other lane is walking
+                l = rl;
+                lroot = rl;
+                done_oc = (((rx >> (l - 1)) & 1u) << 2) | (((ry >> (l - 1)) & 1u) << 1) | ((rz >> (l - 1)) & 1u);
+                const uint32_t clr = ~((1u << l) - 1u);
+                x0 = rx & clr;
+                y0 = ry & clr;
+                z0 = rz & clr;
+                w = s_word[(l - 1) * kKnnBlock + (tid - tl + rsrc)];
+                s_word[(l - 1) * kKnnBlock + tid] = w;
+                moved = climbed = true;
+            } else if (up && l == lroot && !avail) {
+                // nothing left: wait for a hand-over or the end of the round
+            } else if (up && l == lroot) {
+                if (kCount) ++c_step;
+                const int m = __builtin_ctz(avail);
+                avail &= avail - 1;
+                const uint64_t sw = s_sw[team * kTeam + m], sc = s_sc[team * kTeam + m];
+                const uint32_t cx = ((uint32_t)sc & 0x1FFFFFu) | (((qs >> 2) & 1u) << l0);
+                const uint32_t cy = ((uint32_t)(sc >> 21) & 0x1FFFFFu) | (((qs >> 1) & 1u) << l0);
+                const uint32_t cz = ((uint32_t)(sc >> 42) & 0x1FFFFFu) | ((qs & 1u) << l0);
+                const int32_t ci = (int32_t)node_first(sw) + __popc((uint32_t)sw & 0xFFu & ((1u << qs) - 1u));
+                const Dist bd = box_dist(cx, cy, cz, l0);
+                if (bd <= kth && !skipped(cx, cy, cz, l0)) {
+                    if (l0 == 0) {
+                        pend = true;
+                        cv = cand(bd, ci);
+                    } else {
+                        const u64x2 pr = *(const u64x2 *)(node + 2 * (s_base[l0] + ci));
+                        w = pr.x;
+                        wo = pr.y;
+                        if (kCount) ++c_node;
+                        s_word[(l0 - 1) * kKnnBlock + tid] = w;
+                        x0 = cx;
+                        y0 = cy;
+                        z0 = cz;
+                        moved = true;
+                    }
+                }
+            } else if (up) {
+                if (kCount) ++c_step;
+                done_oc = (((x0 >> l) & 1u) << 2) | (((y0 >> l) & 1u) << 1) | ((z0 >> l) & 1u);
+                ++l;
+                open &= ~(1u << l);
+                const uint32_t clr = ~((1u << l) - 1u);
+                x0 &= clr;
+                y0 &= clr;
+                z0 &= clr;
+                w = s_word[(l - 1) * kKnnBlock + tid];
+                moved = climbed = true;
+            } else {
+                if (kCount) ++c_step;
+                const uint32_t sl = __builtin_ctz(pm);
+                pm &= pm - 1;
+                const uint32_t oc = near_order(sl) ^ qol;
+                const Dist bd = ((oc & 4u) ? gxh : gxl) + ((oc & 2u) ? gyh : gyl) + ((oc & 1u) ? gzh : gzl);
+                const int cl = l - 1;
+                const uint32_t cx = x0 | (((oc >> 2) & 1u) << cl), cy = y0 | (((oc >> 1) & 1u) << cl),
+                               cz = z0 | ((oc & 1u) << cl);
+                if (bd <= bnd && !(touch && skipped(cx, cy, cz, cl))) {
+                    const int32_t ci = (int32_t)node_first(w) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
+                    if (cl == 0) {
+                        pend = true;
+                        cv = cand(bd, ci);
+                    } else {
+                        const u64x2 pr = *(const u64x2 *)(node + 2 * (s_base[cl] + ci));
+                        w = pr.x;
+                        wo = pr.y;
+                        if (kCount) ++c_node;
+                        s_word[(cl - 1) * kKnnBlock + tid] = w;
+                        if (pm) open |= 1u << l;
+                        l = cl;
+                        x0 = cx;
+                        y0 = cy;
+                        z0 = cz;
+                        moved = true;
+                    }
+                }
+            }
+            if (moved) {
+                enter(!climbed);
+                const uint32_t done_slots = climbed ? (2u << near_order(done_oc ^ qol)) - 1u : 0u;
+                pm = slot_mask((uint32_t)w & near, qol) & ~done_slots;
+                if (climbed && ((given >> l) & 1u)) {  // its remaining children went to another lane
+                    pm = 0;
+                    given &= ~(1u << l);
+                }
+            }
+        }
+        // ---- the team's list takes what its lanes offered, one lane after
+        // another; the team's k-th distance follows (every lane of a team is
+        // active here)
+        {
+            const uint64_t b = __ballot(pend);
+            if (b) {
+                uint32_t tm = (uint32_t)(b >> (kTeam * tw)) & tmask;
+                while (tm) {
+                    const int src = __builtin_ctz(tm);
+                    tm &= tm - 1;
+                    list.insert(LIST::bcast(cv, tbase + src), tl);
+                }
+                kth = list.kth(k, tbase);
+                bnd = kth < (uint64_t)bnd ? to_dist(kth) : bnd;
+            }
+        }
+        // ---- end of a round: every lane of a walking team is out of work
+        const bool busy = phase == kWalk && !(pm == 0 && l == lroot && !avail);
+        if (phase == kWalk && !((uint32_t)(__ballot(busy) >> (kTeam * tw)) & tmask)) {
+            // Exact once every voxel within the k-th distance lies in the
+            // region searched so far: the pruning only ever used k-th
+            // distances of real candidates, so no voxel of that ball inside
+            // the region was missed.
+            bool done;
+            if (round0) {
+                // every voxel outside the level-la cell is at least m away
+                const uint32_t c3[3] = {qv.x, qv.y, qv.z};
+                uint64_t m = ~0ull;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    const uint32_t lo = c3[a] > r ? c3[a] - r : 0;
-                    const uint32_t hi = (uint64_t)c3[a] + r < top ? c3[a] + r : top;
-                    const uint32_t own = c3[a] >> ls, clo = lo >> ls, chi = hi >> ls;
-                    if ((m >> (2 - a)) & 1u) {
-                        const uint32_t other = own == clo ? chi : clo;
-                        ok = ok && other != own;
-                        c[a] = other << ls;
-                    } else {
-                        c[a] = own << ls;
-                    }
+                    const uint32_t b = (c3[a] >> la) << la;
+                    const uint64_t below = (uint64_t)(c3[a] - b) + 1, above = (uint64_t)b + (1u << la) - c3[a];
+                    if (b > 0 && below < m) m = below;
+                    if ((uint64_t)b + (1u << la) <= top && above < m) m = above;
                 }
+                done = m == ~0ull || (kth != LIST::kNone && m * m > kth);
+            } else {
+                done = (kth != LIST::kNone && isqrt64(kth) <= r) || ls == (int)depth;
             }
-        }
-        const int64_t cn = ok && !skipped(c[0], c[1], c[2], ls) ? find_node(c[0], c[1], c[2], ls) : -1;
-        // The start cells are shared out a child at a time: lane tl walks
-        // child near_order(tl) ^ (query octant) of every start cell in turn,
-        // so that the heaviest cell's work is spread over the whole team.
-        // Start cells at level 0 are voxels: each is offered by its lane.
-        const int l0 = ls - 1;  // level of the walked subtrees
-        uint32_t avail = 0;     // start cells that have this lane's child
-        uint32_t qs = 0;
-        if (ls == 0) {
-            bool pend = false;
-            Cand cv{};
-            if (cn >= 0) {
-                const Dist d = box_dist(c[0], c[1], c[2], 0);
-                if (d <= kth) {
-                    pend = true;
-                    cv = cand(d, (int32_t)cn);
-                }
-            }
-            team_offer(pend, cv);
-        } else {
-            s_sw[tid] = cn >= 0 ? node[2 * (s_base[ls] + cn)] : 0ull;
-            if (kCount) c_node += cn >= 0 ? 1u : 0u;
-            s_sc[tid] = (uint64_t)c[0] | ((uint64_t)c[1] << 21) | ((uint64_t)c[2] << 42);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            qs = near_order((uint32_t)tl) ^ qo(l0);
+            if (done) {
 #pragma unroll
-            for (int m = 0; m < kTeam; ++m) avail |= (uint32_t)((s_sw[team * kTeam + m] >> qs) & 1u) << m;
-        }
-        if (ls != 0) {
-            // depth-first walk of each subtree, nearest child first (a lane
-            // whose walks are over stays in the loop for its team's
-            // insertions until every lane of the wave is done)
-            int l = l0;
-            uint32_t x0 = 0, y0 = 0, z0 = 0;
-            uint64_t w = 0, wo = 0;  // the open node's words: mask and first child; oriented box
-            // Per open node: the query's octant one level down, the squared
-            // gap to the low and the high child half on each axis (a child's
-            // box distance is then three selects and two adds), whether its
-            // children are cells of the skipped level, and the bound,
-            // refreshed from the team's at every node.
-            uint32_t qol = 0;
-            Dist gxl = 0, gxh = 0, gyl = 0, gyh = 0, gzl = 0, gzh = 0;
-            bool touch = false;
-            // the bound in the distance type, saturated (every distance of a
-            // packed-list grid is below 2^32 - 1, so "<=" keeps its meaning)
-            Dist bnd = 0;
-            auto to_dist = [](uint64_t b) __attribute__((always_inline)) -> Dist {
-                return b > (uint64_t)(Dist)~(Dist)0 ? (Dist)~(Dist)0 : (Dist)b;
-            };
-            uint32_t near = 0;  // children (by octant) within the bound at entry
-            auto enter = [&](bool fresh) __attribute__((always_inline)) {
-                const int cl = l - 1;
-                qol = qo(cl);
-                // gaps to the low half [0, h) and the high half [h, 2h) of the
-                // node along an axis, each cut to the node's voxel box
-                // [blo, bhi], from the query's signed offset t (every
-                // coordinate is below 2^21): max(a - t, t - b, 0) over the
-                // cut interval [a, b] (an empty cut has no child to visit)
-                const int32_t h = 1 << cl;
-                auto gaps = [&](int a, uint32_t q, uint32_t c0, Dist &lo2, Dist &hi2) __attribute__((always_inline)) {
-                    uint32_t blo, bhi;
-                    node_box(w, a, l, blo, bhi);
-                    const int32_t t = (int32_t)(q - c0);
-                    const int32_t la_ = (int32_t)blo, lb = min((int32_t)bhi, h - 1);
-                    const int32_t ha = max((int32_t)blo, h), hb = min((int32_t)bhi, 2 * h - 1);
-                    const int32_t gl = max(max(la_ - t, t - lb), 0), gh = max(max(ha - t, t - hb), 0);
-                    lo2 = (Dist)gl * (Dist)gl;
-                    hi2 = (Dist)gh * (Dist)gh;
-                };
-                gaps(0, qv.x, x0, gxl, gxh);
-                gaps(1, qv.y, y0, gyl, gyh);
-                gaps(2, qv.z, z0, gzl, gzh);
-                touch = skip && cl == sk_l;
-                bnd = to_dist(kth);
-                // children already beyond the bound never take a step
-                const Dist xl = gxl, xh = gxh;
-                const Dist q0 = xl + gyl, q1 = xl + gyh, q2 = xh + gyl, q3 = xh + gyh;
-                near = (q0 + gzl <= bnd ? 0x01u : 0u) | (q0 + gzh <= bnd ? 0x02u : 0u) |
-                       (q1 + gzl <= bnd ? 0x04u : 0u) | (q1 + gzh <= bnd ? 0x08u : 0u) |
-                       (q2 + gzl <= bnd ? 0x10u : 0u) | (q2 + gzh <= bnd ? 0x20u : 0u) |
-                       (q3 + gzl <= bnd ? 0x40u : 0u) | (q3 + gzh <= bnd ? 0x80u : 0u);
-                // a node just loaded whose oriented box lies beyond the bound
-                // opens no child (rounded up, the bound only keeps more);
-                // tested from the second round on, when the query's own
-                // cell did not hold its neighbours (a query near the voxels,
-                // whose first round mostly settles it, would pay for the
-                // test and rarely gain)
-                if (fresh && near && !round0) {
-                    const float hc = (float)((1u << l) - 1u) * 0.5f;
-                    const float lb2 = obb_dist2(wo, l, (float)qv.x - ((float)x0 + hc),
-                                                (float)qv.y - ((float)y0 + hc), (float)qv.z - ((float)z0 + hc));
-                    if (lb2 > (float)bnd * (1.f + 1.f / 1048576.f) + 1.f) near = 0;
-                }
-            };
-            uint32_t pm = 0;
-            bool fin = false;
-            // Work sharing within the team: lroot is the level this lane's
-            // walk climbs back to (l0, or the node it took over); bit L of
-            // open marks an ancestor at level L on its path that has children
-            // left after the one walked, bit L of given one whose remaining
-            // children another lane took over.
-            int lroot = l0;
-            uint32_t open = 0, given = 0;
-            // One iteration: take over work, start this lane's next subtree,
-            // climb back to the parent (its slots up to the one just finished
-            // are done), or take the next child -- prune it, offer it (a
-            // voxel), or descend into it; then the team inserts what its
-            // lanes offered.  Taking over, starting, climbing and descending
-            // share one node-entry tail, so a wave whose lanes take different
-            // paths runs it once.
-            for (;;) {
-                // A lane without work left takes the remaining children of the
-                // shallowest open ancestor of a lane that has one (the k-th
-                // idle lane of the team pairs with its k-th such lane).  A
-                // team's lanes move in step, so no atomics are needed.
-                bool recv = false;
-                int rsrc = 0;
-                uint32_t rx = 0, ry = 0, rz = 0;
-                int rl = 0;
-                {
-                    const bool idle = pm == 0 && l == lroot && !avail;
-                    const uint32_t ti = (uint32_t)(__ballot(idle) >> (kTeam * tw)) & 0xFFu;
-                    const uint32_t td = (uint32_t)(__ballot(open != 0) >> (kTeam * tw)) & 0xFFu;
-                    if (__ballot(ti != 0 && td != 0)) {
-                        const uint32_t below = (1u << tl) - 1u;
-                        const int np = min(__popc(ti), __popc(td));
-                        const int dl = open ? 31 - __builtin_clz(open) : 0;
-                        if (open && __popc(td & below) < np) {
-                            given |= 1u << dl;
-                            open &= ~(1u << dl);
-                        }
-                        const int ri = __popc(ti & below);
-                        uint32_t m = td;
-#pragma unroll
-                        for (int i = 0; i < kTeam - 1; ++i)
-                            if (i < ri) m &= m - 1u;
-                        rsrc = m ? __builtin_ctz(m) : tl;
-                        rl = __shfl(dl, tbase + rsrc, 64);
-                        rx = (uint32_t)__shfl((int)x0, tbase + rsrc, 64);
-                        ry = (uint32_t)__shfl((int)y0, tbase + rsrc, 64);
-                        rz = (uint32_t)__shfl((int)z0, tbase + rsrc, 64);
-                        recv = idle && ri < np;
+                for (int s = 0; s < LIST::E; ++s) {
+                    const int pos = tl * LIST::E + s;
+                    if (pos < k) {
+                        int64_t idx;
+                        uint64_t d2;
+                        list.out(s, idx, d2);
+                        idx_out[j * k + pos] = idx;
+                        d2_out[j * k + pos] = d2;
                     }
                 }
-                bool pend = false;
-                Cand cv{};
-                const bool up = pm == 0;
-                bool moved = false, climbed = false;
-                uint32_t done_oc = 0;
-                if (recv) {
-                    // enter the ancestor as if climbing back into it from the
-                    // child the other lane is walking
-                    l = rl;
-                    lroot = rl;
-                    done_oc = (((rx >> (l - 1)) & 1u) << 2) | (((ry >> (l - 1)) & 1u) << 1) | ((rz >> (l - 1)) & 1u);
-                    const uint32_t clr = ~((1u << l) - 1u);
-                    x0 = rx & clr;
-                    y0 = ry & clr;
-                    z0 = rz & clr;
-                    w = s_word[l * kKnnBlock + (tid - tl + rsrc)];
-                    s_word[l * kKnnBlock + tid] = w;
-                    fin = false;
-                    moved = climbed = true;
-                } else if (fin) {
-                } else if (up && l == lroot && !avail) {
-                    fin = true;
-                } else if (up && l == lroot) {
-                    if (kCount) ++c_step;
-                    const int m = __builtin_ctz(avail);
-                    avail &= avail - 1;
-                    const uint64_t sw = s_sw[team * kTeam + m], sc = s_sc[team * kTeam + m];
-                    const uint32_t cx = ((uint32_t)sc & 0x1FFFFFu) | (((qs >> 2) & 1u) << l0);
-                    const uint32_t cy = ((uint32_t)(sc >> 21) & 0x1FFFFFu) | (((qs >> 1) & 1u) << l0);
-                    const uint32_t cz = ((uint32_t)(sc >> 42) & 0x1FFFFFu) | ((qs & 1u) << l0);
-                    const int32_t ci = (int32_t)node_first(sw) + __popc((uint32_t)sw & 0xFFu & ((1u << qs) - 1u));
-                    const Dist bd = box_dist(cx, cy, cz, l0);
-                    if (bd <= kth && !skipped(cx, cy, cz, l0)) {
-                        if (l0 == 0) {
-                            pend = true;
-                            cv = cand(bd, ci);
-                        } else {
-                            const u64x2 pr = *(const u64x2 *)(node + 2 * (s_base[l0] + ci));
-                            w = pr.x;
-                            wo = pr.y;
-                            if (kCount) ++c_node;
-                            s_word[l0 * kKnnBlock + tid] = w;
-                            x0 = cx;
-                            y0 = cy;
-                            z0 = cz;
-                            moved = true;
-                        }
-                    }
-                } else if (up) {
-                    if (kCount) ++c_step;
-                    done_oc = (((x0 >> l) & 1u) << 2) | (((y0 >> l) & 1u) << 1) | ((z0 >> l) & 1u);
-                    ++l;
-                    open &= ~(1u << l);
-                    const uint32_t clr = ~((1u << l) - 1u);
-                    x0 &= clr;
-                    y0 &= clr;
-                    z0 &= clr;
-                    w = s_word[l * kKnnBlock + tid];
-                    moved = climbed = true;
+                slot = next_slot();
+                phase = kQuery;
+            } else {
+                // the region just searched is skipped from now on
+                skip = true;
+                if (round0) {
+                    sk_l = la;
+                    sk_x0 = sk_x1 = qv.x >> la;
+                    sk_y0 = sk_y1 = qv.y >> la;
+                    sk_z0 = sk_z1 = qv.z >> la;
                 } else {
-                    if (kCount) ++c_step;
-                    const uint32_t sl = __builtin_ctz(pm);
-                    pm &= pm - 1;
-                    const uint32_t oc = near_order(sl) ^ qol;
-                    const Dist bd = ((oc & 4u) ? gxh : gxl) + ((oc & 2u) ? gyh : gyl) + ((oc & 1u) ? gzh : gzl);
-                    const int cl = l - 1;
-                    const uint32_t cx = x0 | (((oc >> 2) & 1u) << cl), cy = y0 | (((oc >> 1) & 1u) << cl),
-                                   cz = z0 | ((oc & 1u) << cl);
-                    if (bd <= bnd && !(touch && skipped(cx, cy, cz, cl))) {
-                        const int32_t ci = (int32_t)node_first(w) + __popc((uint32_t)w & 0xFFu & ((1u << oc) - 1u));
-                        if (cl == 0) {
-                            pend = true;
-                            cv = cand(bd, ci);
-                        } else {
-                            const u64x2 pr = *(const u64x2 *)(node + 2 * (s_base[cl] + ci));
-                            w = pr.x;
-                            wo = pr.y;
-                            if (kCount) ++c_node;
-                            s_word[cl * kKnnBlock + tid] = w;
-                            if (pm) open |= 1u << l;
-                            l = cl;
-                            x0 = cx;
-                            y0 = cy;
-                            z0 = cz;
-                            moved = true;
-                        }
-                    }
+                    sk_l = ls;
+                    sk_x0 = (qv.x > r ? qv.x - r : 0) >> ls;
+                    sk_y0 = (qv.y > r ? qv.y - r : 0) >> ls;
+                    sk_z0 = (qv.z > r ? qv.z - r : 0) >> ls;
+                    sk_x1 = ((uint64_t)qv.x + r < top ? qv.x + r : top) >> ls;
+                    sk_y1 = ((uint64_t)qv.y + r < top ? qv.y + r : top) >> ls;
+                    sk_z1 = ((uint64_t)qv.z + r < top ? qv.z + r : top) >> ls;
                 }
-                if (moved) {
-                    enter(!climbed);
-                    const uint32_t done_slots = climbed ? (2u << near_order(done_oc ^ qol)) - 1u : 0u;
-                    pm = slot_mask((uint32_t)w & near, qol) & ~done_slots;
-                    if (climbed && ((given >> l) & 1u)) {  // its remaining children went to another lane
-                        pm = 0;
-                        given &= ~(1u << l);
-                    }
-                }
-                team_offer(pend, cv);
-                bnd = kth < (uint64_t)bnd ? to_dist(kth) : bnd;
-                if (!__ballot(!fin)) break;
+                const uint64_t bound = kth;
+                // next cube: the k-th distance ball, or a grown cube while
+                // fewer than k candidates are known (from round 0 at least one
+                // level-la cell wide, so that the next region contains the la
+                // cell)
+                if (bound != LIST::kNone) r = isqrt64(bound);
+                else if (round0) r = ((1u << la) - 1) / 2 > 1 ? ((1u << la) - 1) / 2 : 1;
+                else r = 2 * r + 1;
+                if (r > top) r = top;
+                ls = 0;
+                while (ls < (int)depth && (1u << ls) < 2 * r + 1) ++ls;
+                round0 = false;
+                phase = kRound;
             }
         }
-        // Exact once every voxel within the k-th distance lies in the region
-        // searched so far: the pruning only ever used k-th distances of real
-        // candidates, so no voxel of that ball inside the region was missed.
-        bool done;
-        if (round0) {
-            // every voxel outside the level-la cell is at least m away
-            const uint32_t c3[3] = {qv.x, qv.y, qv.z};
-            uint64_t m = ~0ull;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const uint32_t b = (c3[a] >> la) << la;
-                const uint64_t below = (uint64_t)(c3[a] - b) + 1, above = (uint64_t)b + (1u << la) - c3[a];
-                if (b > 0 && below < m) m = below;
-                if ((uint64_t)b + (1u << la) <= top && above < m) m = above;
-            }
-            done = m == ~0ull || (kth != LIST::kNone && m * m > kth);
-        } else {
-            done = (kth != LIST::kNone && isqrt64(kth) <= r) || ls == (int)depth;
-        }
-        if (done) break;
-        // the region just searched is skipped from now on
-        skip = true;
-        if (round0) {
-            sk_l = la;
-            sk_x0 = sk_x1 = qv.x >> la;
-            sk_y0 = sk_y1 = qv.y >> la;
-            sk_z0 = sk_z1 = qv.z >> la;
-        } else {
-            sk_l = ls;
-            sk_x0 = (qv.x > r ? qv.x - r : 0) >> ls;
-            sk_y0 = (qv.y > r ? qv.y - r : 0) >> ls;
-            sk_z0 = (qv.z > r ? qv.z - r : 0) >> ls;
-            sk_x1 = ((uint64_t)qv.x + r < top ? qv.x + r : top) >> ls;
-            sk_y1 = ((uint64_t)qv.y + r < top ? qv.y + r : top) >> ls;
-            sk_z1 = ((uint64_t)qv.z + r < top ? qv.z + r : top) >> ls;
-        }
-        const uint64_t bound = kth;
-        // next cube: the k-th distance ball, or a grown cube while fewer than
-        // k candidates are known (from round 0 at least one level-la cell
-        // wide, so that the next region contains the la cell)
-        if (bound != LIST::kNone) r = isqrt64(bound);
-        else if (round0) r = ((1u << la) - 1) / 2 > 1 ? ((1u << la) - 1) / 2 : 1;
-        else r = 2 * r + 1;
-        if (r > top) r = top;
-        ls = 0;
-        while (ls < (int)depth && (1u << ls) < 2 * r + 1) ++ls;
-        round0 = false;
+        if (!__ballot(phase != kDone)) break;
     }
+    if (kCount) {  // the team's sums, one atomic per counter per team
 #pragma unroll
-    for (int s = 0; s < LIST::E; ++s) {
-        const int pos = tl * LIST::E + s;
-        if (pos < k) {
-            int64_t idx;
-            uint64_t d2;
-            list.out(s, idx, d2);
-            idx_out[j * k + pos] = idx;
-            d2_out[j * k + pos] = d2;
+        for (int o2 = 1; o2 < kTeam; o2 <<= 1) {
+            c_node += __shfl_xor(c_node, o2, 64);
+            c_dense += __shfl_xor(c_dense, o2, 64);
+            c_vox += __shfl_xor(c_vox, o2, 64);
+            c_step += __shfl_xor(c_step, o2, 64);
         }
-    }
-    if (kCount) {  // the team's sums, one atomic per counter per query
-#pragma unroll
-        for (int o = 1; o < kTeam; o <<= 1) {
-            c_node += __shfl_xor(c_node, o, 64);
-            c_dense += __shfl_xor(c_dense, o, 64);
-            c_vox += __shfl_xor(c_vox, o, 64);
-            c_step += __shfl_xor(c_step, o, 64);
-        }
-        if (tl == 0) {
+        if (tl == 0 && (c_node | c_dense | c_vox | c_step)) {
             atomicAdd(&work[0], (unsigned long long)c_node);
             atomicAdd(&work[1], (unsigned long long)c_dense);
             atomicAdd(&work[2], (unsigned long long)c_vox);
@@ -1390,6 +1447,14 @@ static int knn_la(uint32_t depth) {
 static bool knn_order(int64_t nq) {
     if (const char *e = getenv("CGA_KNN_ORDER")) return atoi(e) != 0 && nq > 0;
     return nq >= kOrderMin;
+}
+
+// Launch knob (never changes results): CGA_KNN_QUEUE = 1 / 0 forces the
+// search's query counter on / off; by default it is on from
+// kKnnQueuePerTeam queries per resident team.
+static int knn_queue_knob() {
+    if (const char *e = getenv("CGA_KNN_QUEUE")) return atoi(e) != 0 ? 1 : 0;
+    return -1;
 }
 
 // Upper bound on the number of octree nodes of n unique keys: level L has at
@@ -1505,21 +1570,63 @@ static void tree_build(const KnnLayout &L, const K *keys, int64_t n, const int64
     }
 }
 
+// Blocks of the search kernel resident on the whole GPU at once (occupancy
+// per CU times the CU count; no cap if the runtime cannot say), cached per
+// kernel, LDS size and device.
+template <int KT>
+static int64_t knn_resident_blocks(bool packed, bool counting, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<bool, bool, size_t, int>, int64_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return INT64_MAX;
+    std::lock_guard<std::mutex> lk(mu);
+    const auto key = std::make_tuple(packed, counting, lds, dev);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    hipError_t e;
+    if (packed)
+        e = counting ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_knn_tree<KT, PackedList<KT>, true>, kKnnBlock, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_knn_tree<KT, PackedList<KT>, false>, kKnnBlock, lds);
+    else
+        e = counting ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_knn_tree<KT, WideList<KT>, true>, kKnnBlock, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_knn_tree<KT, WideList<KT>, false>, kKnnBlock, lds);
+    if (e != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        per_cu = cus = 0;
+    const int64_t b = (int64_t)per_cu * cus;
+    cache[key] = b > 0 ? b : INT64_MAX;
+    return cache[key];
+}
+
 template <int KT, bool kCount = false>
 static void knn_launch(const cga_grid *g, const KnnLayout &L, const float *q, int64_t nq, int k,
                        int64_t *idx, uint64_t *d2, hipStream_t s,
                        unsigned long long *work = nullptr) {
     CGA_PROF(kCount ? "knn_count" : "knn", s);
-    const size_t lds = (size_t)(g->depth + 1) * kKnnBlock * sizeof(uint64_t);
-    const unsigned blocks = (unsigned)((nq + kTeamsPerBlock - 1) / kTeamsPerBlock);
+    const size_t lds = (size_t)(g->depth > 1 ? g->depth - 1 : 1) * kKnnBlock * sizeof(uint64_t);
+    // as many blocks as the GPU holds at once (each team then takes its
+    // queries round-robin), fewer for small query sets
+    const int64_t want = (nq + kTeamsPerBlock - 1) / kTeamsPerBlock;
+    const int64_t cap = knn_resident_blocks<KT>(g->depth <= kPackedDepth, kCount, lds);
+    const unsigned blocks = (unsigned)(want < cap ? want : cap);
+    // Teams take their queries from a counter (zeroed with the control block
+    // at the call's start) when each has many to take: a slow query then
+    // holds up only its own team.  With few queries per team the counter's
+    // atomics would contend (c2: 100k queries, 1.21 against 0.80 ms), and
+    // each team takes every grid-stride'th query.  The counter's 32 bits must
+    // not wrap.
+    const int64_t teams = (int64_t)blocks * kTeamsPerBlock;
+    const int knob = knn_queue_knob();
+    const bool queue = knob >= 0 ? knob == 1 : nq >= kKnnQueuePerTeam * teams;
+    uint32_t *qctr = queue && nq < (int64_t)UINT32_MAX - teams ? &L.ctl->tile_ctr[kKnnQueryCtr] : nullptr;
     if (g->depth <= kPackedDepth)
         k_knn_tree<KT, PackedList<KT>, kCount><<<blocks, kKnnBlock, lds, s>>>(
             L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
-            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, L.perm, work);
+            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, qctr, L.perm, work);
     else
         k_knn_tree<KT, WideList<KT>, kCount><<<blocks, kKnnBlock, lds, s>>>(
             L.node, L.dense, L.lvl, L.nodes, q, nq, L.ob, g->origin[0], g->origin[1], g->origin[2],
-            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, L.perm, work);
+            g->scale, g->depth, L.dl, k, knn_la(g->depth), idx, d2, &L.ctl->err, qctr, L.perm, work);
 }
 
 template <bool kCount>

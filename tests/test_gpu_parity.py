@@ -401,6 +401,41 @@ def test_knn_query_order(gpu, w_c2s, monkeypatch, k):
     assert e.value.status == gpu.ENONFINITE
 
 
+@pytest.mark.parametrize("k", [1, 8, 16, 32])
+@pytest.mark.parametrize("ordered", ["0", "1"])
+def test_knn_query_queue(gpu, w_c2s, monkeypatch, k, ordered):
+    """Teams taking their queries from the counter (on by default from 8
+    queries per resident team, forced here at small sizes, with and without
+    the Morton ordering) leave every row where it belongs: ties, a ragged
+    query count, wide lists, a non-finite query, and the counting build."""
+    monkeypatch.setenv("CGA_KNN_QUEUE", "1")
+    monkeypatch.setenv("CGA_KNN_ORDER", ordered)
+    g = w_c2s["grid"]
+    ka, _ = gpu.cga_build(dev(w_c2s["a"]), g)
+    say("knn queue c2s", k, ordered)
+    _check_knn(gpu, ka, w_c2s["q"], g, k)
+    idx, d2, work = gpu.cga_knn_count(ka, dev(w_c2s["q"]), g, k)
+    widx, wd2 = oracle.knn_kdtree(u64(ka), w_c2s["q"], g, k)
+    np.testing.assert_array_equal(d2.cpu().numpy().view(np.uint64), wd2)
+    np.testing.assert_array_equal(idx.cpu().numpy(), widx)
+    assert work["node_loads"] > 0 and work["steps"] > 0
+    rng = np.random.default_rng(31)
+    g5 = Grid((0.0, 0.0, 0.0), 1.0, 5, M)
+    pts = rng.integers(0, 32, (300, 3)).astype(np.float32)
+    k5, _ = gpu.cga_build(dev(pts), g5)
+    q = rng.integers(-3, 35, (4097, 3)).astype(np.float32)
+    _check_knn(gpu, k5, q, g5, k, tier="brute")
+    _check_knn(gpu, k5, q[:1], g5, k, tier="brute")
+    g21 = Grid((0.0, 0.0, 0.0), float(2 ** 21), 21, M)
+    k21, _ = gpu.cga_build(dev(rng.uniform(0, 1, (20_000, 3)).astype(np.float32)), g21)
+    _check_knn(gpu, k21, rng.uniform(0, 1, (3000, 3)).astype(np.float32), g21, k)
+    bad = q[:100].copy()
+    bad[57, 2] = np.nan
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_knn(k5, dev(bad), g5, k)
+    assert e.value.status == gpu.ENONFINITE
+
+
 def test_knn_query_order_auto(gpu, w_c2s):
     """At 2^18 queries the ordering switches on by itself; the rows equal
     those of the unordered search on the same queries."""
