@@ -1088,6 +1088,9 @@ def main():
                 "peak": round(VALU_PEAK_GINST, 1), "unit": "G wave64 VALU inst/s",
                 "frac": round(gi / VALU_PEAK_GINST, 4),
                 "valu_insts_per_launch": sq["valu_insts_per_launch"],
+                "peak_model": "256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU "
+                              "instruction; instructions that issue in fewer cycles take "
+                              "the fraction above 1",
                 "source": "profiles/knn_%s_sq.json" % args.workload}
 
     by_kernel = {}

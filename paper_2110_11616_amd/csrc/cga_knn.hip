@@ -24,18 +24,19 @@
 // costs no more than the keys themselves) to its node, so a search enters the
 // tree near the bottom instead of at the root.
 //
-// Queries: a team of 8 lanes answers one query.  Round 0 searches the
-// query's level-LA cell: lane t walks child t (in visiting order) of each of
-// the cell's eight children, depth-first, nearest child first, pruning cells
-// whose nearest point is strictly farther than the team's current k-th
-// distance (kept in LDS, so ties survive); dealing out grandchildren rather
-// than children spreads the work of the query's own, busiest part of the cell
-// over the team.  The lanes' candidate lists, ordered by (squared distance,
-// key index), are then merged by a butterfly of bitonic merges.  If the
-// k-th distance ball is not inside the searched cell, the next round searches
-// the up to 8 cells of the smallest level that cover the ball's bounding cube
-// (their children dealt out the same way), and repeats with the grown ball
-// until a round that started from a known bound covers it.
+// Queries: a team of 8 lanes answers one query at a time.  Round 0 searches
+// the query's level-LA cell: lane t walks child t (in visiting order) of each
+// of the cell's eight children, depth-first, nearest child first, pruning
+// cells whose nearest point is strictly farther than the team's current k-th
+// distance (so ties survive); a lane whose walks are over takes over the
+// remaining children of a busy lane's shallowest open node.  The team keeps
+// one candidate list, ordered by (squared distance, key index), spread over
+// its lanes.  If the k-th distance ball is not inside the searched cell, the
+// next round searches the up to 8 cells of the smallest level that cover the
+// ball's bounding cube (their children dealt out the same way), and repeats
+// with the grown ball until a round that started from a known bound covers
+// it.  The teams of a wave do not wait for each other: each goes on with its
+// next round or query.
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -47,13 +48,15 @@
 namespace cga {
 
 constexpr int kKnnBlock = 256;
-#ifndef CGA_KNN_TEAM
-#define CGA_KNN_TEAM 8
-#endif
-constexpr int kTeam = CGA_KNN_TEAM;  // lanes per query
-constexpr int kCells = 8;            // start cells of a round, children of a node
-static_assert(kTeam >= kCells && kTeam <= 32 && (kTeam & (kTeam - 1)) == 0, "team size");
-constexpr int kTeamsPerBlock = kKnnBlock / kTeam;
+constexpr int kCells = 8;  // start cells of a round, children of a node
+// Lanes per query: 16 from k = 9 on (more work per query to share out: 1M
+// queries, k = 16, over 2 x 10M sphere points at depth 14, 59.6 against
+// 63.1 ms), else 8 (100k queries, k = 8, over 2 x 1M LiDAR points at depth
+// 12: 0.81 against 1.04 ms with 16).
+template <int KT>
+constexpr int knn_team() {
+    return KT >= 16 ? 16 : 8;
+}
 constexpr int kMaxDepth = 21;
 constexpr int kTreeRows = 4;                       // rows of 256 keys per build tile
 constexpr int kTreeTile = kTreeRows * 256;         // keys per build tile
@@ -733,7 +736,7 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Candidate lists of one query, shared by its team of kTeam lanes: ascending
+// Candidate lists of one query, shared by its team of knn_team<KT>() lanes: ascending
 // in (squared distance, key index) over the team, lane t holding positions
 // t*E .. t*E + E - 1 in registers (every array below is indexed only inside
 // unrolled loops).  A candidate offered by one lane is sent to the whole team
@@ -747,6 +750,7 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
 template <int KT>
 struct PackedList {
     using Dist = uint32_t;
+    static constexpr int kTeam = knn_team<KT>();
     static constexpr int E = KT >= kTeam ? KT / kTeam : 1;  // entries per lane
     static constexpr uint64_t kNone = ~0ull;  // bound meaning "no k-th candidate yet"
     struct Cand {
@@ -798,6 +802,7 @@ struct PackedList {
 template <int KT>
 struct WideList {
     using Dist = uint64_t;
+    static constexpr int kTeam = knn_team<KT>();
     static constexpr int E = KT >= kTeam ? KT / kTeam : 1;
     static constexpr uint64_t kNone = ~0ull;
     struct Cand {
@@ -874,7 +879,7 @@ constexpr int knn_waves_per_eu() {
     return (KT <= 8 && sizeof(typename LIST::Dist) == 4) ? 5 : 1;
 }
 
-// One query at a time per team of kTeam lanes: each team's first query by
+// One query at a time per team of kTeam = knn_team<KT>() lanes: each team's first query by
 // its place in the grid, the next ones from a counter (qctr, zero at launch;
 // without it, round-robin over the grid).  LIST is
 // PackedList (depth <= 15) or WideList.  The kernel is one loop whose every
@@ -902,6 +907,8 @@ void k_knn_tree(
     extern __shared__ uint64_t s_word[];
     __shared__ uint64_t s_sw[kKnnBlock], s_sc[kKnnBlock];  // start cells of the round: word, corner
     __shared__ int64_t s_base[kMaxDepth + 1];
+    constexpr int kTeam = knn_team<KT>(), kTeamsPerBlock = kKnnBlock / kTeam;
+    static_assert(kTeam >= kCells && kTeam <= 32 && (kTeam & (kTeam - 1)) == 0, "team size");
     const int tid = threadIdx.x, team = tid / kTeam, tl = tid % kTeam;
     const int tw = (tid & 63) / kTeam, tbase = (tid & 63) - tl;  // team within the wave, its lane 0
     const uint32_t tmask = (uint32_t)((1ull << kTeam) - 1ull);
@@ -1604,17 +1611,18 @@ static void knn_launch(const cga_grid *g, const KnnLayout &L, const float *q, in
                        unsigned long long *work = nullptr) {
     CGA_PROF(kCount ? "knn_count" : "knn", s);
     const size_t lds = (size_t)(g->depth > 1 ? g->depth - 1 : 1) * kKnnBlock * sizeof(uint64_t);
-    // as many blocks as the GPU holds at once (each team then takes its
-    // queries round-robin), fewer for small query sets
+    // as many blocks as the GPU holds at once (each team then goes on from
+    // query to query), fewer for small query sets
+    constexpr int kTeamsPerBlock = kKnnBlock / knn_team<KT>();
     const int64_t want = (nq + kTeamsPerBlock - 1) / kTeamsPerBlock;
     const int64_t cap = knn_resident_blocks<KT>(g->depth <= kPackedDepth, kCount, lds);
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
     // Teams take their queries from a counter (zeroed with the control block
     // at the call's start) when each has many to take: a slow query then
     // holds up only its own team.  With few queries per team the counter's
-    // atomics would contend (c2: 100k queries, 1.21 against 0.80 ms), and
-    // each team takes every grid-stride'th query.  The counter's 32 bits must
-    // not wrap.
+    // atomics would contend (100k queries over 2 x 1M LiDAR points: 1.21
+    // against 0.80 ms), and each team takes every grid-stride'th query.  The
+    // counter's 32 bits must not wrap.
     const int64_t teams = (int64_t)blocks * kTeamsPerBlock;
     const int knob = knn_queue_knob();
     const bool queue = knob >= 0 ? knob == 1 : nq >= kKnnQueuePerTeam * teams;
