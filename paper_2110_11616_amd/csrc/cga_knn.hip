@@ -908,7 +908,9 @@ void k_knn_tree(
     __shared__ uint64_t s_sw[kKnnBlock], s_sc[kKnnBlock];  // start cells of the round: word, corner
     __shared__ int64_t s_base[kMaxDepth + 1];
     constexpr int kTeam = knn_team<KT>(), kTeamsPerBlock = kKnnBlock / kTeam;
-    static_assert(kTeam >= kCells && kTeam <= 32 && (kTeam & (kTeam - 1)) == 0, "team size");
+    // (the list's lane shift is a DPP row shift: a team lies within a row of
+    // 16 lanes)
+    static_assert(kTeam >= kCells && kTeam <= 16 && (kTeam & (kTeam - 1)) == 0, "team size");
     const int tid = threadIdx.x, team = tid / kTeam, tl = tid % kTeam;
     const int tw = (tid & 63) / kTeam, tbase = (tid & 63) - tl;  // team within the wave, its lane 0
     const uint32_t tmask = (uint32_t)((1ull << kTeam) - 1ull);
