@@ -870,26 +870,25 @@ struct WideList {
     }
 };
 
-// Waves per SIMD the search is compiled for: the search is bound by the
-// latency of dependent node loads, so more waves in flight pay as long as the
-// registers still fit without spilling (packed lists up to k = 8: 96 VGPRs);
-// 1 leaves the choice to the compiler.
+// Waves per SIMD the search is compiled for: five for packed lists up to
+// k = 8 (94 VGPRs, no spills); 1 leaves the choice to the compiler (95 to
+// 107 VGPRs, four or five waves, none spilling).
 template <int KT, class LIST>
 constexpr int knn_waves_per_eu() {
     return (KT <= 8 && sizeof(typename LIST::Dist) == 4) ? 5 : 1;
 }
 
-// One query at a time per team of kTeam = knn_team<KT>() lanes: each team's first query by
-// its place in the grid, the next ones from a counter (qctr, zero at launch;
-// without it, round-robin over the grid).  LIST is
-// PackedList (depth <= 15) or WideList.  The kernel is one loop whose every
-// trip moves each team one step in its own query: set up a query, set up a
-// round (its start cells), walk (one step per lane, with work handed from
-// busy lanes to idle ones), end a round, so that a team whose query or round
-// is over goes on with the next one instead of waiting for the other teams
-// of its wave.  kCount (a measurement build, same results): every lane
-// counts its node-word loads, dense-table loads, voxels whose distance it
-// took and walk steps, summed into work[0..3].
+// One query at a time per team of knn_team<KT>() lanes: each team's first
+// query by its place in the grid, the next ones from a counter (qctr, zero at
+// launch; without it, round-robin over the grid).  LIST is PackedList (depth
+// <= 15) or WideList.  The kernel is one loop whose every trip moves each
+// team one step in its own query: set up a query, set up a round (its start
+// cells), walk (one step per lane, with work handed from busy lanes to idle
+// ones), end a round, so that a team whose query or round is over goes on
+// with the next one instead of waiting for the other teams of its wave.
+// kCount (a measurement build, same results): every lane counts its
+// node-word loads, dense-table loads, voxels whose distance it took and walk
+// steps, summed into work[0..3].
 template <int KT, class LIST, bool kCount = false>
 __global__ __launch_bounds__(kKnnBlock) __attribute__((amdgpu_waves_per_eu(knn_waves_per_eu<KT, LIST>())))
 void k_knn_tree(
