@@ -1465,6 +1465,13 @@ static int knn_queue_knob() {
     return -1;
 }
 
+// Launch knob (never changes results): CGA_KNN_BLOCKS = n caps the search's
+// grid at n blocks, so that every team answers many queries in turn.
+static int knn_blocks_knob() {
+    if (const char *e = getenv("CGA_KNN_BLOCKS")) return atoi(e);
+    return 0;
+}
+
 // Upper bound on the number of octree nodes of n unique keys: level L has at
 // most min(n, 8^(depth - L)) nodes.
 static int64_t tree_nodes_max(int64_t n, uint32_t depth) {
@@ -1616,7 +1623,8 @@ static void knn_launch(const cga_grid *g, const KnnLayout &L, const float *q, in
     // query to query), fewer for small query sets
     constexpr int kTeamsPerBlock = kKnnBlock / knn_team<KT>();
     const int64_t want = (nq + kTeamsPerBlock - 1) / kTeamsPerBlock;
-    const int64_t cap = knn_resident_blocks<KT>(g->depth <= kPackedDepth, kCount, lds);
+    int64_t cap = knn_resident_blocks<KT>(g->depth <= kPackedDepth, kCount, lds);
+    if (const int b = knn_blocks_knob(); b > 0 && b < cap) cap = b;
     const unsigned blocks = (unsigned)(want < cap ? want : cap);
     // Teams take their queries from a counter (zeroed with the control block
     // at the call's start) when each has many to take: a slow query then

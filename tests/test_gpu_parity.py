@@ -436,6 +436,37 @@ def test_knn_query_queue(gpu, w_c2s, monkeypatch, k, ordered):
     assert e.value.status == gpu.ENONFINITE
 
 
+@pytest.mark.parametrize("k", [1, 8, 16, 32])
+@pytest.mark.parametrize("queue", ["0", "1"])
+@pytest.mark.parametrize("blocks", ["1", "3"])
+def test_knn_few_blocks(gpu, w_c2s, monkeypatch, k, queue, blocks):
+    """A grid of one or three blocks (32 or 96 teams of 8 lanes, 16 or 48 of
+    16) answers every query: each team goes through many queries in turn,
+    from the counter or round-robin, with ties, a ragged count, wide lists
+    and a non-finite query among them."""
+    monkeypatch.setenv("CGA_KNN_BLOCKS", blocks)
+    monkeypatch.setenv("CGA_KNN_QUEUE", queue)
+    g = w_c2s["grid"]
+    ka, _ = gpu.cga_build(dev(w_c2s["a"]), g)
+    say("knn few blocks c2s", k, queue, blocks)
+    q = w_c2s["q"][:20_000]
+    _check_knn(gpu, ka, q, g, k)
+    rng = np.random.default_rng(37)
+    g5 = Grid((0.0, 0.0, 0.0), 1.0, 5, M)
+    pts = rng.integers(0, 32, (300, 3)).astype(np.float32)
+    k5, _ = gpu.cga_build(dev(pts), g5)
+    q5 = rng.integers(-3, 35, (3001, 3)).astype(np.float32)
+    _check_knn(gpu, k5, q5, g5, k, tier="brute")
+    g21 = Grid((0.0, 0.0, 0.0), float(2 ** 21), 21, M)
+    k21, _ = gpu.cga_build(dev(rng.uniform(0, 1, (20_000, 3)).astype(np.float32)), g21)
+    _check_knn(gpu, k21, rng.uniform(0, 1, (3000, 3)).astype(np.float32), g21, k)
+    bad = q5[:500].copy()
+    bad[333, 0] = np.inf
+    with pytest.raises(gpu.CgaError) as e:
+        gpu.cga_knn(k5, dev(bad), g5, k)
+    assert e.value.status == gpu.ENONFINITE
+
+
 def test_knn_query_order_auto(gpu, w_c2s):
     """At 2^18 queries the ordering switches on by itself; the rows equal
     those of the unordered search on the same queries."""
