@@ -296,6 +296,7 @@ constexpr int kScanLevels = 6;  // levels whose oriented boxes are fitted to the
 constexpr int kTreeBigCtr = 24;  // control-block counters of the big-node lists, one per level
 constexpr int kLinearSortCtr = 8;  // tile counters of the LINEAR keys' re-key sort (up to 8 passes)
 constexpr int kKnnQueryCtr = 20;   // control-block counter of the search's query queue
+constexpr int kObbMinLevel = 8;    // least start-cell level of a round that tests oriented boxes
 constexpr int64_t kKnnQueuePerTeam = 8;  // queries per team from which the search uses it
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 constexpr int kNodeBoxShift = 40;
@@ -1058,11 +1059,12 @@ void k_knn_tree(
                (q2 + gzl <= bnd ? 0x10u : 0u) | (q2 + gzh <= bnd ? 0x20u : 0u) |
                (q3 + gzl <= bnd ? 0x40u : 0u) | (q3 + gzh <= bnd ? 0x80u : 0u);
         // a node just loaded whose oriented box lies beyond the bound opens
-        // no child (rounded up, the bound only keeps more); tested from the
-        // second round on, when the query's own cell did not hold its
-        // neighbours (a query near the voxels, whose first round mostly
-        // settles it, would pay for the test and rarely gain)
-        if (fresh && near && !round0) {
+        // no child (rounded up, the bound only keeps more); tested in rounds
+        // from cells of level kObbMinLevel up, those of queries far from the
+        // voxels (near ones, settled in smaller rounds, would pay for the
+        // test and rarely gain: on the 2 x 10M sphere points, rounds from
+        // smaller cells pruned one node load per thousand with it)
+        if (fresh && near && !round0 && ls >= kObbMinLevel) {
             const float hc = (float)((1u << l) - 1u) * 0.5f;
             const float lb2 = obb_dist2(wo, l, (float)qv.x - ((float)x0 + hc),
                                         (float)qv.y - ((float)y0 + hc), (float)qv.z - ((float)z0 + hc));
@@ -1070,7 +1072,9 @@ void k_knn_tree(
         }
     };
 
+    uint32_t trip = 0;
     for (;;) {
+        ++trip;
         bool pend = false;  // this lane's voxel for the team's list, if any
         Cand cv{};
         // ---- next query of the team
@@ -1174,8 +1178,10 @@ void k_knn_tree(
         if (phase == kWalk) {
             // A lane without work left takes the remaining children of the
             // shallowest open ancestor of a lane that has one (the k-th idle
-            // lane of the team pairs with its k-th such lane).  A team's lanes
-            // move in step, so no atomics are needed.
+            // lane of the team pairs with its k-th such lane), every other
+            // trip (each hand-over costs the wave about 40 instructions; on
+            // every trip the 1M-query search took 3 % longer).  A team's
+            // lanes move in step, so no atomics are needed.
             bool recv = false;
             int rsrc = 0, rl = 0;
             uint32_t rx = 0, ry = 0, rz = 0;
@@ -1183,7 +1189,7 @@ void k_knn_tree(
                 const bool idle = pm == 0 && l == lroot && !avail;
                 const uint32_t ti = (uint32_t)(__ballot(idle) >> (kTeam * tw)) & tmask;
                 const uint32_t td = (uint32_t)(__ballot(open != 0) >> (kTeam * tw)) & tmask;
-                if (__ballot(ti != 0 && td != 0)) {
+                if ((trip & 1u) && __ballot(ti != 0 && td != 0)) {
                     const uint32_t below = (1u << tl) - 1u;
                     const int np = min(__popc(ti), __popc(td));
                     const int gl = open ? 31 - __builtin_clz(open) : 0;
