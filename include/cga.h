@@ -260,7 +260,12 @@ int cga_project(const cga_grid *grid, const void *d_keys, int64_t n, const int64
  * go to the smaller LINEAR position.  From 2^18 queries on, the queries
  * are searched in the order of their Morton keys (results are unchanged;
  * the workspace then grows by about 24 bytes per query, so size it with the
- * same nq as the call).
+ * same nq as the call).  Launch knobs, read from the environment at each
+ * call, change no result: CGA_KNN_ORDER (1 / 0: the Morton ordering on /
+ * off), CGA_KNN_LA (level of the first round's cell, default 4),
+ * CGA_KNN_QUEUE (1 / 0: teams take queries from a counter / round-robin;
+ * by default the counter from 8 queries per resident team) and
+ * CGA_KNN_BLOCKS (a cap on the search's grid).
  * Errors: CGA_ENONFINITE for a non-finite query (device); CGA_EMISMATCH
  * (device) when the keys are not sorted, unique and within the grid (the
  * results are then unspecified, but every access stays in bounds). */
